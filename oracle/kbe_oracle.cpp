@@ -1,0 +1,804 @@
+// TEST INFRASTRUCTURE -- NOT PART OF THE PRODUCT PATH.
+//
+// Plain, slow, FP64 CPU reference of the Kadanoff-Baym propagation step of
+// arXiv 2505.19467 ("GPU Acceleration of Non-equilibrium Green's Function
+// Calculation using OpenACC and CUDA FORTRAN"). Only the tests, the smoke check
+// and the CPU-baseline leg of the benchmark load this library. It shares no code,
+// header or table with the HIP library, and it never calls it.
+//
+// Every function follows a passage of the paper (cited by section / equation /
+// algorithm) or, where the paper is silent, the reading listed in the design
+// notes (the same reading is restated at each function):
+//
+//   k grid ............ eq. (kj): k_j = -pi + 2 pi j / n per axis (0-based j)
+//   Hamiltonian ....... Sec. "Computational Kernels", eq. (Htotal)/(ham), with a
+//                       Peierls substitution k -> k - A(t) pol for the pulse
+//   self-energy ....... eq. (2BSE) (second Born), evaluated in real space
+//   collision integral  eq. (CI) in its Langreth "left" form, trapezoid rule
+//                       ("standard second order numerical integration")
+//   propagation ....... Algorithm "prop" (predictor, fixed number of corrector
+//                       passes, re-evaluation after the step) with an
+//                       exponential-midpoint solve of eq. (Green)
+//
+// Conventions: G^<(t,t') = i<c^dag(t') c(t)>, G^>(t,t') = -i<c(t) c^dag(t')>;
+// G^{<,>}(t',t) = -[G^{<,>}(t,t')]^dag; rho(t) = -i G^<(t,t).
+//
+// Storage (oracle-private): row j of the two-time lower triangle is an array
+// [t'=0..j][k][comp(0:<,1:>)][a][b] of complex numbers.
+//
+// Pins (tests/test_oracle_pins.py, CPU only):
+//   sigma_row ....... eq. (2BSE) direct double momentum sums (interband preset, with the
+//                     paper's allind_kpk index map) and the Hubbard momentum convolution;
+//                     conserving pairing (sum_k tr[S^> G^< - S^< G^>] imaginary)
+//   collision_row ... exact on piecewise-linear integrands (trapezoid), zero at t = 0
+//   propagators ..... scipy expm of -i h dt and of the augmented phi_1 matrix
+//   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
+//   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
+//                     dt-convergence ratio 4, TDHF limit vs RK4
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------- scalar types
+template <class R>
+struct Cx {
+  R re, im;
+  Cx() : re(0.0), im(0.0) {}
+  Cx(R r) : re(r), im(0.0) {}
+  Cx(R r, R i) : re(r), im(i) {}
+};
+template <class R> inline Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> inline Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> inline Cx<R> operator-(Cx<R> a) { return {-a.re, -a.im}; }
+template <class R> inline Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> inline Cx<R> operator*(Cx<R> a, double s) { return {a.re * s, a.im * s}; }
+template <class R> inline Cx<R> scale(Cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R> inline Cx<R> conj(Cx<R> a) { return {a.re, -a.im}; }
+template <class R> inline Cx<R>& operator+=(Cx<R>& a, Cx<R> b) { a.re += b.re; a.im += b.im; return a; }
+template <class R> inline Cx<R>& operator-=(Cx<R>& a, Cx<R> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <class R> inline Cx<R> cexpi(R x) { using std::cos; using std::sin; return {cos(x), sin(x)}; }
+template <class R> inline R abs2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+typedef double R;
+typedef Cx<R> C;
+const C I1(0.0, 1.0);
+
+// ---------------------------------------------------------------- parameters
+// Mirrors OracleParams in oracle/oracle.py (ctypes); plain data.
+struct Params {
+  int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, pad_;
+  double dt, U, temp, filling, amp, omega, t0, width, polx, poly;
+};
+enum { INT_HUBBARD = 0, INT_INTERBAND = 1 };
+enum {
+  OBS_T = 0, OBS_N, OBS_EKIN, OBS_EHF, OBS_ECORR, OBS_ETOT, OBS_JX, OBS_JY, OBS_A,
+  OBS_NORB = 9, OBS_NBAND = 13, NOBS = 17
+};
+
+struct Grid {
+  int nkx, nky, nk, nb, dim;
+  std::vector<double> kx, ky;  // eq. (kj)
+  explicit Grid(const Params& p) : nkx(p.nkx), nky(p.nky), nk(p.nkx * p.nky), nb(p.nb) {
+    dim = (p.nky == 1) ? 1 : 2;
+    kx.resize(nkx);
+    ky.resize(nky);
+    for (int j = 0; j < nkx; ++j) kx[j] = -M_PI + 2.0 * M_PI * j / nkx;
+    for (int j = 0; j < nky; ++j) ky[j] = -M_PI + 2.0 * M_PI * j / nky;
+  }
+  // flattened k index: k = ix * nky + iy
+  int ix(int k) const { return k / nky; }
+  int iy(int k) const { return k % nky; }
+};
+
+// ---------------------------------------------------------------- small dense matrices
+// n x n complex matrices in row-major arrays.
+void mm(int n, const C* A, const C* B, C* out) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      C s;
+      for (int l = 0; l < n; ++l) s += A[i * n + l] * B[l * n + j];
+      out[i * n + j] = s;
+    }
+}
+void adjoint(int n, const C* A, C* out) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[j * n + i] = conj(A[i * n + j]);
+}
+
+// Eigen-decomposition of a Hermitian matrix by cyclic complex Jacobi rotations.
+// On exit w holds the eigenvalues in ascending order and the columns of Vec the
+// eigenvectors (A = Vec diag(w) Vec^dag).
+void eigh(int n, const C* Ain, double* w, C* Vec) {
+  std::vector<C> A(Ain, Ain + n * n);
+  for (int i = 0; i < n * n; ++i) Vec[i] = C();
+  for (int i = 0; i < n; ++i) Vec[i * n + i] = C(1.0);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) (p == q ? dia : off) += abs2(A[p * n + q]);
+    if (off <= 1e-34 * (dia + 1e-300)) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        C apq = A[p * n + q];
+        double r = std::sqrt(abs2(apq));
+        if (r < 1e-300) continue;
+        C ph = scale(apq, 1.0 / r);  // e^{i phi}
+        double a = A[p * n + p].re, b = A[q * n + q].re;
+        // rotate the real symmetric problem [[a, r], [r, b]]
+        double theta = (b - a) / (2.0 * r);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        // W = diag(1, e^{-i phi}) * [[c, s], [-s, c]] on the (p, q) plane
+        C wpp(c), wpq(s), wqp = scale(conj(ph), -s), wqq = scale(conj(ph), c);
+        for (int i = 0; i < n; ++i) {  // A <- A W
+          C aip = A[i * n + p], aiq = A[i * n + q];
+          A[i * n + p] = aip * wpp + aiq * wqp;
+          A[i * n + q] = aip * wpq + aiq * wqq;
+        }
+        for (int j = 0; j < n; ++j) {  // A <- W^dag A
+          C apj = A[p * n + j], aqj = A[q * n + j];
+          A[p * n + j] = conj(wpp) * apj + conj(wqp) * aqj;
+          A[q * n + j] = conj(wpq) * apj + conj(wqq) * aqj;
+        }
+        A[p * n + q] = C();
+        A[q * n + p] = C();
+        A[p * n + p].im = 0.0;
+        A[q * n + q].im = 0.0;
+        for (int i = 0; i < n; ++i) {  // Vec <- Vec W
+          C vip = Vec[i * n + p], viq = Vec[i * n + q];
+          Vec[i * n + p] = vip * wpp + viq * wqp;
+          Vec[i * n + q] = vip * wpq + viq * wqq;
+        }
+      }
+  }
+  // sort ascending
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::vector<double> d(n);
+  for (int i = 0; i < n; ++i) d[i] = A[i * n + i].re;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  std::vector<C> V2(n * n);
+  for (int c = 0; c < n; ++c) {
+    w[c] = d[idx[c]];
+    for (int i = 0; i < n; ++i) V2[i * n + c] = Vec[i * n + idx[c]];
+  }
+  std::copy(V2.begin(), V2.end(), Vec);
+}
+
+// f(h) = U diag(f(w)) U^dag for a Hermitian h.
+template <class F>
+void matfun(int n, const C* h, F f, C* out) {
+  std::vector<double> w(n);
+  std::vector<C> U(n * n);
+  eigh(n, h, w.data(), U.data());
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      C s;
+      for (int b = 0; b < n; ++b) s += U[i * n + b] * f(w[b]) * conj(U[j * n + b]);
+      out[i * n + j] = s;
+    }
+}
+
+// ---------------------------------------------------------------- model
+// Pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2), along pol.
+double pulse_A(const Params& p, double t) {
+  double x = (t - p.t0) / p.width;
+  return p.amp * std::sin(p.omega * t) * std::exp(-x * x);
+}
+
+// h0(k - A pol) = T0 + sum_d [T_d e^{i q_d} + T_d^dag e^{-i q_d}], q = k - A pol.
+void h0(const Params& p, const Grid& g, const C* hop, int k, double A, C* out) {
+  int nb = g.nb;
+  double q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      C s = hop[a * nb + b];
+      for (int d = 0; d < g.dim; ++d) {
+        const C* T = hop + (1 + d) * nb * nb;
+        s += T[a * nb + b] * cexpi(q[d]) + conj(T[b * nb + a]) * cexpi(-q[d]);
+      }
+      out[a * nb + b] = s;
+    }
+}
+
+// velocity d h0 / d k_d at k - A pol: i (T_d e^{i q_d} - T_d^dag e^{-i q_d})
+void vel(const Params& p, const Grid& g, const C* hop, int k, double A, int d, C* out) {
+  int nb = g.nb;
+  double q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      if (d >= g.dim) { out[a * nb + b] = C(); continue; }
+      const C* T = hop + (1 + d) * nb * nb;
+      out[a * nb + b] = I1 * (T[a * nb + b] * cexpi(q[d]) - conj(T[b * nb + a]) * cexpi(-q[d]));
+    }
+}
+
+// Mean-field (first-order) self-energy from the local density matrix
+// rho_loc = N_k^{-1} sum_k rho(k).
+//  Hubbard (intra-orbital U, opposite spins): Sigma_ab = delta_ab U rho_loc,aa.
+//  Interband, eq. (ham): Hartree U n_c on v and U n_v on c, Fock -U rho_loc,vc on
+//  the off-diagonal.
+void hf_field(const Params& p, const Grid& g, const std::vector<C>& rho, C* out) {
+  int nb = g.nb, nbb = nb * nb;
+  std::vector<C> loc(nbb);
+  for (int k = 0; k < g.nk; ++k)
+    for (int i = 0; i < nbb; ++i) loc[i] += rho[k * nbb + i];
+  for (int i = 0; i < nbb; ++i) loc[i] = loc[i] * (1.0 / g.nk);
+  for (int i = 0; i < nbb; ++i) out[i] = C();
+  if (!p.hf) return;
+  if (p.interaction == INT_HUBBARD) {
+    for (int a = 0; a < nb; ++a) out[a * nb + a] = C(p.U * loc[a * nb + a].re);
+  } else {
+    out[0] = C(p.U * loc[3].re);
+    out[3] = C(p.U * loc[0].re);
+    out[1] = loc[1] * (-p.U);
+    out[2] = loc[2] * (-p.U);
+  }
+}
+
+// k-independent one-body term: the -U c_c^dag c_c term of eq. (ham) (interband only).
+void onebody_extra(const Params& p, int nb, C* out) {
+  for (int i = 0; i < nb * nb; ++i) out[i] = C();
+  if (p.interaction == INT_INTERBAND) out[3] = C(-p.U);
+}
+
+// ---------------------------------------------------------------- state
+struct State {
+  const Params& p;
+  Grid g;
+  std::vector<C> hop;
+  int nbb, blk;                    // nb^2, 2 nb^2 (one (t,t') block: lesser then greater)
+  std::vector<std::vector<C>> rows;  // rows[j]: [t'][k][comp][a][b]
+  std::vector<C> rho_prev, rho_cur, D_prev, D_cur;  // [k][a][b]
+  std::vector<C> I_prev, I_cur;    // [t'][k][comp][a][b], t' = 0..m
+  std::vector<C> sig;              // [j][k][comp][a][b], j = 0..m
+  std::vector<double> obs;
+  State(const Params& pp, const double* hopd) : p(pp), g(pp) {
+    nbb = g.nb * g.nb;
+    blk = 2 * nbb;
+    hop.resize(3 * nbb);
+    for (int i = 0; i < 3 * nbb; ++i) hop[i] = C(hopd[2 * i], hopd[2 * i + 1]);
+  }
+  C* at(int j, int tp, int k) { return rows[j].data() + ((size_t)tp * g.nk + k) * blk; }
+};
+
+// Equal-time block of G from rho: G^< = i rho, G^> = -i (1 - rho).
+void set_diag_block(int nb, const C* rho, C* blk) {
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      C r = rho[a * nb + b];
+      blk[a * nb + b] = I1 * r;
+      C one_minus = (a == b ? C(1.0) : C()) - r;
+      blk[nb * nb + a * nb + b] = -(I1 * one_minus);
+    }
+}
+
+// Initial state: uncorrelated Fermi-Dirac density of h0(k - A(0)) at temperature T,
+// chemical potential by bisection so that N_k^{-1} sum_k tr rho = nb * filling.
+// (The paper starts from a given G; the configurations ask for an uncorrelated
+// state at half filling and temperature T.)
+double initial_state(const Params& p, const Grid& g, const C* hop, std::vector<C>& rho) {
+  int nb = g.nb, nbb = nb * nb;
+  std::vector<double> w(g.nk * nb);
+  std::vector<C> U(g.nk * nbb), h(nbb);
+  double A0 = pulse_A(p, 0.0);
+  for (int k = 0; k < g.nk; ++k) {
+    h0(p, g, hop, k, A0, h.data());
+    eigh(nb, h.data(), &w[k * nb], &U[k * nbb]);
+  }
+  auto fermi = [&](double e, double mu) { return 1.0 / (1.0 + std::exp((e - mu) / p.temp)); };
+  double lo = *std::min_element(w.begin(), w.end()) - 50.0 * p.temp - 1.0;
+  double hi = *std::max_element(w.begin(), w.end()) + 50.0 * p.temp + 1.0;
+  double target = nb * p.filling * g.nk;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    double n = 0.0;
+    for (double e : w) n += fermi(e, mid);
+    if (n < target) lo = mid; else hi = mid;
+    if (hi - lo < 1e-15 * std::max(1.0, std::fabs(mid))) break;
+  }
+  double mu = 0.5 * (lo + hi);
+  rho.assign(g.nk * nbb, C());
+  for (int k = 0; k < g.nk; ++k)
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) {
+        C s;
+        for (int c = 0; c < nb; ++c)
+          s += U[k * nbb + a * nb + c] * fermi(w[k * nb + c], mu) * conj(U[k * nbb + b * nb + c]);
+        rho[k * nbb + a * nb + b] = s;
+      }
+  return mu;
+}
+
+// ---------------------------------------------------------------- self-energy
+// Real-space transforms over the k grid of eq. (kj):
+//   g(R) = N_k^{-1} sum_k e^{i k.R} G(k),     Sigma(k) = sum_R e^{-i k.R} Sigma(R).
+// Written as two 1D direct sums (the exponential factorises over the axes).
+struct Dft {
+  int nx, ny;
+  std::vector<C> ex, ey;  // ex[j * nx + R] = e^{i kx_j R}
+  explicit Dft(const Grid& g) : nx(g.nkx), ny(g.nky) {
+    ex.resize(nx * nx);
+    ey.resize(ny * ny);
+    for (int j = 0; j < nx; ++j)
+      for (int r = 0; r < nx; ++r) ex[j * nx + r] = cexpi(g.kx[j] * r);
+    for (int j = 0; j < ny; ++j)
+      for (int r = 0; r < ny; ++r) ey[j * ny + r] = cexpi(g.ky[j] * r);
+  }
+  // g(s R) = N_k^{-1} sum_k e^{i s k.R} G(k) for R = (rx, ry), rx in [0, nx), ry in [0, ny)
+  // and s = +1 or -1 (the lattice vector R or -R); in indexed k = ix*ny + iy, out R = rx*ny + ry.
+  void to_real(const C* in, C* out, int s = +1) const {
+    std::vector<C> tmp(nx * ny);
+    for (int ix = 0; ix < nx; ++ix)
+      for (int ry = 0; ry < ny; ++ry) {
+        C acc;
+        for (int iy = 0; iy < ny; ++iy) {
+          C e = ey[iy * ny + ry];
+          acc += in[ix * ny + iy] * (s > 0 ? e : conj(e));
+        }
+        tmp[ix * ny + ry] = acc;
+      }
+    for (int rx = 0; rx < nx; ++rx)
+      for (int ry = 0; ry < ny; ++ry) {
+        C acc;
+        for (int ix = 0; ix < nx; ++ix) {
+          C e = ex[ix * nx + rx];
+          acc += tmp[ix * ny + ry] * (s > 0 ? e : conj(e));
+        }
+        out[rx * ny + ry] = acc * (1.0 / (nx * ny));
+      }
+  }
+  // S(k) = sum_R e^{-i k.R} S(R).
+  void to_k(const C* in, C* out) const {
+    std::vector<C> tmp(nx * ny);
+    for (int rx = 0; rx < nx; ++rx)
+      for (int iy = 0; iy < ny; ++iy) {
+        C s;
+        for (int ry = 0; ry < ny; ++ry) s += in[rx * ny + ry] * conj(ey[iy * ny + ry]);
+        tmp[rx * ny + iy] = s;
+      }
+    for (int ix = 0; ix < nx; ++ix)
+      for (int iy = 0; iy < ny; ++iy) {
+        C s;
+        for (int rx = 0; rx < nx; ++rx) s += tmp[rx * ny + iy] * conj(ex[ix * nx + rx]);
+        out[ix * ny + iy] = s;
+      }
+  }
+};
+
+// Second-Born self-energy on row m, eq. (2BSE), for every t_j, j = 0..m:
+//   Sigma^<(k; t_m, t_j) and Sigma^>(k; t_m, t_j) from G(k; t_m, t_j) (row m) and
+//   G(k; t_j, t_m) = -[G(k; t_m, t_j)]^dag.
+// In real space the double k-sum of eq. (2BSE) becomes a product at each lattice
+// vector R (momentum conservation): for the Hubbard preset (opposite-spin bubble)
+//   Sigma^<_ab(R; t,t') = U^2 G^<_ab(R; t,t') G^<_ab(R; t,t') G^>_ba(-R; t',t)
+// and for the paper's interband preset (jbar = other band)
+//   Sigma^<_jm(R) = U^2 G^>_{mbar jbar}(-R; t',t) [G^<_{jbar mbar}(R) G^<_jm(R)
+//                                                - G^<_{j mbar}(R) G^<_{jbar m}(R)],
+// with lesser and greater swapped for Sigma^>. U(t) is constant here.
+// row: [j][k][comp][a][b]; out: same layout.
+void sigma_row(const Params& p, const Grid& g, int m, const C* row, C* out) {
+  int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
+  Dft dft(g);
+  double UU = p.U * p.U;
+  if (!p.corr) {
+    std::fill(out, out + (size_t)(m + 1) * nk * blk, C());
+    return;
+  }
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j <= m; ++j) {
+    // gf[comp][a][b][R] = G^comp_ab(R; t_m, t_j); gb[comp][a][b][R] = G^comp_ab(-R; t_j, t_m)
+    std::vector<C> gf(blk * nk), gb(blk * nk), in(nk), o(nk), sr(blk * nk);
+    for (int comp = 0; comp < 2; ++comp)
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
+          for (int k = 0; k < nk; ++k)
+            in[k] = row[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b];
+          dft.to_real(in.data(), &gf[((comp * nb + a) * nb + b) * nk]);
+          // G(k; t_j, t_m)_{ab} = -conj(G(k; t_m, t_j)_{ba})
+          for (int k = 0; k < nk; ++k)
+            in[k] = -conj(row[((size_t)j * nk + k) * blk + comp * nbb + b * nb + a]);
+          dft.to_real(in.data(), &gb[((comp * nb + a) * nb + b) * nk], -1);
+        }
+    auto G = [&](const std::vector<C>& v, int comp, int a, int b, int R) -> C {
+      return v[((comp * nb + a) * nb + b) * nk + R];
+    };
+    for (int comp = 0; comp < 2; ++comp) {
+      int oth = 1 - comp;  // Sigma^< uses G^> on the backward line, and vice versa
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+          for (int R = 0; R < nk; ++R) {
+            C s;
+            if (p.interaction == INT_HUBBARD) {
+              s = G(gf, comp, a, b, R) * G(gf, comp, a, b, R) * G(gb, oth, b, a, R);
+            } else {
+              int ab = 1 - a, bb = 1 - b;
+              C back = G(gb, oth, bb, ab, R);
+              s = back * (G(gf, comp, ab, bb, R) * G(gf, comp, a, b, R) -
+                          G(gf, comp, a, bb, R) * G(gf, comp, ab, b, R));
+            }
+            sr[((comp * nb + a) * nb + b) * nk + R] = s * UU;
+          }
+    }
+    for (int comp = 0; comp < 2; ++comp)
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
+          dft.to_k(&sr[((comp * nb + a) * nb + b) * nk], o.data());
+          for (int k = 0; k < nk; ++k)
+            out[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b] = o[k];
+        }
+  }
+}
+
+// ---------------------------------------------------------------- collision integral
+// Trapezoid weight of node j on [0, p] (eq. (CI) with the paper's "standard second
+// order" rule): 1/2 at both ends, 1 inside, nothing on an empty interval.
+double trap(int j, int pend) {
+  if (pend <= 0) return 0.0;
+  return (j == 0 || j == pend) ? 0.5 : 1.0;
+}
+
+// Collision integrals of row m, eq. (CI), in the Langreth left form (reading of the
+// paper's right-form expression that needs no self-energy history):
+//   I^{<,>}(t_m, t') = int_0^{t_m} dtb Sigma^R(t_m, tb) G^{<,>}(tb, t')
+//                    + int_0^{t'}  dtb Sigma^{<,>}(t_m, tb) G^A(tb, t'),
+//   Sigma^R = Sigma^> - Sigma^< (tb < t_m),  G^A(tb,t') = -(G^> - G^<)(tb, t') (tb < t'),
+// on the grid with trapezoid weights, for t' = t_0 .. t_m.
+// hist(j, t', k) returns the stored block (j >= t'); blocks above the diagonal come from
+// G(j, t') = -[G(t', j)]^dag.
+template <class Hist>
+void collision_row(const Params& p, const Grid& g, int m, Hist hist, const C* sig, C* Iout) {
+  int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
+  double dt = p.dt;
+#pragma omp parallel for schedule(dynamic)
+  for (int k = 0; k < nk; ++k) {
+    std::vector<C> Gb(blk), SR(nbb), GR(nbb), tmp(nbb), acc(blk);
+    for (int tp = 0; tp <= m; ++tp) {
+      std::fill(acc.begin(), acc.end(), C());
+      for (int j = 0; j <= m; ++j) {
+        // G(t_j, t')
+        if (j >= tp) {
+          const C* src = hist(j, tp, k);
+          std::copy(src, src + blk, Gb.begin());
+        } else {
+          const C* src = hist(tp, j, k);
+          for (int c = 0; c < 2; ++c) {
+            adjoint(nb, src + c * nbb, &Gb[c * nbb]);
+            for (int i = 0; i < nbb; ++i) Gb[c * nbb + i] = -Gb[c * nbb + i];
+          }
+        }
+        const C* S = sig + ((size_t)j * nk + k) * blk;  // Sigma(t_m, t_j)
+        for (int i = 0; i < nbb; ++i) {
+          SR[i] = S[nbb + i] - S[i];
+          GR[i] = Gb[nbb + i] - Gb[i];
+        }
+        double w1 = trap(j, m) * dt;
+        double w2 = (j <= tp) ? trap(j, tp) * dt : 0.0;
+        for (int c = 0; c < 2; ++c) {
+          if (w1 != 0.0) {
+            mm(nb, SR.data(), &Gb[c * nbb], tmp.data());
+            for (int i = 0; i < nbb; ++i) acc[c * nbb + i] += tmp[i] * w1;
+          }
+          if (w2 != 0.0) {
+            mm(nb, S + c * nbb, GR.data(), tmp.data());
+            for (int i = 0; i < nbb; ++i) acc[c * nbb + i] -= tmp[i] * w2;
+          }
+        }
+      }
+      std::copy(acc.begin(), acc.end(), Iout + ((size_t)tp * nk + k) * blk);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- propagators
+// For the midpoint Hamiltonian hbar of one step:
+//   V = e^{-i hbar dt},  Vh = e^{-i hbar dt/2},  Phi = (V - 1) hbar^{-1} = -i dt phi1(-i hbar dt),
+// so that y(dt) = V y(0) + Phi f solves i dy/dt = hbar y + f exactly for constant f.
+// Computed from the spectral decomposition of hbar.
+void propagators(int nb, double dt, const C* hbar, C* V, C* Vh, C* Phi) {
+  matfun(nb, hbar, [&](double e) { return cexpi(-e * dt); }, V);
+  matfun(nb, hbar, [&](double e) { return cexpi(-e * dt * 0.5); }, Vh);
+  matfun(nb, hbar, [&](double e) {
+    // -i dt sum_n z^n/(n+1)!,  z = -i e dt
+    C z(0.0, -e * dt);
+    if (std::fabs(e * dt) < 1.0) {
+      C term(1.0), s(1.0);
+      for (int n = 1; n < 30; ++n) {
+        term = term * z * (1.0 / (n + 1));
+        s += term;
+      }
+      return C(0.0, -dt) * s;
+    }
+    return (cexpi(-e * dt) - C(1.0)) * (1.0 / e);
+  }, Phi);
+}
+
+// ---------------------------------------------------------------- observables
+void observables(State& st, int m, double* o) {
+  const Params& p = st.p;
+  const Grid& g = st.g;
+  int nb = g.nb, nbb = st.nbb, nk = g.nk;
+  double t = m * p.dt, A = pulse_A(p, t), s = p.spin_deg;
+  std::vector<C> h(nbb), v(nbb), hf(nbb), U(nbb);
+  std::vector<double> w(nb);
+  hf_field(p, g, st.rho_cur, hf.data());
+  double N = 0, Ekin = 0, Ehf = 0, Ecorr = 0, J[2] = {0, 0};
+  std::vector<double> norb(nb, 0.0), nband(nb, 0.0);
+  for (int k = 0; k < nk; ++k) {
+    const C* r = &st.rho_cur[k * nbb];
+    h0(p, g, st.hop.data(), k, A, h.data());
+    for (int a = 0; a < nb; ++a) {
+      N += r[a * nb + a].re;
+      norb[a] += r[a * nb + a].re;
+      for (int b = 0; b < nb; ++b) {
+        Ekin += (h[a * nb + b] * r[b * nb + a]).re;
+        Ehf += (hf[a * nb + b] * r[b * nb + a]).re;
+      }
+    }
+    // E_corr from the equal-time collision integral I^<(t,t) (Galitskii-Migdal form)
+    const C* Ik = &st.I_cur[((size_t)m * nk + k) * st.blk];
+    for (int a = 0; a < nb; ++a) Ecorr += (C(0.0, -0.5) * Ik[a * nb + a]).re;
+    for (int d = 0; d < 2; ++d) {
+      vel(p, g, st.hop.data(), k, A, d, v.data());
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) J[d] += (v[a * nb + b] * r[b * nb + a]).re;
+    }
+    eigh(nb, h.data(), w.data(), U.data());
+    for (int bnd = 0; bnd < nb; ++bnd) {
+      C sacc;
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) sacc += conj(U[a * nb + bnd]) * r[a * nb + b] * U[b * nb + bnd];
+      nband[bnd] += sacc.re;
+    }
+  }
+  // the interband preset's one-body -U n_c term is part of the single-particle energy
+  std::vector<C> ob(nbb);
+  onebody_extra(p, nb, ob.data());
+  for (int k = 0; k < nk; ++k)
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) Ekin += (ob[a * nb + b] * st.rho_cur[k * nbb + b * nb + a]).re;
+  double inv = 1.0 / nk;
+  for (int i = 0; i < NOBS; ++i) o[i] = 0.0;
+  o[OBS_T] = t;
+  o[OBS_N] = s * N * inv;
+  o[OBS_EKIN] = s * Ekin * inv;
+  o[OBS_EHF] = 0.5 * s * Ehf * inv;
+  o[OBS_ECORR] = s * Ecorr * inv;
+  o[OBS_ETOT] = o[OBS_EKIN] + o[OBS_EHF] + o[OBS_ECORR];
+  o[OBS_JX] = s * J[0] * inv;
+  o[OBS_JY] = s * J[1] * inv;
+  o[OBS_A] = A;
+  for (int a = 0; a < nb && a < 4; ++a) o[OBS_NORB + a] = norb[a] * inv;
+  for (int b = 0; b < nb && b < 4; ++b) o[OBS_NBAND + b] = nband[b] * inv;
+}
+
+// ---------------------------------------------------------------- time step
+// One step m-1 -> m of Algorithm "prop" (fixed number K of corrector passes), with
+// eq. (Green) solved by the exponential midpoint rule:
+//   G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t'),   t' < t_m,
+//   rho_m      = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag,
+// where Ibar = I(t_{m-1},.) (predictor) or (I(t_{m-1},.) + I(t_m,.))/2 (corrector),
+// Dbar the same average of D = I^<(t,t) + I^<(t,t)^dag (the equal-time form of
+// eq. (Green)), and hbar = h0(k - A(t_{m-1/2})) + Sigma^HF[rho] with rho = rho_{m-1}
+// (predictor) or (rho_{m-1} + rho_m)/2 (corrector). After the last corrector pass
+// Sigma and I are evaluated once more on the accepted row; they feed the next
+// step's predictor (the algorithm's "Evaluate ... I(t_{n_t-1}, .)").
+void sigma_and_collision(State& st, int m) {
+  int nk = st.g.nk, blk = st.blk;
+  std::vector<C> row((size_t)(m + 1) * nk * blk);
+  std::copy(st.rows[m].begin(), st.rows[m].end(), row.begin());
+  st.sig.assign((size_t)(m + 1) * nk * blk, C());
+  sigma_row(st.p, st.g, m, row.data(), st.sig.data());
+  st.I_cur.assign((size_t)(m + 1) * nk * blk, C());
+  collision_row(st.p, st.g, m, [&](int j, int tp, int k) { return (const C*)st.at(j, tp, k); },
+                st.sig.data(), st.I_cur.data());
+  int nb = st.g.nb, nbb = st.nbb;
+  st.D_cur.assign(nk * nbb, C());
+  for (int k = 0; k < nk; ++k) {
+    const C* Ik = &st.I_cur[((size_t)m * nk + k) * blk];
+    for (int a = 0; a < nb; ++a)
+      for (int b = 0; b < nb; ++b) st.D_cur[k * nbb + a * nb + b] = Ik[a * nb + b] + conj(Ik[b * nb + a]);
+  }
+}
+
+void update_row(State& st, int m, bool corrector) {
+  const Params& p = st.p;
+  const Grid& g = st.g;
+  int nb = g.nb, nbb = st.nbb, blk = st.blk, nk = g.nk;
+  std::vector<C> rho_h(nk * nbb);
+  for (int i = 0; i < nk * nbb; ++i)
+    rho_h[i] = corrector ? (st.rho_prev[i] + st.rho_cur[i]) * 0.5 : st.rho_prev[i];
+  std::vector<C> hf(nbb), ob(nbb);
+  hf_field(p, g, rho_h, hf.data());
+  onebody_extra(p, nb, ob.data());
+  for (int i = 0; i < nbb; ++i) hf[i] += ob[i];
+  double Amid = pulse_A(p, (m - 0.5) * p.dt);
+  std::vector<C> new_rho(nk * nbb);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nk; ++k) {
+    std::vector<C> h(nbb), V(nbb), Vh(nbb), Phi(nbb), Ib(blk), t1(nbb), t2(nbb), t3(nbb), adj(nbb);
+    h0(p, g, st.hop.data(), k, Amid, h.data());
+    for (int i = 0; i < nbb; ++i) h[i] += hf[i];
+    propagators(nb, p.dt, h.data(), V.data(), Vh.data(), Phi.data());
+    for (int tp = 0; tp < m; ++tp) {
+      const C* Ip = &st.I_prev[((size_t)tp * nk + k) * blk];
+      for (int i = 0; i < blk; ++i)
+        Ib[i] = corrector ? (Ip[i] + st.I_cur[((size_t)tp * nk + k) * blk + i]) * 0.5 : Ip[i];
+      const C* Gold = st.at(m - 1, tp, k);
+      C* Gnew = st.at(m, tp, k);
+      for (int c = 0; c < 2; ++c) {
+        mm(nb, V.data(), Gold + c * nbb, t1.data());
+        mm(nb, Phi.data(), &Ib[c * nbb], t2.data());
+        for (int i = 0; i < nbb; ++i) Gnew[c * nbb + i] = t1[i] + t2[i];
+      }
+    }
+    // density matrix
+    std::vector<C> Db(nbb);
+    for (int i = 0; i < nbb; ++i)
+      Db[i] = corrector ? (st.D_prev[k * nbb + i] + st.D_cur[k * nbb + i]) * 0.5 : st.D_prev[k * nbb + i];
+    mm(nb, V.data(), &st.rho_prev[k * nbb], t1.data());
+    adjoint(nb, V.data(), adj.data());
+    mm(nb, t1.data(), adj.data(), t2.data());
+    mm(nb, Vh.data(), Db.data(), t1.data());
+    adjoint(nb, Vh.data(), adj.data());
+    mm(nb, t1.data(), adj.data(), t3.data());
+    for (int i = 0; i < nbb; ++i) new_rho[k * nbb + i] = t2[i] - t3[i] * p.dt;
+  }
+  st.rho_cur = new_rho;
+  for (int k = 0; k < nk; ++k) set_diag_block(nb, &st.rho_cur[k * nbb], st.at(m, m, k));
+}
+
+void step(State& st, int m) {
+  int nk = st.g.nk, blk = st.blk;
+  st.rows.emplace_back((size_t)(m + 1) * nk * blk);
+  update_row(st, m, false);
+  for (int it = 0; it < st.p.n_corr; ++it) {
+    sigma_and_collision(st, m);
+    update_row(st, m, true);
+  }
+  sigma_and_collision(st, m);
+  st.I_prev = st.I_cur;
+  st.D_prev = st.D_cur;
+  st.rho_prev = st.rho_cur;
+}
+
+void init(State& st) {
+  int nk = st.g.nk, nbb = st.nbb, blk = st.blk;
+  initial_state(st.p, st.g, st.hop.data(), st.rho_cur);
+  st.rows.clear();
+  st.rows.emplace_back((size_t)nk * blk);
+  for (int k = 0; k < nk; ++k) set_diag_block(st.g.nb, &st.rho_cur[k * nbb], st.at(0, 0, k));
+  st.rho_prev = st.rho_cur;
+  sigma_and_collision(st, 0);  // I(t_0, t_0) = 0: both integrals are empty
+  st.I_prev = st.I_cur;
+  st.D_prev = st.D_cur;
+}
+
+void to_doubles(const C* src, size_t n, double* dst) {
+  for (size_t i = 0; i < n; ++i) { dst[2 * i] = src[i].re; dst[2 * i + 1] = src[i].im; }
+}
+void from_doubles(const double* src, size_t n, C* dst) {
+  for (size_t i = 0; i < n; ++i) dst[i] = C(src[2 * i], src[2 * i + 1]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_nobs() { return NOBS; }
+
+// Full propagation: nsteps steps from the initial state. obs: (nsteps+1) x NOBS.
+// final_row (optional): row nsteps, [t'][k][comp][a][b] complex (interleaved re/im).
+// hist (optional): rows 0..nsteps concatenated in the same per-row layout.
+// rho_out (optional): final rho [k][a][b].
+int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, double* final_row,
+               double* hist, double* rho_out) {
+  if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
+  if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  State st(*p, hop);
+  init(st);
+  if (obs) observables(st, 0, obs);
+  for (int m = 1; m <= nsteps; ++m) {
+    step(st, m);
+    if (obs) observables(st, m, obs + (size_t)m * NOBS);
+  }
+  if (final_row) to_doubles(st.rows[nsteps].data(), st.rows[nsteps].size(), final_row);
+  if (hist) {
+    size_t off = 0;
+    for (int j = 0; j <= nsteps; ++j) {
+      to_doubles(st.rows[j].data(), st.rows[j].size(), hist + 2 * off);
+      off += st.rows[j].size();
+    }
+  }
+  if (rho_out) to_doubles(st.rho_cur.data(), st.rho_cur.size(), rho_out);
+  return 0;
+}
+
+// Sigma on row m: row and out are [j=0..m][k][comp][a][b] complex.
+int oracle_sigma_row(const Params* p, int32_t m, const double* row, double* out) {
+  Grid g(*p);
+  size_t n = (size_t)(m + 1) * g.nk * 2 * g.nb * g.nb;
+  std::vector<C> r(n), o(n);
+  from_doubles(row, n, r.data());
+  sigma_row(*p, g, m, r.data(), o.data());
+  to_doubles(o.data(), n, out);
+  return 0;
+}
+
+// Collision integrals I(t_m, t'), t' = 0..m. hist: rows 0..m concatenated
+// (row j = [t'=0..j][k][comp][a][b]); sig: [j][k][comp][a][b]; out: [t'][k][comp][a][b].
+int oracle_collision_row(const Params* p, int32_t m, const double* hist, const double* sig, double* out) {
+  Grid g(*p);
+  int blk = 2 * g.nb * g.nb, nk = g.nk;
+  std::vector<size_t> rowoff(m + 2, 0);
+  for (int j = 0; j <= m; ++j) rowoff[j + 1] = rowoff[j] + (size_t)(j + 1) * nk * blk;
+  std::vector<C> H(rowoff[m + 1]), S((size_t)(m + 1) * nk * blk), O((size_t)(m + 1) * nk * blk);
+  from_doubles(hist, H.size(), H.data());
+  from_doubles(sig, S.size(), S.data());
+  collision_row(*p, g, m,
+                [&](int j, int tp, int k) { return (const C*)&H[rowoff[j] + ((size_t)tp * nk + k) * blk]; },
+                S.data(), O.data());
+  to_doubles(O.data(), O.size(), out);
+  return 0;
+}
+
+// V, Vh, Phi for a batch of Hermitian matrices hbar: [count][a][b] -> out [count][3][a][b].
+int oracle_propagators(int32_t nb, int32_t count, double dt, const double* hbar, double* out) {
+  int nbb = nb * nb;
+  std::vector<C> h(nbb), V(nbb), Vh(nbb), Phi(nbb);
+  for (int i = 0; i < count; ++i) {
+    from_doubles(hbar + 2 * (size_t)i * nbb, nbb, h.data());
+    propagators(nb, dt, h.data(), V.data(), Vh.data(), Phi.data());
+    to_doubles(V.data(), nbb, out + 2 * ((size_t)i * 3 + 0) * nbb);
+    to_doubles(Vh.data(), nbb, out + 2 * ((size_t)i * 3 + 1) * nbb);
+    to_doubles(Phi.data(), nbb, out + 2 * ((size_t)i * 3 + 2) * nbb);
+  }
+  return 0;
+}
+
+// Eigen-decomposition (ascending) of a batch of Hermitian matrices.
+int oracle_eigh(int32_t nb, int32_t count, const double* A, double* w, double* vec) {
+  int nbb = nb * nb;
+  std::vector<C> a(nbb), v(nbb);
+  for (int i = 0; i < count; ++i) {
+    from_doubles(A + 2 * (size_t)i * nbb, nbb, a.data());
+    eigh(nb, a.data(), w + (size_t)i * nb, v.data());
+    to_doubles(v.data(), nbb, vec + 2 * (size_t)i * nbb);
+  }
+  return 0;
+}
+
+// Initial density matrix rho0 [k][a][b] and chemical potential.
+int oracle_initial_state(const Params* p, const double* hop, double* rho0, double* mu) {
+  Grid g(*p);
+  int nbb = g.nb * g.nb;
+  std::vector<C> H(3 * nbb);
+  from_doubles(hop, 3 * nbb, H.data());
+  std::vector<C> rho;
+  double m = initial_state(*p, g, H.data(), rho);
+  to_doubles(rho.data(), rho.size(), rho0);
+  if (mu) *mu = m;
+  return 0;
+}
+
+// h0(k - A pol) for every k: out [k][a][b].
+int oracle_h0(const Params* p, const double* hop, double A, double* out) {
+  Grid g(*p);
+  int nbb = g.nb * g.nb;
+  std::vector<C> H(3 * nbb), h(nbb);
+  from_doubles(hop, 3 * nbb, H.data());
+  for (int k = 0; k < g.nk; ++k) {
+    h0(*p, g, H.data(), k, A, h.data());
+    to_doubles(h.data(), nbb, out + 2 * (size_t)k * nbb);
+  }
+  return 0;
+}
+
+}  // extern "C"

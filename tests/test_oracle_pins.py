@@ -1,0 +1,281 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: a brute-force
+sum written from the paper's formula, a closed form, a library routine for a
+special case, a conservation law or a convergence order.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import oracle as O
+from paper_2505_19467_amd import inputs
+from tests import brute
+
+
+def _obs(r, name):
+    return r["obs"][:, O.OBS[name]]
+
+
+# ---------------------------------------------------------------- k grid and index map
+@pytest.mark.parametrize("nk", [4, 8, 16, 24])
+def test_allind_kpk_is_modular_sum(nk):
+    """Index map of the paper (three-case formula) equals the modular sum of the
+    eq. (kj) momenta, the indexing the real-space self-energy relies on."""
+    k = brute.kgrid(nk)
+    for j1 in range(1, nk + 1):
+        for j2 in range(1, nk + 1):
+            idx = brute.allind_kpk(j1, j2, nk)
+            assert 1 <= idx <= nk
+            assert idx == ((j1 - 1) + (j2 - 1) - nk // 2) % nk + 1
+            d = (k[j1 - 1] + k[j2 - 1] - k[idx - 1]) / (2 * np.pi)
+            assert abs(d - round(d)) < 1e-12
+
+
+# ---------------------------------------------------------------- self-energy
+@pytest.mark.parametrize("nk,lesser_seed", [(4, 1), (6, 2), (8, 3)])
+def test_sigma_interband_matches_eq_2bse_direct_sum(nk, lesser_seed):
+    """Interband preset: oracle (real-space products) == eq. (2BSE) direct sums."""
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=2, hop=np.zeros((3, 2, 2), complex), U=1.3,
+                        dt=0.02, nt=4, spin_deg=1, interaction=inputs.INTERACTION_INTERBAND)
+    m = 2
+    row = inputs.random_complex((m + 1, nk, 2, 2, 2), lesser_seed)
+    sig = O.sigma_row(cfg, m, row)
+    for j in range(m + 1):
+        for comp, lesser in ((0, True), (1, False)):
+            ref = brute.paper_sigma_direct(row[j, :, 0], row[j, :, 1], cfg.U, lesser)
+            assert np.abs(sig[j, :, comp] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nkx,nky,nb", [(6, 1, 2), (3, 4, 2), (4, 2, 3), (2, 3, 4)])
+def test_sigma_hubbard_matches_momentum_convolution(nkx, nky, nb):
+    """Hubbard preset: oracle == momentum-space double sum over (k1, k2)."""
+    cfg = inputs.Config(name="t", nkx=nkx, nky=nky, nb=nb, hop=np.zeros((3, nb, nb), complex), U=0.7,
+                        dt=0.02, nt=4)
+    m = 1
+    row = inputs.random_complex((m + 1, nkx * nky, 2, nb, nb), 11 + nb)
+    sig = O.sigma_row(cfg, m, row)
+    for j in range(m + 1):
+        for comp, lesser in ((0, True), (1, False)):
+            ref = brute.hubbard_sigma_direct(row[j, :, 0], row[j, :, 1], cfg.U, nkx, nky, lesser)
+            assert np.abs(sig[j, :, comp] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("interaction", [inputs.INTERACTION_HUBBARD, inputs.INTERACTION_INTERBAND])
+def test_sigma_conserving_pairing(interaction):
+    """sum_k tr[Sigma^>(t,tb) G^<(tb,t) - Sigma^<(t,tb) G^>(tb,t)] is purely imaginary
+    for every tb (the property behind exact particle-number conservation)."""
+    nk = 6
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=2, hop=np.zeros((3, 2, 2), complex), U=1.1,
+                        dt=0.02, nt=4, interaction=interaction)
+    m = 3
+    row = inputs.random_complex((m + 1, nk, 2, 2, 2), 7)
+    sig = O.sigma_row(cfg, m, row)
+    for j in range(m + 1):
+        Gb = brute.backward(row[j])
+        val = (np.einsum("kab,kba->", sig[j, :, 1], Gb[:, 0]) -
+               np.einsum("kab,kba->", sig[j, :, 0], Gb[:, 1]))
+        assert abs(val.real) <= 1e-12 * abs(val)
+
+
+# ---------------------------------------------------------------- collision integral
+def _linear_history(nk, nb, m, dt, seed):
+    """Sigma row constant in t_j; G(t_j, t') = A + B t_j + C t' (j >= t') with A and
+    B + C anti-Hermitian, so that the upper triangle -G^dag joins continuously."""
+    rng = np.random.default_rng(seed)
+
+    def cplx(*shape):
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+    def antiherm(x):
+        return 0.5 * (x - np.conj(np.swapaxes(x, -1, -2)))
+
+    A = antiherm(cplx(nk, 2, nb, nb))
+    B = cplx(nk, 2, nb, nb)
+    C = antiherm(cplx(nk, 2, nb, nb)) - B
+    S = cplx(nk, 2, nb, nb)
+    rows = []
+    for j in range(m + 1):
+        tj = j * dt
+        rows.append(np.array([A + B * tj + C * (tp * dt) for tp in range(j + 1)]))
+    sig = np.array([S for _ in range(m + 1)])
+    return rows, sig, A, B, C, S
+
+
+@pytest.mark.parametrize("m", [1, 2, 7])
+def test_collision_trapezoid_exact_on_piecewise_linear(m):
+    """With Sigma constant and G piecewise linear in the integration variable the
+    trapezoid rule of eq. (CI) is exact: compare against the analytic integrals of
+    the Langreth left form (both pieces, both components, every t')."""
+    nk, nb, dt = 3, 2, 0.05
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=nb, hop=np.zeros((3, nb, nb), complex), U=1.0,
+                        dt=dt, nt=m)
+    rows, sig, A, B, C, S = _linear_history(nk, nb, m, dt, 3)
+    I = O.collision_row(cfg, m, rows, sig)
+    tm = m * dt
+    dag = lambda x: np.conj(np.swapaxes(x, -1, -2))
+    SR = S[:, 1] - S[:, 0]
+    for tp in range(m + 1):
+        s = tp * dt
+        # int_0^{tm} G(tau, s) dtau, split at tau = s
+        lower = -(dag(A) * s + dag(B) * s * s + dag(C) * s * s / 2)  # tau in [0, s]
+        upper = (A + C * s) * (tm - s) + B * (tm * tm - s * s) / 2    # tau in [s, tm]
+        full = lower + upper
+        for comp in range(2):
+            ref = SR @ full[:, comp] - S[:, comp] @ (lower[:, 1] - lower[:, 0])
+            assert np.abs(I[tp, :, comp] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_collision_at_initial_time_is_zero():
+    nk, nb = 2, 2
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=nb, hop=np.zeros((3, nb, nb), complex), U=1.0,
+                        dt=0.1, nt=1)
+    rows = inputs.random_history(nk, nb, 0, 1)
+    sig = inputs.random_complex((1, nk, 2, nb, nb), 2)
+    assert np.abs(O.collision_row(cfg, 0, rows, sig)).max() == 0.0
+
+
+# ---------------------------------------------------------------- propagators, eigen, initial state
+def test_propagators_match_matrix_exponentials():
+    """V = e^{-i h dt}, Vh = e^{-i h dt/2}, and Phi = -i * (top-right block of
+    exp([[-i h dt, dt 1], [0, 0]])) = (V - 1) h^{-1}, via scipy's expm."""
+    for nb in (1, 2, 3, 4):
+        h = inputs.random_hermitian(nb, 5, 40 + nb, scale=2.0)
+        h[0] *= 1e-9  # near-singular hbar exercises the phi_1 limit
+        for dt in (0.02, 0.7):
+            out = O.propagators(h, dt)
+            for i in range(h.shape[0]):
+                V = scipy.linalg.expm(-1j * h[i] * dt)
+                Vh = scipy.linalg.expm(-0.5j * h[i] * dt)
+                aug = np.zeros((2 * nb, 2 * nb), complex)
+                aug[:nb, :nb] = -1j * h[i] * dt
+                aug[:nb, nb:] = dt * np.eye(nb)
+                Phi = -1j * scipy.linalg.expm(aug)[:nb, nb:]
+                np.testing.assert_allclose(out[i, 0], V, atol=1e-13)
+                np.testing.assert_allclose(out[i, 1], Vh, atol=1e-13)
+                np.testing.assert_allclose(out[i, 2], Phi, atol=1e-13 * max(1, dt))
+
+
+def test_eigh_matches_numpy():
+    for nb in (2, 3, 4):
+        A = inputs.random_hermitian(nb, 20, 5 + nb)
+        w, v = O.eigh(A)
+        wn = np.linalg.eigvalsh(A)
+        np.testing.assert_allclose(w, wn, atol=1e-13)
+        recon = v @ (w[..., None] * np.conj(np.swapaxes(v, -1, -2)))
+        np.testing.assert_allclose(recon, A, atol=1e-13)
+
+
+def test_initial_state_fermi_dirac():
+    """rho0 = f(h0) with mu fixed by the filling; C1's band structure is particle-hole
+    symmetric, so mu = 0 there. Compared with numpy's eigh on an independent h0."""
+    for cfg in (inputs.c1(), inputs.c4(), inputs.c5().replace(nkx=4, nky=4)):
+        rho, mu = O.initial_state(cfg)
+        h = brute.h0_numpy(cfg.hop, cfg.nkx, cfg.nky, 0.0)
+        np.testing.assert_allclose(O.h0(cfg, 0.0), h, atol=1e-14)
+        w, v = np.linalg.eigh(h)
+        f = 1.0 / (1.0 + np.exp((w - mu) / cfg.temp))
+        ref = np.einsum("kab,kb,kcb->kac", v, f, v.conj())
+        np.testing.assert_allclose(rho, ref, atol=1e-13)
+        assert abs(np.einsum("kaa->", rho).real / cfg.nk - cfg.nb * cfg.filling) < 1e-12
+    _, mu1 = O.initial_state(inputs.c1())
+    assert abs(mu1) < 1e-12
+
+
+# ---------------------------------------------------------------- propagation: closed forms and laws
+def test_free_propagation_closed_form():
+    """U = 0, A = 0: G^<(k; t, t') = i e^{-i h t} rho0 e^{i h t'} and
+    G^>(k; t, t') = -i e^{-i h t} (1 - rho0) e^{i h t'} on every stored point."""
+    cfg = inputs.c1().replace(U=0.0, pulse=inputs.Pulse(amp=0.0), nkx=8)
+    n = 60
+    r = O.run(cfg, n, history=True)
+    rho0, _ = O.initial_state(cfg)
+    w, v = np.linalg.eigh(brute.h0_numpy(cfg.hop, cfg.nkx, cfg.nky, 0.0))
+    worst = 0.0
+    for m in (1, 17, n):
+        Um = np.einsum("kab,kb,kcb->kac", v, np.exp(-1j * w * m * cfg.dt), v.conj())
+        for j in range(m + 1):
+            Uj = np.einsum("kab,kb,kcb->kac", v, np.exp(1j * w * j * cfg.dt), v.conj())
+            gl = 1j * Um @ rho0 @ Uj
+            gg = -1j * Um @ (np.eye(cfg.nb) - rho0) @ Uj
+            worst = max(worst, np.abs(r["rows"][m][j, :, 0] - gl).max(), np.abs(r["rows"][m][j, :, 1] - gg).max())
+    assert worst < 1e-13
+
+
+def test_number_conservation_exact():
+    """N(t) is conserved to rounding for any dt (conserving second Born + HF)."""
+    for cfg in (inputs.c1().replace(nkx=8), inputs.c4().replace(nkx=4, nky=4)):
+        r = O.run(cfg, 60)
+        N = _obs(r, "N")
+        assert np.abs(N - N[0]).max() < 1e-12
+        assert abs(N[0] - cfg.spin_deg * cfg.nb * cfg.filling) < 1e-12
+
+
+def _energy_balance(r, cfg):
+    """E_tot(t) - E_tot(0) + int_0^t Adot J_pol dt (trapezoid on the run's grid)."""
+    pu = cfg.pulse
+    t = _obs(r, "t")
+    g = np.exp(-((t - pu.t0) / pu.width) ** 2)
+    Adot = pu.amp * (pu.omega * np.cos(pu.omega * t) * g -
+                     np.sin(pu.omega * t) * g * 2 * (t - pu.t0) / pu.width ** 2)
+    J = _obs(r, "Jx") * pu.pol[0] + _obs(r, "Jy") * pu.pol[1]
+    f = Adot * J
+    W = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * cfg.dt)])
+    E = _obs(r, "Etot")
+    return E - E[0] + W
+
+
+@pytest.mark.parametrize("amp", [0.0, 0.5])
+def test_energy_conservation_second_order(amp):
+    """Total energy (kinetic + HF + Galitskii-Migdal correlation) is conserved, and
+    with a pulse balanced by the work -int Adot J, to O(dt^2): halving dt divides the
+    largest deviation by ~4."""
+    base = inputs.c1().replace(nkx=8, pulse=inputs.Pulse(amp=amp))
+    errs = []
+    for dt in (0.04, 0.02, 0.01):
+        cfg = base.replace(dt=dt)
+        r = O.run(cfg, int(round(2.0 / dt)))
+        errs.append(np.abs(_energy_balance(r, cfg)).max())
+    assert 3.5 < errs[0] / errs[1] < 4.6 and 3.5 < errs[1] / errs[2] < 4.6, errs
+    assert errs[2] < 5e-5
+
+
+def test_dt_convergence_second_order():
+    """Observables at T = 2 converge at second order in dt (1D nk=4 and 2D 4x4)."""
+    for base in (inputs.c1().replace(nkx=4), inputs.c4().replace(nkx=4, nky=4)):
+        vals = []
+        for dt in (0.04, 0.02, 0.01):
+            cfg = base.replace(dt=dt)
+            r = O.run(cfg, int(round(2.0 / dt)))
+            vals.append(r["obs"][-1, [O.OBS["Etot"], O.OBS["Jx"], O.OBS["n_band1"], O.OBS["Ecorr"]]])
+        e1 = np.abs(vals[0] - vals[1])
+        e2 = np.abs(vals[1] - vals[2])
+        ratio = e1 / e2
+        assert np.all((ratio > 3.5) & (ratio < 4.6)), ratio
+
+
+def test_tdhf_limit_matches_rk4():
+    """With the correlation self-energy off, the scheme reduces to time-dependent
+    Hartree-Fock; compare the density matrix with an RK4 solution at dt/32 and check
+    second-order convergence of the difference."""
+    base = inputs.c1().replace(nkx=6, corr=0, U=1.5)
+    errs = []
+    for dt in (0.04, 0.02):
+        cfg = base.replace(dt=dt)
+        n = int(round(2.0 / dt))
+        r = O.run(cfg, n)
+        rho0, _ = O.initial_state(cfg)
+        ref = brute.tdhf_rk4(cfg, rho0, 2.0, 32)
+        errs.append(np.abs(r["rho"] - ref[-1]).max())
+    assert errs[1] < 1e-4 and 3.5 < errs[0] / errs[1] < 4.6, errs
+
+
+def test_corrector_count_changes_at_higher_order():
+    """K = 2 corrector passes differ from K = 1 by much less than the O(dt^2) error."""
+    cfg = inputs.c1().replace(nkx=4)
+    r1 = O.run(cfg, 50)
+    r2 = O.run(cfg.replace(n_corr=2), 50)
+    r_fine = O.run(cfg.replace(dt=cfg.dt / 2), 100)
+    d12 = np.abs(r1["obs"][-1] - r2["obs"][-1]).max()
+    dfine = np.abs(r1["obs"][-1] - r_fine["obs"][-1]).max()
+    assert d12 < dfine

@@ -1,0 +1,203 @@
+/*
+ * kbe.h -- C ABI of the MI355X (gfx950) Kadanoff-Baym propagation library.
+ *
+ * The library advances the two-time lesser/greater Green's functions
+ * G^{<,>}_{ab}(k; t, t') of a lattice model, one time slice per step, exactly as
+ * arXiv 2505.19467 states the problem: Algorithm "prop" (predictor, corrector
+ * passes, re-evaluation), eq. (Green) for the per-k equations of motion, eq. (CI)
+ * for the collision (memory) integrals and eq. (2BSE) for the second-Born
+ * self-energy, on the k grid of eq. (kj). Every step of the path runs in HIP
+ * kernels on the caller's stream; there is no host fallback.
+ *
+ * Conventions
+ *   G^<(t,t') = i<c^dag(t') c(t)>, G^>(t,t') = -i<c(t) c^dag(t')>,
+ *   G(t',t) = -[G(t,t')]^dag, rho(t) = -i G^<(t,t).
+ *   k grid: k_j = -pi + 2 pi j / n per axis (eq. (kj), 0-based j); flattened k = ix*nky + iy.
+ *   Complex numbers are two doubles (re, im), interleaved.
+ *
+ * Memory ownership
+ *   All device memory is allocated by the caller (e.g. as torch tensors) with the
+ *   sizes returned by kbe_workspace_query, and must outlive the context. The library
+ *   allocates no device memory. Host pointers passed to a call are read before the
+ *   call returns.
+ *
+ * Errors
+ *   Every int-returning function returns KBE_OK (0) or a negative KBE_ERR_* code;
+ *   kbe_last_error gives a message for the last failing call on a context. Calls
+ *   that only enqueue work (kbe_step, kbe_stage_*) report launch errors immediately
+ *   and kernel-side faults at the next synchronising call.
+ */
+#ifndef KBE_H_
+#define KBE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KBE_OK = 0,
+  KBE_ERR_INVALID_ARG = -1,  /* null pointer, out-of-range parameter */
+  KBE_ERR_SHAPE = -2,        /* unsupported sizes (nb, grid, nt_max) */
+  KBE_ERR_HIP = -3,          /* a HIP runtime call failed */
+  KBE_ERR_STATE = -4,        /* call out of order (e.g. stepping past nt_max) */
+  KBE_ERR_NONFINITE = -5,    /* a NaN/Inf appeared in the propagated state */
+  KBE_ERR_NOT_CONVERGED = -6
+};
+
+/* Interaction presets (eq. (ham) and eq. (2BSE)). */
+enum {
+  KBE_INT_HUBBARD = 0,   /* spin-degenerate, intra-orbital on-site U: Sigma_ab = U^2 G_ab G_ab G_ba */
+  KBE_INT_INTERBAND = 1  /* the paper's spinless two-band model (nb = 2): direct - exchange */
+};
+
+enum { KBE_FP64 = 0, KBE_FP32 = 1 };
+
+/* Observable columns of the per-step time series (see kbe_observables). */
+enum {
+  KBE_OBS_T = 0,      /* time t_m = m dt */
+  KBE_OBS_N = 1,      /* particles per site, s/N_k sum_k tr rho */
+  KBE_OBS_EKIN = 2,   /* s/N_k sum_k tr[h0(k - A) rho] */
+  KBE_OBS_EHF = 3,    /* s/(2 N_k) sum_k tr[Sigma^HF rho] */
+  KBE_OBS_ECORR = 4,  /* -(i/2) s/N_k sum_k tr I^<(t,t) (Galitskii-Migdal) */
+  KBE_OBS_ETOT = 5,
+  KBE_OBS_JX = 6,     /* s/N_k sum_k tr[v_x(k - A) rho] */
+  KBE_OBS_JY = 7,
+  KBE_OBS_A = 8,      /* pulse amplitude A(t_m) */
+  KBE_OBS_NORB = 9,   /* 4 columns: orbital occupations per spin N_k^-1 sum_k rho_aa */
+  KBE_OBS_NBAND = 13, /* 4 columns: band occupations per spin in the eigenbasis of h0(k - A), ascending */
+  KBE_NOBS = 17
+};
+
+/* Workload description (plain data; the caller keeps ownership). */
+typedef struct {
+  int32_t nkx, nky;     /* k grid; nky = 1 is a 1D chain. 1 <= nkx, nky <= 64, nkx*nky <= 1024 */
+  int32_t nb;           /* orbitals per spin, 1..4 (interband preset: 2) */
+  int32_t spin_deg;     /* 1 or 2: prefactor s of the observables */
+  int32_t interaction;  /* KBE_INT_* */
+  int32_t hf;           /* 1: include the first-order (Hartree-Fock) self-energy in h */
+  int32_t corr;         /* 1: include the second-Born correlation self-energy */
+  int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes */
+  int32_t nt_max;       /* largest step index the buffers hold */
+  int32_t precision;    /* KBE_FP64 (KBE_FP32 reserved for the split-precision form) */
+  double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
+} kbe_config;
+
+/* Peierls pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2) along pol = (pol[0], pol[1]). */
+typedef struct {
+  double amp, omega, t0, width, pol[2];
+} kbe_pulse;
+
+typedef struct kbe_ctx kbe_ctx;
+
+/*
+ * Device layout (all complex128):
+ *   history : G^{<,>}_{ab}(k; t_j, t') for 0 <= t' <= j <= nt_max, packed lower triangle per
+ *             k and per component, contiguous in t', rows padded to 8 elements (128 B):
+ *               elem(k, c, j, t') = (k * C + c) * P + rowoff(j) + t'
+ *             C = 2 nb^2, c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>),
+ *             rowoff(j) = 32 Q (Q+1) + 8 r (Q+1) with Q = j / 8, r = j % 8, P = rowoff(nt_max + 1).
+ *   workspace: the per-step rows (self-energy row, collision rows, density matrices,
+ *             propagators, partial sums); sub-buffers are located with kbe_buffer.
+ *   obs     : (nt_max + 1) x KBE_NOBS doubles, row m written when step m completes.
+ */
+int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* workspace_bytes,
+                        size_t* obs_bytes);
+
+/*
+ * Create a context and prepare the initial state on the stream (asynchronously): the
+ * uncorrelated Fermi-Dirac density of h0(k - A(0)) at temperature cfg->temp, with the
+ * chemical potential found by bisection for cfg->filling, row 0 of the history
+ * (G^< = i rho0, G^> = -i(1 - rho0)) and the observables of t_0.
+ *   hop   : host, 3 complex nb x nb blocks T0, Tx, Ty (row-major, interleaved re/im);
+ *           h0(k) = T0 + sum_d (T_d e^{i k_d} + T_d^dag e^{-i k_d}); Ty is ignored when nky = 1.
+ *   pulse : host, may be NULL (no pulse).
+ *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
+ */
+int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+               void* d_workspace, void* d_obs, void* hip_stream, kbe_ctx** out);
+
+/* Advance nsteps time steps (Algorithm "prop" with K = cfg->n_corr fixed corrector passes),
+ * asynchronously. KBE_ERR_STATE if the step index would pass nt_max. */
+int kbe_step(kbe_ctx* ctx, int32_t nsteps);
+
+/* Index of the last completed step (0 after kbe_create). */
+int32_t kbe_current_step(const kbe_ctx* ctx);
+
+/* Synchronise the stream and copy observable rows first..first+count-1 to host_out
+ * (count x KBE_NOBS doubles). Returns KBE_ERR_NONFINITE if the state is not finite. */
+int kbe_observables(kbe_ctx* ctx, int32_t first, int32_t count, double* host_out);
+
+void kbe_destroy(kbe_ctx* ctx);
+const char* kbe_last_error(const kbe_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Stage entry points: one call per step of the path, on the context's buffers, for the
+ * time slice t_m. kbe_step is the composition
+ *   propagators(m, 0); update(m, PREDICT);
+ *   K x { sigma(m); collision(m); propagators(m, 1); update(m, CORRECT) };
+ *   sigma(m); collision(m); commit(m); observables(m)
+ * (the corrector's collision and update are fused inside kbe_step).
+ * ------------------------------------------------------------------------------------- */
+
+/* Sub-buffers of the workspace (kbe_buffer). */
+enum {
+  KBE_BUF_SIGMA = 0,  /* [k][3][nb^2][Tp]: Sigma^<, Sigma^>, Sigma^> - Sigma^< of (t_m, t_j), j <= m */
+  KBE_BUF_I_PREV = 1, /* [k][C][Tp]: I^{<,>}(t_{m-1}, t'), t' <= m-1 */
+  KBE_BUF_I_CUR = 2,  /* [k][C][Tp]: I^{<,>}(t_m, t'), t' <= m */
+  KBE_BUF_RHO_PREV = 3, /* [k][nb^2] */
+  KBE_BUF_RHO_CUR = 4,
+  KBE_BUF_D_PREV = 5,   /* [k][nb^2]: D = I^<(t,t) + I^<(t,t)^dag */
+  KBE_BUF_D_CUR = 6,
+  KBE_BUF_PROP = 7,     /* [k][3][nb^2]: V = e^{-i hbar dt}, Vh = e^{-i hbar dt/2}, Phi = (V-1) hbar^{-1} */
+  KBE_BUF_COL0 = 8,     /* [k][C][Tp]: G(t_j, t_0) copy of history column 0 */
+  KBE_BUF_DIAG = 9,     /* [k][C][Tp]: G(t_j, t_j) copy of the history diagonal */
+  KBE_NBUF = 10
+};
+/* Tp = 8 * ceil((nt_max + 1) / 8). Current device pointer and size of a sub-buffer (the
+ * _PREV/_CUR roles swap at every completed step). */
+int kbe_buffer(const kbe_ctx* ctx, int32_t which, void** ptr, size_t* bytes);
+
+/* a-1: hbar = h0(k - A(t_{m-1/2})) + Sigma^HF[rho], rho = rho_{m-1} (mode 0) or
+ * (rho_{m-1} + rho_m)/2 (mode 1), and V, Vh, Phi per k into KBE_BUF_PROP. */
+int kbe_stage_propagators(kbe_ctx* ctx, int32_t m, int32_t mode);
+
+/* a-2: second-Born Sigma^{<,>}(k; t_m, t_j), j = 0..m, from history row m (eq. (2BSE)), by
+ * batched k <-> R transforms and pointwise products, into KBE_BUF_SIGMA. */
+int kbe_stage_sigma(kbe_ctx* ctx, int32_t m);
+
+/* a-3 + a-4: collision integrals I^{<,>}(t_m, t'), t' = 0..m (eq. (CI), Langreth left form,
+ * trapezoid weights) from history rows 0..m, KBE_BUF_SIGMA, COL0 and DIAG, into
+ * KBE_BUF_I_CUR; D_m into KBE_BUF_D_CUR. */
+int kbe_stage_collision(kbe_ctx* ctx, int32_t m);
+
+/* a-5: row m of the history and rho_m from row m-1:
+ * mode 0 (predictor): G(t_m, t') = V G(t_{m-1}, t') + Phi I(t_{m-1}, t'),
+ * mode 1 (corrector): same with (I(t_{m-1}, .) + I(t_m, .))/2 (recomputes I(t_m, .) first);
+ * rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag, and the equal-time block. */
+int kbe_stage_update(kbe_ctx* ctx, int32_t m, int32_t mode);
+
+/* a-6: observables of t_m from rho_m and I^<(t_m, t_m) into row m of d_obs. */
+int kbe_stage_observables(kbe_ctx* ctx, int32_t m);
+
+/* Make step m the current step and swap the _PREV/_CUR roles as kbe_step does after
+ * its evaluation pass. */
+int kbe_stage_commit(kbe_ctx* ctx, int32_t m);
+
+/* Refresh the COL0 and DIAG copies from history rows 0..m (after the caller wrote
+ * history rows directly). */
+int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m);
+
+/* Per-launch timing of the history-sum kernel with HIP events on the context's stream.
+ * kbe_timing(ctx, 1) starts recording (clearing earlier records); kbe_timing_query
+ * synchronises and returns the number of launches, their summed duration (ms) and the
+ * algorithmic bytes they move (each stored history block read once). */
+int kbe_timing(kbe_ctx* ctx, int32_t enable);
+int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* algo_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KBE_H_ */

@@ -1,0 +1,435 @@
+// Context and C ABI (include/kbe.h) of the gfx950 Kadanoff-Baym library: workspace
+// layout over caller-owned device buffers, and the per-step launch sequence of
+// Algorithm "prop" (predictor, K corrector passes, evaluation on the accepted row).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kbe.h"
+#include "kbe_kernels.hpp"
+
+using kbe::cplx;
+using kbe::Dims;
+using kbe::LaunchArgs;
+
+namespace {
+
+enum {
+  B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_COUNT
+};
+
+struct Layout {
+  Dims d;
+  size_t off[B_COUNT];
+  size_t bytes[B_COUNT];
+  size_t ws_bytes, hist_bytes, obs_bytes;
+};
+
+int make_layout(const kbe_config* c, Layout* L, std::string* why) {
+  if (!c) { *why = "null config"; return KBE_ERR_INVALID_ARG; }
+  if (c->nb < 1 || c->nb > 4) { *why = "nb must be 1..4"; return KBE_ERR_SHAPE; }
+  if (c->nkx < 1 || c->nky < 1 || c->nkx > 64 || c->nky > 64 || c->nkx * c->nky > 1024) {
+    *why = "k grid must satisfy 1 <= nkx, nky <= 64 and nkx * nky <= 1024";
+    return KBE_ERR_SHAPE;
+  }
+  if ((4 * c->nkx * c->nky + c->nkx + c->nky) * 16 > 65536) {
+    *why = "k grid too large for the self-energy kernel's LDS tile (4 nk + nkx + nky <= 4096)";
+    return KBE_ERR_SHAPE;
+  }
+  if (c->nt_max < 1 || c->nt_max > 8192) { *why = "nt_max must be 1..8192"; return KBE_ERR_SHAPE; }
+  if (c->interaction != KBE_INT_HUBBARD) {
+    *why = "only the Hubbard interaction preset is implemented on the GPU";
+    return KBE_ERR_SHAPE;
+  }
+  if (c->precision != KBE_FP64) { *why = "only the FP64 form is implemented"; return KBE_ERR_SHAPE; }
+  if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
+  if (!(c->dt > 0.0) || !(c->temp > 0.0) || !std::isfinite(c->U) || c->spin_deg < 1 || c->spin_deg > 2) {
+    *why = "dt and temp must be positive, U finite, spin_deg 1 or 2";
+    return KBE_ERR_INVALID_ARG;
+  }
+  Dims& d = L->d;
+  d.nkx = c->nkx;
+  d.nky = c->nky;
+  d.nk = c->nkx * c->nky;
+  d.nb = c->nb;
+  d.nbb = c->nb * c->nb;
+  d.C = 2 * d.nbb;
+  d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
+  d.Smax = (c->nt_max + 63) / 64;
+  d.P = kbe::row_off((int64_t)c->nt_max + 1);
+  const size_t cz = sizeof(cplx);
+  size_t nk = d.nk;
+  size_t sz[B_COUNT];
+  sz[B_SIGMA] = nk * 3 * d.nbb * d.Tp * cz;
+  sz[B_IA] = sz[B_IB] = nk * d.C * d.Tp * cz;
+  sz[B_RHOA] = sz[B_RHOB] = sz[B_DA] = sz[B_DB] = nk * d.nbb * cz;
+  sz[B_PROP] = nk * 3 * d.nbb * cz;
+  sz[B_COL0] = sz[B_DIAG] = sz[B_COLSUM] = nk * d.C * d.Tp * cz;
+  sz[B_ROWPART] = nk * (size_t)d.Smax * d.nbb * d.Tp * cz;
+  sz[B_HF] = d.nbb * cz;
+  sz[B_HOP] = 3 * d.nbb * cz;
+  sz[B_EIGW] = nk * d.nb * sizeof(double);
+  sz[B_EIGU] = nk * d.nbb * cz;
+  sz[B_MU] = sizeof(double);
+  size_t off = 0;
+  for (int i = 0; i < B_COUNT; ++i) {
+    L->off[i] = off;
+    L->bytes[i] = sz[i];
+    off += (sz[i] + 255) / 256 * 256;
+  }
+  L->ws_bytes = off;
+  L->hist_bytes = (size_t)nk * d.C * (size_t)d.P * cz;
+  L->obs_bytes = (size_t)(c->nt_max + 1) * KBE_NOBS * sizeof(double);
+  return KBE_OK;
+}
+
+double pulse_A(const kbe_pulse& p, double t) {
+  if (p.width <= 0.0) return 0.0;
+  double x = (t - p.t0) / p.width;
+  return p.amp * std::sin(p.omega * t) * std::exp(-x * x);
+}
+
+}  // namespace
+
+struct kbe_ctx {
+  kbe_config cfg;
+  kbe_pulse pulse;
+  Layout L;
+  hipStream_t st;
+  char* ws;
+  cplx* hist;
+  double* obs;
+  int cur;   // slot holding the *_prev role
+  int step;  // last completed step
+  std::string err;
+  std::vector<cplx> hop_host;
+  // timing of the history-sum launches
+  bool timing;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_m;
+  size_t ev_used;
+
+  template <class T>
+  T* buf(int b) const { return reinterpret_cast<T*>(ws + L.off[b]); }
+
+  LaunchArgs args() const {
+    LaunchArgs a;
+    a.hist = hist;
+    a.sig = buf<cplx>(B_SIGMA);
+    a.I_prev = buf<cplx>(cur == 0 ? B_IA : B_IB);
+    a.I_cur = buf<cplx>(cur == 0 ? B_IB : B_IA);
+    a.col0 = buf<cplx>(B_COL0);
+    a.diag = buf<cplx>(B_DIAG);
+    a.colsum = buf<cplx>(B_COLSUM);
+    a.rowpart = buf<cplx>(B_ROWPART);
+    a.rho_prev = buf<cplx>(cur == 0 ? B_RHOA : B_RHOB);
+    a.rho_cur = buf<cplx>(cur == 0 ? B_RHOB : B_RHOA);
+    a.D_prev = buf<cplx>(cur == 0 ? B_DA : B_DB);
+    a.D_cur = buf<cplx>(cur == 0 ? B_DB : B_DA);
+    a.props = buf<cplx>(B_PROP);
+    a.hfbuf = buf<cplx>(B_HF);
+    a.hop = buf<cplx>(B_HOP);
+    a.eig_w = buf<double>(B_EIGW);
+    a.eig_U = buf<cplx>(B_EIGU);
+    a.mu = buf<double>(B_MU);
+    a.obs = obs;
+    a.Ax = a.Ay = 0.0;
+    a.dt = cfg.dt;
+    a.U = cfg.U;
+    a.UU = cfg.U * cfg.U;
+    a.temp = cfg.temp;
+    a.target = (double)cfg.nb * cfg.filling * (double)L.d.nk;
+    a.spin = cfg.spin_deg;
+    a.interaction = cfg.interaction;
+    a.hf = cfg.hf;
+    a.corr = cfg.corr;
+    return a;
+  }
+  void set_A(LaunchArgs& a, double t) const {
+    double A = pulse_A(pulse, t);
+    a.Ax = A * pulse.pol[0];
+    a.Ay = A * pulse.pol[1];
+  }
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int check(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(KBE_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return KBE_OK;
+  }
+  int bulk_timed(const LaunchArgs& a, int m) {
+    if (timing && m >= 1) {
+      if (ev_used + 2 > ev.size()) {
+        for (int i = 0; i < 256; ++i) {
+          hipEvent_t e;
+          if (hipEventCreate(&e) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventCreate failed");
+          ev.push_back(e);
+        }
+      }
+      if (hipEventRecord(ev[ev_used], st) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventRecord failed");
+      int rc = check(kbe::launch_bulk(L.d, a, m, st), "history-sum launch");
+      if (rc) return rc;
+      if (hipEventRecord(ev[ev_used + 1], st) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventRecord failed");
+      ev_used += 2;
+      ev_m.push_back(m);
+      return KBE_OK;
+    }
+    return check(kbe::launch_bulk(L.d, a, m, st), "history-sum launch");
+  }
+  // Sigma row, equal-time collision integral, history sums of row m.
+  int collision_parts(LaunchArgs& a, int m) {
+    int rc = check(kbe::launch_sigma(L.d, a, m, st), "self-energy launch");
+    if (!rc) rc = check(kbe::launch_diag_I(L.d, a, m, st), "equal-time collision launch");
+    if (!rc) rc = bulk_timed(a, m);
+    return rc;
+  }
+  int props(LaunchArgs& a, int m, int mode) {
+    set_A(a, (m - 0.5) * cfg.dt);
+    int rc = check(kbe::launch_hf(L.d, a, mode == 0 ? 0.0 : 0.5, st), "mean-field launch");
+    if (!rc) rc = check(kbe::launch_props(L.d, a, st), "propagator launch");
+    return rc;
+  }
+  int observe(int m) {
+    LaunchArgs a = args();
+    double t = m * cfg.dt;
+    set_A(a, t);
+    return check(kbe::launch_obs(L.d, a, m, t, pulse_A(pulse, t), st), "observables launch");
+  }
+  int one_step() {
+    int m = step + 1;
+    if (m > cfg.nt_max) return fail(KBE_ERR_STATE, "step index would pass nt_max");
+    LaunchArgs a = args();
+    int rc = props(a, m, 0);
+    if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_PREDICT, st), "predictor launch");
+    for (int it = 0; it < cfg.n_corr && !rc; ++it) {
+      rc = collision_parts(a, m);
+      if (!rc) rc = props(a, m, 1);
+      if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_CORRECT, st), "corrector launch");
+    }
+    if (!rc) rc = collision_parts(a, m);
+    if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_EVAL, st), "collision-row launch");
+    if (!rc) rc = observe(m);
+    if (rc) return rc;
+    cur ^= 1;
+    step = m;
+    return KBE_OK;
+  }
+};
+
+extern "C" {
+
+int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* workspace_bytes,
+                        size_t* obs_bytes) {
+  Layout L;
+  std::string why;
+  int rc = make_layout(cfg, &L, &why);
+  if (rc) return rc;
+  if (history_bytes) *history_bytes = L.hist_bytes;
+  if (workspace_bytes) *workspace_bytes = L.ws_bytes;
+  if (obs_bytes) *obs_bytes = L.obs_bytes;
+  return KBE_OK;
+}
+
+int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+               void* d_workspace, void* d_obs, void* hip_stream, kbe_ctx** out) {
+  if (!out) return KBE_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!cfg || !hop || !d_history || !d_workspace || !d_obs) return KBE_ERR_INVALID_ARG;
+  kbe_ctx* c = new kbe_ctx();
+  c->cfg = *cfg;
+  if (pulse) c->pulse = *pulse;
+  else std::memset(&c->pulse, 0, sizeof(c->pulse));
+  std::string why;
+  int rc = make_layout(cfg, &c->L, &why);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  c->st = (hipStream_t)hip_stream;
+  c->ws = (char*)d_workspace;
+  c->hist = (cplx*)d_history;
+  c->obs = (double*)d_obs;
+  c->cur = 0;
+  c->step = 0;
+  c->timing = false;
+  c->ev_used = 0;
+  const Dims& d = c->L.d;
+  c->hop_host.resize(3 * d.nbb);
+  for (int i = 0; i < 3 * d.nbb; ++i) c->hop_host[i] = make_double2(hop[2 * i], hop[2 * i + 1]);
+  if (d.nky == 1)
+    for (int i = 0; i < d.nbb; ++i) c->hop_host[2 * d.nbb + i] = make_double2(0.0, 0.0);
+  LaunchArgs a = c->args();
+  rc = c->check(hipMemcpyAsync(a.hop, c->hop_host.data(), 3 * d.nbb * sizeof(cplx), hipMemcpyHostToDevice, c->st),
+                "copy of the hopping blocks");
+  if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_IA), 2 * c->L.bytes[B_IA] / sizeof(cplx), c->st), "zero");
+  if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_IB), 2 * c->L.bytes[B_IB] / sizeof(cplx), c->st), "zero");
+  if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_DA), 2 * c->L.bytes[B_DA] / sizeof(cplx), c->st), "zero");
+  if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_DB), 2 * c->L.bytes[B_DB] / sizeof(cplx), c->st), "zero");
+  if (!rc) rc = c->check(kbe::launch_fill_zero(c->obs, c->L.obs_bytes / sizeof(double), c->st), "zero");
+  if (!rc) {
+    c->set_A(a, 0.0);
+    rc = c->check(kbe::launch_init(d, a, c->st), "initial-state launch");
+  }
+  if (!rc) rc = c->observe(0);
+  if (!rc) rc = c->check(hipStreamSynchronize(c->st), "initial state");
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return KBE_OK;
+}
+
+int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
+  if (!ctx || nsteps < 0) return KBE_ERR_INVALID_ARG;
+  if (ctx->step + nsteps > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_STATE, "step index would pass nt_max");
+  for (int i = 0; i < nsteps; ++i) {
+    int rc = ctx->one_step();
+    if (rc) return rc;
+  }
+  return KBE_OK;
+}
+
+int32_t kbe_current_step(const kbe_ctx* ctx) { return ctx ? ctx->step : -1; }
+
+int kbe_observables(kbe_ctx* ctx, int32_t first, int32_t count, double* host_out) {
+  if (!ctx || !host_out || first < 0 || count < 0 || first + count > ctx->cfg.nt_max + 1)
+    return KBE_ERR_INVALID_ARG;
+  int rc = ctx->check(hipStreamSynchronize(ctx->st), "stream synchronisation");
+  if (rc) return rc;
+  rc = ctx->check(hipMemcpy(host_out, ctx->obs + (size_t)first * KBE_NOBS, (size_t)count * KBE_NOBS * sizeof(double),
+                            hipMemcpyDeviceToHost),
+                  "observables copy");
+  if (rc) return rc;
+  for (int i = 0; i < count * KBE_NOBS; ++i)
+    if (!std::isfinite(host_out[i])) return ctx->fail(KBE_ERR_NONFINITE, "non-finite observable");
+  return KBE_OK;
+}
+
+void kbe_destroy(kbe_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->st);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* kbe_last_error(const kbe_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int kbe_buffer(const kbe_ctx* ctx, int32_t which, void** ptr, size_t* bytes) {
+  if (!ctx || !ptr) return KBE_ERR_INVALID_ARG;
+  int b;
+  int c = ctx->cur;
+  switch (which) {
+    case KBE_BUF_SIGMA: b = B_SIGMA; break;
+    case KBE_BUF_I_PREV: b = c == 0 ? B_IA : B_IB; break;
+    case KBE_BUF_I_CUR: b = c == 0 ? B_IB : B_IA; break;
+    case KBE_BUF_RHO_PREV: b = c == 0 ? B_RHOA : B_RHOB; break;
+    case KBE_BUF_RHO_CUR: b = c == 0 ? B_RHOB : B_RHOA; break;
+    case KBE_BUF_D_PREV: b = c == 0 ? B_DA : B_DB; break;
+    case KBE_BUF_D_CUR: b = c == 0 ? B_DB : B_DA; break;
+    case KBE_BUF_PROP: b = B_PROP; break;
+    case KBE_BUF_COL0: b = B_COL0; break;
+    case KBE_BUF_DIAG: b = B_DIAG; break;
+    default: return KBE_ERR_INVALID_ARG;
+  }
+  *ptr = ctx->ws + ctx->L.off[b];
+  if (bytes) *bytes = ctx->L.bytes[b];
+  return KBE_OK;
+}
+
+static int check_m(kbe_ctx* ctx, int32_t m, int lo) {
+  if (!ctx) return KBE_ERR_INVALID_ARG;
+  if (m < lo || m > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_INVALID_ARG, "time-slice index out of range");
+  return KBE_OK;
+}
+
+int kbe_stage_propagators(kbe_ctx* ctx, int32_t m, int32_t mode) {
+  int rc = check_m(ctx, m, 1);
+  if (rc) return rc;
+  if (mode != 0 && mode != 1) return ctx->fail(KBE_ERR_INVALID_ARG, "mode must be 0 or 1");
+  LaunchArgs a = ctx->args();
+  return ctx->props(a, m, mode);
+}
+
+int kbe_stage_sigma(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  LaunchArgs a = ctx->args();
+  return ctx->check(kbe::launch_sigma(ctx->L.d, a, m, ctx->st), "self-energy launch");
+}
+
+int kbe_stage_collision(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  LaunchArgs a = ctx->args();
+  rc = ctx->check(kbe::launch_diag_I(ctx->L.d, a, m, ctx->st), "equal-time collision launch");
+  if (!rc) rc = ctx->bulk_timed(a, m);
+  if (!rc) rc = ctx->check(kbe::launch_row(ctx->L.d, a, m, KBE_ROW_EVAL, ctx->st), "collision-row launch");
+  return rc;
+}
+
+int kbe_stage_update(kbe_ctx* ctx, int32_t m, int32_t mode) {
+  int rc = check_m(ctx, m, 1);
+  if (rc) return rc;
+  if (mode != 0 && mode != 1) return ctx->fail(KBE_ERR_INVALID_ARG, "mode must be 0 or 1");
+  LaunchArgs a = ctx->args();
+  return ctx->check(kbe::launch_row(ctx->L.d, a, m, mode == 0 ? KBE_ROW_PREDICT : KBE_ROW_CORRECT, ctx->st),
+                    "update launch");
+}
+
+int kbe_stage_observables(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  return ctx->observe(m);
+}
+
+int kbe_stage_commit(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  ctx->cur ^= 1;
+  ctx->step = m;
+  return KBE_OK;
+}
+
+int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  LaunchArgs a = ctx->args();
+  return ctx->check(kbe::launch_aux(ctx->L.d, a, m, ctx->st), "aux launch");
+}
+
+int kbe_timing(kbe_ctx* ctx, int32_t enable) {
+  if (!ctx) return KBE_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  ctx->ev_m.clear();
+  return KBE_OK;
+}
+
+int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* algo_bytes) {
+  if (!ctx) return KBE_ERR_INVALID_ARG;
+  int rc = ctx->check(hipStreamSynchronize(ctx->st), "stream synchronisation");
+  if (rc) return rc;
+  double ms_sum = 0.0, bytes = 0.0;
+  const Dims& d = ctx->L.d;
+  for (size_t i = 0; i < ctx->ev_m.size(); ++i) {
+    float ms = 0.f;
+    rc = ctx->check(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]), "hipEventElapsedTime");
+    if (rc) return rc;
+    ms_sum += ms;
+    double m = ctx->ev_m[i];
+    bytes += 0.5 * m * (m + 1.0) * d.nk * d.C * sizeof(cplx);
+  }
+  if (launches) *launches = (int64_t)ctx->ev_m.size();
+  if (total_ms) *total_ms = ms_sum;
+  if (algo_bytes) *algo_bytes = bytes;
+  return KBE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Device-side helpers of the gfx950 Kadanoff-Baym library: complex arithmetic on
+// double2, small fixed-size matrix products, the packed two-time layout, and the
+// single-particle Hamiltonian of the lattice model.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kbe {
+
+typedef double2 cplx;
+
+// ------------------------------------------------------------------ complex arithmetic
+__device__ __forceinline__ cplx cmk(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ cplx czero() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cneg(cplx a) { return make_double2(-a.x, -a.y); }
+__device__ __forceinline__ cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ cplx cscal(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ cplx cmuli(cplx a) { return make_double2(-a.y, a.x); }  // i * a
+// acc += a * b
+__device__ __forceinline__ void cmac(cplx& acc, cplx a, cplx b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += a * conj(b)
+__device__ __forceinline__ void cmacc(cplx& acc, cplx a, cplx b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.y, b.x, acc.y);
+  acc.y = fma(-a.x, b.y, acc.y);
+}
+__device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------------ NB x NB matrices (row-major)
+template <int NB>
+__device__ __forceinline__ void mat_zero(cplx* A) {
+#pragma unroll
+  for (int i = 0; i < NB * NB; ++i) A[i] = czero();
+}
+// acc += A B
+template <int NB>
+__device__ __forceinline__ void mm_acc(cplx* acc, const cplx* A, const cplx* B) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int l = 0; l < NB; ++l) cmac(acc[i * NB + j], A[i * NB + l], B[l * NB + j]);
+}
+// acc += A B^dag   ((A B^dag)_ij = sum_l A_il conj(B_jl))
+template <int NB>
+__device__ __forceinline__ void mm_acc_bdag(cplx* acc, const cplx* A, const cplx* B) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int l = 0; l < NB; ++l) cmacc(acc[i * NB + j], A[i * NB + l], B[j * NB + l]);
+}
+
+// ------------------------------------------------------------------ layout
+// Packed two-time history: rows padded to 8 elements (128 B) so that every row of every
+// (k, component) plane starts on a cache-line boundary.
+//   rowoff(j) = sum_{i<j} 8 ceil((i+1)/8) = 32 Q (Q+1) + 8 r (Q+1),  Q = j/8, r = j%8.
+__host__ __device__ __forceinline__ int64_t row_off(int64_t j) {
+  int64_t Q = j >> 3, r = j & 7;
+  return 32 * Q * (Q + 1) + 8 * r * (Q + 1);
+}
+
+struct Dims {
+  int nkx, nky, nk, nb;
+  int nbb, C;      // nb^2, 2 nb^2 complex components per two-time block
+  int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
+  int Smax;        // number of 64-column strips of the largest history pass
+  int64_t P;       // padded length of one (k, component) plane of the history
+};
+
+// Element index helpers (complex units).
+__host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
+  return ((int64_t)k * d.C + c) * d.P + row_off(j) + tp;
+}
+__host__ __device__ __forceinline__ int64_t rowbuf_idx(const Dims& d, int k, int c, int t) {
+  return ((int64_t)k * d.C + c) * d.Tp + t;
+}
+// Sigma row: [k][3][nb^2][Tp] with components 0: Sigma^<, 1: Sigma^>, 2: Sigma^> - Sigma^<.
+__host__ __device__ __forceinline__ int64_t sig_idx(const Dims& d, int k, int s, int e, int t) {
+  return (((int64_t)k * 3 + s) * d.nbb + e) * d.Tp + t;
+}
+
+// ------------------------------------------------------------------ model
+// Bloch Hamiltonian h0(q) = T0 + sum_d [T_d e^{i q_d} + T_d^dag e^{-i q_d}] at q = k - A,
+// k from eq. (kj): k_j = -pi + 2 pi j / n. hop = [T0, Tx, Ty], each NB x NB.
+template <int NB>
+__device__ __forceinline__ void bloch_h0(const cplx* __restrict__ hop, int nkx, int nky, int k, double Ax,
+                                         double Ay, cplx* h) {
+  int ix = k / nky, iy = k - (k / nky) * nky;
+  double qx = -M_PI + 2.0 * M_PI * (double)ix / (double)nkx - Ax;
+  double sx, cx;
+  sincos(qx, &sx, &cx);
+  cplx ex = cmk(cx, sx), emx = cmk(cx, -sx);
+  cplx ey = czero(), emy = czero();
+  bool two = nky > 1;
+  if (two) {
+    double qy = -M_PI + 2.0 * M_PI * (double)iy / (double)nky - Ay;
+    double sy, cy;
+    sincos(qy, &sy, &cy);
+    ey = cmk(cy, sy);
+    emy = cmk(cy, -sy);
+  }
+  const cplx* T0 = hop;
+  const cplx* Tx = hop + NB * NB;
+  const cplx* Ty = hop + 2 * NB * NB;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      cplx s = T0[a * NB + b];
+      s = cadd(s, cmul(Tx[a * NB + b], ex));
+      s = cadd(s, cmul(cconj(Tx[b * NB + a]), emx));
+      if (two) {
+        s = cadd(s, cmul(Ty[a * NB + b], ey));
+        s = cadd(s, cmul(cconj(Ty[b * NB + a]), emy));
+      }
+      h[a * NB + b] = s;
+    }
+}
+
+// Velocity d h0 / d q_d = i (T_d e^{i q_d} - T_d^dag e^{-i q_d}) at q = k - A.
+template <int NB>
+__device__ __forceinline__ void bloch_vel(const cplx* __restrict__ hop, int nkx, int nky, int k, double Ax,
+                                          double Ay, int dir, cplx* v) {
+  int ix = k / nky, iy = k - (k / nky) * nky;
+  double q = dir == 0 ? (-M_PI + 2.0 * M_PI * (double)ix / (double)nkx - Ax)
+                      : (-M_PI + 2.0 * M_PI * (double)iy / (double)nky - Ay);
+  double sq, cq;
+  sincos(q, &sq, &cq);
+  cplx e = cmk(cq, sq), em = cmk(cq, -sq);
+  const cplx* T = hop + (1 + dir) * NB * NB;
+  bool on = (dir == 0) || (nky > 1);
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      cplx s = csub(cmul(T[a * NB + b], e), cmul(cconj(T[b * NB + a]), em));
+      v[a * NB + b] = on ? cmuli(s) : czero();
+    }
+}
+
+// Eigen-decomposition of a Hermitian NB x NB matrix held by one thread: cyclic Jacobi
+// sweeps with complex plane rotations. A is overwritten; w ascending, columns of V the
+// eigenvectors (A_in = V diag(w) V^dag).
+template <int NB>
+__device__ void jacobi_eigh(cplx* A, double* w, cplx* V) {
+#pragma unroll
+  for (int i = 0; i < NB * NB; ++i) V[i] = czero();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) V[i * NB + i] = cmk(1.0, 0.0);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (p == q) dia += cabs2(A[p * NB + q]);
+        else off += cabs2(A[p * NB + q]);
+      }
+    if (!(off > 1e-34 * (dia + 1e-300))) break;
+#pragma unroll
+    for (int p = 0; p < NB - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < NB; ++q) {
+        cplx apq = A[p * NB + q];
+        double r = sqrt(cabs2(apq));
+        if (r < 1e-300) continue;
+        cplx e = cscal(apq, 1.0 / r);
+        double tau = (A[q * NB + q].x - A[p * NB + p].x) / (2.0 * r);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        // plane unitary: col p = (c, -s conj(e)), col q = (s, c conj(e))
+        cplx wqp = cscal(cconj(e), -s), wqq = cscal(cconj(e), c);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          cplx aip = A[i * NB + p], aiq = A[i * NB + q];
+          A[i * NB + p] = cadd(cscal(aip, c), cmul(aiq, wqp));
+          A[i * NB + q] = cadd(cscal(aip, s), cmul(aiq, wqq));
+          cplx vip = V[i * NB + p], viq = V[i * NB + q];
+          V[i * NB + p] = cadd(cscal(vip, c), cmul(viq, wqp));
+          V[i * NB + q] = cadd(cscal(vip, s), cmul(viq, wqq));
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          cplx apj = A[p * NB + j], aqj = A[q * NB + j];
+          A[p * NB + j] = cadd(cscal(apj, c), cmul(cconj(wqp), aqj));
+          A[q * NB + j] = cadd(cscal(apj, s), cmul(cconj(wqq), aqj));
+        }
+        A[p * NB + q] = czero();
+        A[q * NB + p] = czero();
+        A[p * NB + p].y = 0.0;
+        A[q * NB + q].y = 0.0;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) w[i] = A[i * NB + i].x;
+  // insertion sort, ascending, carrying the eigenvector columns
+  for (int i = 1; i < NB; ++i)
+    for (int j = i; j > 0 && w[j - 1] > w[j]; --j) {
+      double tw = w[j];
+      w[j] = w[j - 1];
+      w[j - 1] = tw;
+      for (int r = 0; r < NB; ++r) {
+        cplx tv = V[r * NB + j];
+        V[r * NB + j] = V[r * NB + j - 1];
+        V[r * NB + j - 1] = tv;
+      }
+    }
+}
+
+}  // namespace kbe

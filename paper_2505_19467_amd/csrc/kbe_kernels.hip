@@ -1,0 +1,906 @@
+// HIP kernels (gfx950) of the Kadanoff-Baym propagation step.
+//
+//   k_init_*      uncorrelated initial state (Fermi-Dirac density of h0, mu by bisection)
+//   k_hf          mean-field (first-order) self-energy from the local density matrix
+//   k_props       per-k propagators V, Vh, Phi of the midpoint Hamiltonian (scaling and
+//                 squaring of an augmented matrix exponential, one wavefront per k)
+//   k_sigma       second-Born self-energy of a time slice, eq. (2BSE), by k <-> R transforms
+//   k_diag_I      equal-time collision integral I^<(t_m, t_m) and D_m
+//   k_hist_bulk   the history sums of eq. (CI): streams the packed triangle of rows
+//                 0..m-1 once, every stored block feeding its column and its row
+//   k_row         end-point terms, collision row assembly, predictor/corrector update
+//   k_obs         observables of one time slice
+//   k_aux         refresh the column-0 / diagonal copies of the history
+#include "kbe_device.hpp"
+#include "kbe_kernels.hpp"
+
+namespace kbe {
+
+// ------------------------------------------------------------------ block reductions
+template <int N>
+__device__ __forceinline__ void block_sum_cplx(cplx* v, cplx* lds /* [N][256] */) {
+  int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) lds[i * 256 + t] = v[i];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) lds[i * 256 + t] = cadd(lds[i * 256 + t], lds[i * 256 + t + s]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = lds[i * 256];
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// ------------------------------------------------------------------ utility
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ initial state
+// Eigen-decomposition of h0(k - A(0)) per k (one thread per k).
+template <int NB>
+__global__ __launch_bounds__(64) void k_init_eig(Dims d, const cplx* __restrict__ hop, double Ax, double Ay,
+                                                 double* __restrict__ w, cplx* __restrict__ U) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nk) return;
+  cplx h[NB * NB], V[NB * NB];
+  double ev[NB];
+  bloch_h0<NB>(hop, d.nkx, d.nky, k, Ax, Ay, h);
+  jacobi_eigh<NB>(h, ev, V);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) w[k * NB + b] = ev[b];
+#pragma unroll
+  for (int i = 0; i < NB * NB; ++i) U[(int64_t)k * NB * NB + i] = V[i];
+}
+
+// Chemical potential by bisection: N_k^{-1} sum_{k,b} f((w - mu)/T) = target (one block).
+__global__ __launch_bounds__(256) void k_init_mu(int n, const double* __restrict__ w, double temp,
+                                                 double target, double* __restrict__ mu_out) {
+  __shared__ double red[256];
+  __shared__ double lohi[2];
+  int t = threadIdx.x;
+  double lo = 1e300, hi = -1e300;
+  for (int i = t; i < n; i += 256) {
+    lo = fmin(lo, w[i]);
+    hi = fmax(hi, w[i]);
+  }
+  red[t] = lo;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmin(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) lohi[0] = red[0] - 50.0 * temp - 1.0;
+  __syncthreads();
+  red[t] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) lohi[1] = red[0] + 50.0 * temp + 1.0;
+  __syncthreads();
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lohi[0] + lohi[1]);
+    double acc = 0.0;
+    for (int i = t; i < n; i += 256) acc += 1.0 / (1.0 + exp((w[i] - mid) / temp));
+    red[t] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    if (t == 0) {
+      if (red[0] < target) lohi[0] = mid;
+      else lohi[1] = mid;
+    }
+    __syncthreads();
+    if (lohi[1] - lohi[0] < 1e-15 * fmax(1.0, fabs(mid))) break;
+  }
+  if (t == 0) *mu_out = 0.5 * (lohi[0] + lohi[1]);
+}
+
+// rho0 = U f(w - mu) U^dag; row 0 of the history (G^< = i rho, G^> = -i (1 - rho)).
+template <int NB>
+__global__ __launch_bounds__(64) void k_init_rho(Dims d, const double* __restrict__ w, const cplx* __restrict__ U,
+                                                 const double* __restrict__ mu, double temp,
+                                                 cplx* __restrict__ rhoA, cplx* __restrict__ rhoB,
+                                                 cplx* __restrict__ hist, cplx* __restrict__ col0,
+                                                 cplx* __restrict__ diag) {
+  constexpr int NBB = NB * NB;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nk) return;
+  double f[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) f[b] = 1.0 / (1.0 + exp((w[k * NB + b] - *mu) / temp));
+  const cplx* Uk = U + (int64_t)k * NBB;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      cplx s = czero();
+#pragma unroll
+      for (int c = 0; c < NB; ++c) s = cadd(s, cscal(cmul(Uk[a * NB + c], cconj(Uk[b * NB + c])), f[c]));
+      int e = a * NB + b;
+      rhoA[(int64_t)k * NBB + e] = s;
+      rhoB[(int64_t)k * NBB + e] = s;
+      cplx gl = cmuli(s);
+      cplx one_minus = csub(cmk(a == b ? 1.0 : 0.0, 0.0), s);
+      cplx gg = cneg(cmuli(one_minus));
+      hist[hist_idx(d, k, e, 0, 0)] = gl;
+      hist[hist_idx(d, k, NBB + e, 0, 0)] = gg;
+      col0[rowbuf_idx(d, k, e, 0)] = gl;
+      col0[rowbuf_idx(d, k, NBB + e, 0)] = gg;
+      diag[rowbuf_idx(d, k, e, 0)] = gl;
+      diag[rowbuf_idx(d, k, NBB + e, 0)] = gg;
+    }
+}
+
+// ------------------------------------------------------------------ mean field
+// hf_out = one-body extra term + Sigma^HF[rho_loc], rho = (1 - wb) rhoA + wb rhoB (one block).
+template <int NB>
+__global__ __launch_bounds__(256) void k_hf(Dims d, const cplx* __restrict__ rhoA, const cplx* __restrict__ rhoB,
+                                            double wb, int interaction, int hf, double U,
+                                            cplx* __restrict__ hf_out) {
+  constexpr int NBB = NB * NB;
+  __shared__ cplx lds[NBB * 256];
+  cplx loc[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) loc[e] = czero();
+  for (int k = threadIdx.x; k < d.nk; k += 256)
+#pragma unroll
+    for (int e = 0; e < NBB; ++e)
+      loc[e] = cadd(loc[e], cadd(cscal(rhoA[(int64_t)k * NBB + e], 1.0 - wb), cscal(rhoB[(int64_t)k * NBB + e], wb)));
+  block_sum_cplx<NBB>(loc, lds);
+  if (threadIdx.x == 0) {
+    double inv = 1.0 / d.nk;
+    cplx out[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) out[e] = czero();
+    if (interaction == KBE_DEV_INT_HUBBARD) {
+      if (hf)
+#pragma unroll
+        for (int a = 0; a < NB; ++a) out[a * NB + a] = cmk(U * loc[a * NB + a].x * inv, 0.0);
+    } else {
+      // eq. (ham): -U c_c^dag c_c one-body term; Hartree U n_c / U n_v, Fock -U rho_vc
+      out[NBB - 1] = cmk(-U, 0.0);
+      if constexpr (NB == 2) {
+        if (hf) {
+          out[0] = cadd(out[0], cmk(U * loc[3].x * inv, 0.0));
+          out[3] = cadd(out[3], cmk(U * loc[0].x * inv, 0.0));
+          out[1] = cscal(loc[1], -U * inv);
+          out[2] = cscal(loc[2], -U * inv);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) hf_out[e] = out[e];
+  }
+}
+
+// ------------------------------------------------------------------ propagators
+// One wavefront per k. The augmented matrix M = [[-i hbar dt, dt 1], [0, 0]] (2NB x 2NB)
+// has exp(M) = [[V, dt phi1(-i hbar dt)], [0, 1]], so Phi = -i * (top-right block).
+// exp(M / 2^s) by a degree-16 Taylor polynomial (Horner), ||M / 2^s||_F <= 1/4, then s
+// squarings; the square before the last is exp(M/2), whose top-left block is Vh.
+template <int NB>
+__global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ hop, const cplx* __restrict__ hf,
+                                               double Ax, double Ay, double dt, cplx* __restrict__ props) {
+  constexpr int N2 = 2 * NB, NN = N2 * N2, NBB = NB * NB;
+  __shared__ cplx sX[4][NN], sE[4][NN];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int k = blockIdx.x * 4 + wv;
+  bool kval = k < d.nk;
+  int r = lane / N2, c = lane - (lane / N2) * N2;
+  bool act = kval && lane < NN;
+  cplx m = czero();
+  if (act) {
+    if (r < NB && c < NB) {
+      cplx h[NBB];
+      bloch_h0<NB>(hop, d.nkx, d.nky, k, Ax, Ay, h);
+      cplx hb = cadd(h[r * NB + c], hf[r * NB + c]);
+      m = cscal(cmuli(hb), -dt);  // -i hbar dt
+    } else if (r < NB && c == r + NB) {
+      m = cmk(dt, 0.0);
+    }
+  }
+  double nrm2 = wave_sum(act ? cabs2(m) : 0.0);
+  int s = 1;
+  double nrm = sqrt(nrm2);
+  while (nrm > ldexp(0.25, s) && s < 60) ++s;
+  double scale = ldexp(1.0, -s);
+  cplx x = cscal(m, scale);
+  cplx id = cmk((act && r == c) ? 1.0 : 0.0, 0.0);
+  if (lane < NN) sX[wv][lane] = x;
+  cplx e = id;
+  if (lane < NN) sE[wv][lane] = e;
+  __syncthreads();
+  for (int n = 16; n >= 1; --n) {  // E <- 1 + X E / n
+    cplx acc = czero();
+    if (lane < NN)
+#pragma unroll
+      for (int l = 0; l < N2; ++l) cmac(acc, sX[wv][r * N2 + l], sE[wv][l * N2 + c]);
+    __syncthreads();
+    e = cadd(id, cscal(acc, 1.0 / n));
+    if (lane < NN) sE[wv][lane] = e;
+    __syncthreads();
+  }
+  cplx half = czero();
+  for (int q = 0; q < s; ++q) {  // E <- E E
+    if (q == s - 1) half = e;
+    cplx acc = czero();
+    if (lane < NN)
+#pragma unroll
+      for (int l = 0; l < N2; ++l) cmac(acc, sE[wv][r * N2 + l], sE[wv][l * N2 + c]);
+    __syncthreads();
+    e = acc;
+    if (lane < NN) sE[wv][lane] = e;
+    __syncthreads();
+  }
+  if (act && r < NB) {
+    cplx* P = props + (int64_t)k * 3 * NBB;
+    if (c < NB) {
+      P[r * NB + c] = e;              // V
+      P[NBB + r * NB + c] = half;     // Vh
+    } else {
+      P[2 * NBB + r * NB + (c - NB)] = cneg(cmuli(e));  // Phi = -i * top-right
+    }
+  }
+}
+
+// ------------------------------------------------------------------ self-energy
+// One block per (t_j, orbital pair ab) of row m. With plain index transforms
+//   g(R) = N_k^{-1} sum_j e^{+2 pi i j.R / n} G(k_j),   S(k_j) = sum_R e^{-2 pi i j.R / n} S(R),
+// the -pi offset of eq. (kj) cancels in the product of two forward lines and one backward
+// line, and the backward line is g_ba(-R; t_j, t_m) = -conj(g_ab(R; t_m, t_j)), so
+//   Hubbard:  Sigma^<_ab(R) = -U^2 g^<_ab(R)^2 conj(g^>_ab(R)),  Sigma^> with < and > swapped.
+// Block-to-work mapping gives each XCD a contiguous range of t_j, so the cache lines of
+// row m that several t_j share stay in one L2.
+template <int NB>
+__global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ sig,
+                                               int m, double UU, int corr) {
+  constexpr int NBB = NB * NB;
+  extern __shared__ cplx lds[];
+  cplx* gl = lds;
+  cplx* gg = lds + d.nk;
+  cplx* tl = lds + 2 * d.nk;
+  cplx* tg = lds + 3 * d.nk;
+  cplx* twx = lds + 4 * d.nk;          // e^{2 pi i p / nkx}
+  cplx* twy = twx + d.nkx;             // e^{2 pi i p / nky}
+  int total = (m + 1) * NBB;
+  int per = (total + 7) >> 3;
+  int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= total) return;
+  int j = item / NBB, ab = item - (item / NBB) * NBB;
+  int t = threadIdx.x;
+  int nx = d.nkx, ny = d.nky, nk = d.nk;
+  for (int p = t; p < nx; p += 256) {
+    double sn, cs;
+    sincospi(2.0 * p / nx, &sn, &cs);
+    twx[p] = cmk(cs, sn);
+  }
+  for (int p = t; p < ny; p += 256) {
+    double sn, cs;
+    sincospi(2.0 * p / ny, &sn, &cs);
+    twy[p] = cmk(cs, sn);
+  }
+  int64_t roff = row_off(m) + j;
+  for (int k = t; k < nk; k += 256) {
+    gl[k] = hist[((int64_t)k * d.C + ab) * d.P + roff];
+    gg[k] = hist[((int64_t)k * d.C + NBB + ab) * d.P + roff];
+  }
+  __syncthreads();
+  // k -> R along y: t[ix][ry] = sum_iy e^{+2 pi i iy ry / ny} g[ix][iy]
+  for (int o = t; o < nk; o += 256) {
+    int ix = o / ny, ry = o - (o / ny) * ny;
+    cplx al = czero(), ag = czero();
+    for (int iy = 0; iy < ny; ++iy) {
+      cplx w = twy[(iy * ry) % ny];
+      cmac(al, gl[ix * ny + iy], w);
+      cmac(ag, gg[ix * ny + iy], w);
+    }
+    tl[o] = al;
+    tg[o] = ag;
+  }
+  __syncthreads();
+  // along x, normalise, pointwise second-Born products
+  double inv = 1.0 / nk;
+  for (int o = t; o < nk; o += 256) {
+    int rx = o / ny, ry = o - (o / ny) * ny;
+    cplx al = czero(), ag = czero();
+    for (int ix = 0; ix < nx; ++ix) {
+      cplx w = twx[(ix * rx) % nx];
+      cmac(al, tl[ix * ny + ry], w);
+      cmac(ag, tg[ix * ny + ry], w);
+    }
+    al = cscal(al, inv);
+    ag = cscal(ag, inv);
+    cplx sl = czero(), sg = czero();
+    if (corr) {
+      sl = cscal(cmul(cmul(al, al), cconj(ag)), -UU);
+      sg = cscal(cmul(cmul(ag, ag), cconj(al)), -UU);
+    }
+    gl[o] = sl;
+    gg[o] = sg;
+  }
+  __syncthreads();
+  // R -> k along y: t[rx][iy] = sum_ry e^{-2 pi i iy ry / ny} S[rx][ry]
+  for (int o = t; o < nk; o += 256) {
+    int rx = o / ny, iy = o - (o / ny) * ny;
+    cplx al = czero(), ag = czero();
+    for (int ry = 0; ry < ny; ++ry) {
+      cplx w = cconj(twy[(iy * ry) % ny]);
+      cmac(al, gl[rx * ny + ry], w);
+      cmac(ag, gg[rx * ny + ry], w);
+    }
+    tl[o] = al;
+    tg[o] = ag;
+  }
+  __syncthreads();
+  for (int o = t; o < nk; o += 256) {
+    int ix = o / ny, iy = o - (o / ny) * ny;
+    cplx al = czero(), ag = czero();
+    for (int rx = 0; rx < nx; ++rx) {
+      cplx w = cconj(twx[(ix * rx) % nx]);
+      cmac(al, tl[rx * ny + iy], w);
+      cmac(ag, tg[rx * ny + iy], w);
+    }
+    sig[sig_idx(d, o, 0, ab, j)] = al;
+    sig[sig_idx(d, o, 1, ab, j)] = ag;
+    sig[sig_idx(d, o, 2, ab, j)] = csub(ag, al);
+  }
+}
+
+// ------------------------------------------------------------------ equal-time collision
+// I^<(t_m, t_m) = dt sum_j a_j [Sigma^>_mj G^<_jm - Sigma^<_mj G^>_jm],  G_jm = -(G_mj)^dag,
+// a_j the trapezoid weights on [0, t_m]; I^> (t_m, t_m) is the same matrix. One block per k.
+template <int NB>
+__global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ hist,
+                                                const cplx* __restrict__ sig, cplx* __restrict__ Icur,
+                                                cplx* __restrict__ Dcur, int m, double dt) {
+  constexpr int NBB = NB * NB;
+  __shared__ cplx lds[NBB * 256];
+  int k = blockIdx.x;
+  cplx acc[NBB];
+  mat_zero<NB>(acc);
+  if (m > 0) {
+    for (int j = threadIdx.x; j <= m; j += 256) {
+      double wgt = (j == 0 || j == m) ? 0.5 : 1.0;
+      cplx Gl[NBB], Gg[NBB], Sl[NBB], Sg[NBB], t[NBB];
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) {
+        Gl[e] = hist[hist_idx(d, k, e, m, j)];
+        Gg[e] = hist[hist_idx(d, k, NBB + e, m, j)];
+        Sl[e] = sig[sig_idx(d, k, 0, e, j)];
+        Sg[e] = sig[sig_idx(d, k, 1, e, j)];
+      }
+      // G_jm = -G_mj^dag:  Sg G^<_jm - Sl G^>_jm = -Sg Gl^dag + Sl Gg^dag
+      mat_zero<NB>(t);
+      mm_acc_bdag<NB>(t, Sl, Gg);
+      cplx u[NBB];
+      mat_zero<NB>(u);
+      mm_acc_bdag<NB>(u, Sg, Gl);
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) acc[e] = cadd(acc[e], cscal(csub(t[e], u[e]), wgt));
+    }
+  }
+  block_sum_cplx<NBB>(acc, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        cplx I = cscal(acc[a * NB + b], dt);
+        Icur[rowbuf_idx(d, k, a * NB + b, m)] = I;
+        Icur[rowbuf_idx(d, k, NBB + a * NB + b, m)] = I;
+        Dcur[(int64_t)k * NBB + a * NB + b] = cadd(cscal(acc[a * NB + b], dt), cconj(cscal(acc[b * NB + a], dt)));
+      }
+  }
+}
+
+// ------------------------------------------------------------------ history sums (hot loop)
+// Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
+// each with weight 1 (end-point weights are corrected in k_row):
+//   column term -> output t':  SR_j G^{<,>}_{j t'}                    (SR = Sigma^> - Sigma^<)
+//   row term    -> output j:   -Sigma^>_{t'} (G^<_{j t'})^dag + Sigma^<_{t'} (G^>_{j t'})^dag,
+//                               t' < j, shared by I^< and I^>    (G_{t' j} = -G_{j t'}^dag)
+// Block = (64-column strip s, k). Lane l owns column t' = 64 s + l and keeps its column
+// sums in registers while the 4 wavefronts walk the rows j >= 64 s (interleaved), so every
+// block of the strip is read from HBM exactly once with 1 KB-contiguous loads per
+// component plane. Each row term is reduced across the 64 lanes with shuffles and stored
+// per strip (rowpart); the 4 wavefronts' column sums are combined in LDS.
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restrict__ hist,
+                                                   const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+                                                   cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  constexpr int CH = (C < 8) ? C : 8;  // components per LDS combine round
+  __shared__ cplx red[3][CH][64];
+  int s = blockIdx.x / d.nk;  // strips with the most rows first
+  int k = blockIdx.x - s * d.nk;
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int tp = 64 * s + lane;
+  bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  cplx Sl[NBB], Sg[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) {
+    Sl[e] = colv ? sk[(0 * NBB + e) * d.Tp + tp] : czero();
+    Sg[e] = colv ? sk[(1 * NBB + e) * d.Tp + tp] : czero();
+  }
+  cplx acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = czero();
+  const cplx* hk = hist + (int64_t)k * C * d.P;
+  cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+  for (int j = 64 * s + wv; j < m; j += 4) {
+    bool v = colv && tp <= j;
+    int64_t off = row_off(j) + tp;
+    cplx G[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) G[c] = v ? hk[(int64_t)c * d.P + off] : czero();
+    cplx SR[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + j];
+    mm_acc<NB>(acc, SR, G);
+    mm_acc<NB>(acc + NBB, SR, G + NBB);
+    cplx rt[NBB];
+    mat_zero<NB>(rt);
+    if (tp < j) {
+      cplx u[NBB];
+      mat_zero<NB>(u);
+      mm_acc_bdag<NB>(rt, Sl, G + NBB);
+      mm_acc_bdag<NB>(u, Sg, G);
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) rt[e] = csub(rt[e], u[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) {
+      rt[e].x = wave_sum(rt[e].x);
+      rt[e].y = wave_sum(rt[e].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + j] = rt[e];
+    }
+  }
+  // combine the 4 wavefronts' column sums
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    if (wv > 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) red[wv - 1][c][lane] = acc[c0 + c];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        cplx a = acc[c0 + c];
+        a = cadd(a, red[0][c][lane]);
+        a = cadd(a, red[1][c][lane]);
+        a = cadd(a, red[2][c][lane]);
+        if (colv) colsum[rowbuf_idx(d, k, c0 + c, tp)] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ row assembly and update
+// Thread per (k, t'), t' <= m.
+//  EVAL/CORRECT, t' < m: I^{<,>}(t_m, t') = dt [bulk + end-point terms], where the
+//   trapezoid corrections of the two integrals of eq. (CI) are
+//     + 1/2 SR_mm G_{m t'} - 1/2 SR_m0 G_{0 t'}                                  (first, [0, t_m])
+//     + [t' > 0] (-1/2 Sigma_{m t'} GR_{t' t'} + 1/2 Sigma_{m0} GR_{0 t'})       (second, [0, t'])
+//   with GR = G^> - G^<, G_{0 t'} = -(G_{t' 0})^dag.
+//  PREDICT/CORRECT, t' < m: G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t').
+//  PREDICT/CORRECT, t' = m: rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag and the
+//   equal-time block G^< = i rho_m, G^> = -i (1 - rho_m).
+template <int NB, int MODE>
+__global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, const cplx* __restrict__ sig,
+                                             const cplx* __restrict__ colsum, const cplx* __restrict__ rowpart,
+                                             cplx* __restrict__ col0, cplx* __restrict__ diag,
+                                             const cplx* __restrict__ Iprev, cplx* __restrict__ Icur,
+                                             const cplx* __restrict__ props, const cplx* __restrict__ rho_prev,
+                                             cplx* __restrict__ rho_cur, const cplx* __restrict__ Dprev,
+                                             const cplx* __restrict__ Dcur, int m, double dt) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  int k = blockIdx.y;
+  int tp = blockIdx.x * 256 + threadIdx.x;
+  if (tp > m) return;
+  if (MODE == KBE_ROW_EVAL && tp == m) return;
+  const cplx* P = props + (int64_t)k * 3 * NBB;
+  if (tp < m) {
+    cplx In[C];
+    if (MODE != KBE_ROW_PREDICT) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) In[c] = colsum[rowbuf_idx(d, k, c, tp)];
+      cplx rs[NBB];
+      mat_zero<NB>(rs);
+      int ns = (tp >> 6) + 1;
+      for (int s = 0; s < ns; ++s) {
+        const cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], rp[(int64_t)e * d.Tp + tp]);
+      }
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) {
+        In[e] = cadd(In[e], rs[e]);
+        In[NBB + e] = cadd(In[NBB + e], rs[e]);
+      }
+      // end-point terms
+      cplx SRmm[NBB], SRm0[NBB], Gm[C], G0[C];
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) {
+        SRmm[e] = sig[sig_idx(d, k, 2, e, m)];
+        SRm0[e] = sig[sig_idx(d, k, 2, e, 0)];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) Gm[c] = hist[hist_idx(d, k, c, m, tp)];
+      if (tp == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) G0[c] = col0[rowbuf_idx(d, k, c, 0)];
+      } else {
+#pragma unroll
+        for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              G0[sc * NBB + a * NB + b] = cneg(cconj(col0[rowbuf_idx(d, k, sc * NBB + b * NB + a, tp)]));
+      }
+      cplx E[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) E[c] = czero();
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+        cplx x1[NBB], x0[NBB];
+        mat_zero<NB>(x1);
+        mat_zero<NB>(x0);
+        mm_acc<NB>(x1, SRmm, Gm + sc * NBB);
+        mm_acc<NB>(x0, SRm0, G0 + sc * NBB);
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cscal(csub(x1[e], x0[e]), 0.5);
+      }
+      if (tp > 0) {
+        cplx GRtt[NBB], GR0t[NBB];
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) {
+          GRtt[e] = csub(diag[rowbuf_idx(d, k, NBB + e, tp)], diag[rowbuf_idx(d, k, e, tp)]);
+          GR0t[e] = csub(G0[NBB + e], G0[e]);
+        }
+#pragma unroll
+        for (int sc = 0; sc < 2; ++sc) {
+          cplx St[NBB], S0[NBB], y1[NBB], y0[NBB];
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) {
+            St[e] = sig[sig_idx(d, k, sc, e, tp)];
+            S0[e] = sig[sig_idx(d, k, sc, e, 0)];
+          }
+          mat_zero<NB>(y1);
+          mat_zero<NB>(y0);
+          mm_acc<NB>(y1, St, GRtt);
+          mm_acc<NB>(y0, S0, GR0t);
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(csub(y0[e], y1[e]), 0.5));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        In[c] = cscal(cadd(In[c], E[c]), dt);
+        Icur[rowbuf_idx(d, k, c, tp)] = In[c];
+      }
+    }
+    if (MODE != KBE_ROW_EVAL) {
+      cplx Ib[C], Go[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        cplx ip = Iprev[rowbuf_idx(d, k, c, tp)];
+        Ib[c] = (MODE == KBE_ROW_PREDICT) ? ip : cscal(cadd(ip, In[c]), 0.5);
+        Go[c] = hist[hist_idx(d, k, c, m - 1, tp)];
+      }
+      cplx V[NBB], Phi[NBB];
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) {
+        V[e] = P[e];
+        Phi[e] = P[2 * NBB + e];
+      }
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+        cplx g[NBB];
+        mat_zero<NB>(g);
+        mm_acc<NB>(g, V, Go + sc * NBB);
+        mm_acc<NB>(g, Phi, Ib + sc * NBB);
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) {
+          hist[hist_idx(d, k, sc * NBB + e, m, tp)] = g[e];
+          if (tp == 0) col0[rowbuf_idx(d, k, sc * NBB + e, m)] = g[e];
+        }
+      }
+    }
+  } else {
+    // tp == m, PREDICT or CORRECT: density matrix and equal-time block
+    cplx V[NBB], Vh[NBB], r0[NBB], Db[NBB], t1[NBB], rho[NBB], t2[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) {
+      V[e] = P[e];
+      Vh[e] = P[NBB + e];
+      r0[e] = rho_prev[(int64_t)k * NBB + e];
+      cplx dp = Dprev[(int64_t)k * NBB + e];
+      Db[e] = (MODE == KBE_ROW_PREDICT) ? dp : cscal(cadd(dp, Dcur[(int64_t)k * NBB + e]), 0.5);
+    }
+    mat_zero<NB>(t1);
+    mm_acc<NB>(t1, V, r0);
+    mat_zero<NB>(rho);
+    mm_acc_bdag<NB>(rho, t1, V);
+    mat_zero<NB>(t1);
+    mm_acc<NB>(t1, Vh, Db);
+    mat_zero<NB>(t2);
+    mm_acc_bdag<NB>(t2, t1, Vh);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        int e = a * NB + b;
+        cplx rv = csub(rho[e], cscal(t2[e], dt));
+        rho_cur[(int64_t)k * NBB + e] = rv;
+        cplx gl = cmuli(rv);
+        cplx gg = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
+        hist[hist_idx(d, k, e, m, m)] = gl;
+        hist[hist_idx(d, k, NBB + e, m, m)] = gg;
+        diag[rowbuf_idx(d, k, e, m)] = gl;
+        diag[rowbuf_idx(d, k, NBB + e, m)] = gg;
+      }
+  }
+}
+
+// ------------------------------------------------------------------ observables
+template <int NB>
+__global__ __launch_bounds__(256) void k_obs(Dims d, const cplx* __restrict__ hop, const cplx* __restrict__ rho,
+                                             const cplx* __restrict__ Icur, int m, double t, double A,
+                                             double Ax, double Ay, int interaction, int hf, double U,
+                                             double spin, double* __restrict__ obs) {
+  constexpr int NBB = NB * NB;
+  constexpr int NV = 6 + 2 * NB;  // N, Ekin, Ehf, Ecorr, Jx, Jy, n_orb[NB], n_band[NB]
+  __shared__ double red[NV][256];
+  __shared__ cplx loc_s[NBB];
+  int tid = threadIdx.x;
+  // local density matrix for the mean field
+  {
+    __shared__ cplx lds[NBB * 256];
+    cplx loc[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) loc[e] = czero();
+    for (int k = tid; k < d.nk; k += 256)
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) loc[e] = cadd(loc[e], rho[(int64_t)k * NBB + e]);
+    block_sum_cplx<NBB>(loc, lds);
+    if (tid == 0)
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) loc_s[e] = cscal(loc[e], 1.0 / d.nk);
+    __syncthreads();
+  }
+  cplx hfm[NBB], ob[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) {
+    hfm[e] = czero();
+    ob[e] = czero();
+  }
+  if (interaction == KBE_DEV_INT_HUBBARD) {
+    if (hf)
+#pragma unroll
+      for (int a = 0; a < NB; ++a) hfm[a * NB + a] = cmk(U * loc_s[a * NB + a].x, 0.0);
+  } else {
+    if constexpr (NB == 2) {
+      ob[3] = cmk(-U, 0.0);
+      if (hf) {
+        hfm[0] = cmk(U * loc_s[3].x, 0.0);
+        hfm[3] = cmk(U * loc_s[0].x, 0.0);
+        hfm[1] = cscal(loc_s[1], -U);
+        hfm[2] = cscal(loc_s[2], -U);
+      }
+    }
+  }
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int k = tid; k < d.nk; k += 256) {
+    cplx r[NBB], h[NBB], v[NBB], Vv[NBB];
+    double w[NB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) r[e] = rho[(int64_t)k * NBB + e];
+    bloch_h0<NB>(hop, d.nkx, d.nky, k, Ax, Ay, h);
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      acc[0] += r[a * NB + a].x;
+      acc[6 + a] += r[a * NB + a].x;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[1] += cmul(cadd(h[a * NB + b], ob[a * NB + b]), r[b * NB + a]).x;
+        acc[2] += cmul(hfm[a * NB + b], r[b * NB + a]).x;
+      }
+      acc[3] += 0.5 * Icur[rowbuf_idx(d, k, a * NB + a, m)].y;  // Re(-i/2 I) = Im(I)/2
+    }
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      bloch_vel<NB>(hop, d.nkx, d.nky, k, Ax, Ay, dir, v);
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[4 + dir] += cmul(v[a * NB + b], r[b * NB + a]).x;
+    }
+    jacobi_eigh<NB>(h, w, Vv);
+#pragma unroll
+    for (int bnd = 0; bnd < NB; ++bnd) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          sacc += cmul(cmul(cconj(Vv[a * NB + bnd]), r[a * NB + b]), Vv[b * NB + bnd]).x;
+      acc[6 + NB + bnd] += sacc;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) red[i][tid] = acc[i];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[i][tid] += red[i][tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double inv = 1.0 / d.nk;
+    double* o = obs + (int64_t)m * KBE_DEV_NOBS;
+    for (int i = 0; i < KBE_DEV_NOBS; ++i) o[i] = 0.0;
+    o[0] = t;
+    o[1] = spin * red[0][0] * inv;
+    o[2] = spin * red[1][0] * inv;
+    o[3] = 0.5 * spin * red[2][0] * inv;
+    o[4] = spin * red[3][0] * inv;
+    o[5] = o[2] + o[3] + o[4];
+    o[6] = spin * red[4][0] * inv;
+    o[7] = spin * red[5][0] * inv;
+    o[8] = A;
+    for (int a = 0; a < NB; ++a) o[9 + a] = red[6 + a][0] * inv;
+    for (int b = 0; b < NB; ++b) o[13 + b] = red[6 + NB + b][0] * inv;
+  }
+}
+
+// ------------------------------------------------------------------ aux copies
+template <int NB>
+__global__ void k_aux(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ col0, cplx* __restrict__ diag,
+                      int m) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int kc = blockIdx.y;
+  if (j > m) return;
+  int k = kc / d.C, c = kc - (kc / d.C) * d.C;
+  col0[rowbuf_idx(d, k, c, j)] = hist[hist_idx(d, k, c, j, 0)];
+  diag[rowbuf_idx(d, k, c, j)] = hist[hist_idx(d, k, c, j, j)];
+}
+
+// ------------------------------------------------------------------ launchers
+template <int NB>
+struct Launch {
+  static hipError_t init(const Dims& d, const LaunchArgs& a, hipStream_t st) {
+    int nb64 = (d.nk + 63) / 64;
+    hipLaunchKernelGGL(k_init_eig<NB>, dim3(nb64), dim3(64), 0, st, d, a.hop, a.Ax, a.Ay, a.eig_w, a.eig_U);
+    hipLaunchKernelGGL(k_init_mu, dim3(1), dim3(256), 0, st, d.nk * NB, (const double*)a.eig_w, a.temp,
+                       a.target, a.mu);
+    hipLaunchKernelGGL(k_init_rho<NB>, dim3(nb64), dim3(64), 0, st, d, (const double*)a.eig_w,
+                       (const cplx*)a.eig_U, (const double*)a.mu, a.temp, a.rho_prev, a.rho_cur, a.hist,
+                       a.col0, a.diag);
+    return hipGetLastError();
+  }
+  static hipError_t hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t st) {
+    hipLaunchKernelGGL(k_hf<NB>, dim3(1), dim3(256), 0, st, d, (const cplx*)a.rho_prev, (const cplx*)a.rho_cur,
+                       wb, a.interaction, a.hf, a.U, a.hfbuf);
+    return hipGetLastError();
+  }
+  static hipError_t props(const Dims& d, const LaunchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_props<NB>, dim3((d.nk + 3) / 4), dim3(256), 0, st, d, a.hop, (const cplx*)a.hfbuf,
+                       a.Ax, a.Ay, a.dt, a.props);
+    return hipGetLastError();
+  }
+  static hipError_t sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+    int total = (m + 1) * NB * NB;
+    int per = (total + 7) / 8;
+    size_t shm = (size_t)(4 * d.nk + d.nkx + d.nky) * sizeof(cplx);
+    hipLaunchKernelGGL(k_sigma<NB>, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.hist, a.sig, m, a.UU,
+                       a.corr);
+    return hipGetLastError();
+  }
+  static hipError_t diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.hist, (const cplx*)a.sig,
+                       a.I_cur, a.D_cur, m, a.dt);
+    return hipGetLastError();
+  }
+  static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+    if (m < 1) return hipSuccess;
+    int ns = (m + 63) / 64;
+    hipLaunchKernelGGL(k_hist_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                       (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    return hipGetLastError();
+  }
+  static hipError_t row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
+    dim3 grid((m + 1 + 255) / 256, d.nk);
+#define KBE_ROW_ARGS                                                                                      \
+  d, a.hist, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag,          \
+      (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
+      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt
+    if (mode == KBE_ROW_PREDICT)
+      hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+    else if (mode == KBE_ROW_CORRECT)
+      hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+    else
+      hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+#undef KBE_ROW_ARGS
+    return hipGetLastError();
+  }
+  static hipError_t obs(const Dims& d, const LaunchArgs& a, int m, double t, double A, hipStream_t st) {
+    hipLaunchKernelGGL(k_obs<NB>, dim3(1), dim3(256), 0, st, d, a.hop, (const cplx*)a.rho_cur,
+                       (const cplx*)a.I_cur, m, t, A, a.Ax, a.Ay, a.interaction, a.hf, a.U, a.spin, a.obs);
+    return hipGetLastError();
+  }
+  static hipError_t aux(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+    dim3 grid((m + 1 + 255) / 256, d.nk * d.C);
+    hipLaunchKernelGGL(k_aux<NB>, grid, dim3(256), 0, st, d, (const cplx*)a.hist, a.col0, a.diag, m);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+#define KBE_DISPATCH(NBV, CALL)                     \
+  switch (NBV) {                                    \
+    case 1: return Launch<1>::CALL;                 \
+    case 2: return Launch<2>::CALL;                 \
+    case 3: return Launch<3>::CALL;                 \
+    case 4: return Launch<4>::CALL;                 \
+    default: return hipErrorInvalidValue;           \
+  }
+
+hipError_t launch_init(const Dims& d, const LaunchArgs& a, hipStream_t st) { KBE_DISPATCH(d.nb, init(d, a, st)); }
+hipError_t launch_hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t st) {
+  KBE_DISPATCH(d.nb, hf(d, a, wb, st));
+}
+hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st) { KBE_DISPATCH(d.nb, props(d, a, st)); }
+hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  KBE_DISPATCH(d.nb, sigma(d, a, m, st));
+}
+hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  KBE_DISPATCH(d.nb, diag_I(d, a, m, st));
+}
+hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  KBE_DISPATCH(d.nb, bulk(d, a, m, st));
+}
+hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
+  KBE_DISPATCH(d.nb, row(d, a, m, mode, st));
+}
+hipError_t launch_obs(const Dims& d, const LaunchArgs& a, int m, double t, double A, hipStream_t st) {
+  KBE_DISPATCH(d.nb, obs(d, a, m, t, A, st));
+}
+hipError_t launch_aux(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  KBE_DISPATCH(d.nb, aux(d, a, m, st));
+}
+
+}  // namespace kbe

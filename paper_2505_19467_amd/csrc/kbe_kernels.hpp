@@ -1,0 +1,56 @@
+// Host-side launch interface of the gfx950 Kadanoff-Baym kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kbe_device.hpp"
+
+#define KBE_DEV_INT_HUBBARD 0
+#define KBE_DEV_INT_INTERBAND 1
+#define KBE_DEV_NOBS 17
+
+#define KBE_ROW_PREDICT 0
+#define KBE_ROW_CORRECT 1
+#define KBE_ROW_EVAL 2
+
+namespace kbe {
+
+// Device pointers and scalars a launch needs (the roles *_prev / *_cur are resolved by
+// the caller for the current step).
+struct LaunchArgs {
+  cplx* hist;
+  cplx* sig;
+  cplx* I_prev;
+  cplx* I_cur;
+  cplx* col0;
+  cplx* diag;
+  cplx* colsum;
+  cplx* rowpart;
+  cplx* rho_prev;
+  cplx* rho_cur;
+  cplx* D_prev;
+  cplx* D_cur;
+  cplx* props;
+  cplx* hfbuf;
+  cplx* hop;
+  double* eig_w;
+  cplx* eig_U;
+  double* mu;
+  double* obs;
+  double Ax, Ay;  // A(t) * pol for the launch at hand
+  double dt, U, UU, temp, target, spin;
+  int interaction, hf, corr;
+};
+
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t st);
+hipError_t launch_init(const Dims& d, const LaunchArgs& a, hipStream_t st);
+hipError_t launch_hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t st);
+hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st);
+hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st);
+hipError_t launch_obs(const Dims& d, const LaunchArgs& a, int m, double t, double A, hipStream_t st);
+hipError_t launch_aux(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+
+}  // namespace kbe

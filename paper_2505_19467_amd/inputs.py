@@ -173,3 +173,14 @@ def random_history(nk: int, nb: int, m: int, seed: int, scale: float = 0.3):
 def random_hermitian(n: int, count: int, seed: int, scale: float = 1.0) -> np.ndarray:
     z = random_complex((count, n, n), seed, scale)
     return 0.5 * (z + np.conj(np.swapaxes(z, -1, -2)))
+
+
+def fill_normal_(tensor, seed: int, scale: float = 1.0):
+    """Fill a (real or complex) torch tensor in place with seeded standard-normal numbers,
+    on the tensor's own device (torch's generator; used for full-size synthetic histories)."""
+    import torch
+    g = torch.Generator(device=tensor.device)
+    g.manual_seed(seed)
+    view = torch.view_as_real(tensor) if tensor.is_complex() else tensor
+    view.normal_(0.0, scale, generator=g)
+    return tensor

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of the gfx950 Kadanoff-Baym library (``libkbe.so``, include/kbe.h).
+
+Argument marshalling only: torch provides device memory and the stream; every step of
+the propagation runs in the library's HIP kernels. Importing this module raises if the
+library has not been built; nothing here falls back to a CPU implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import inputs as _inputs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkbe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_19467_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+KBE_OK = 0
+ERRORS = {-1: "KBE_ERR_INVALID_ARG", -2: "KBE_ERR_SHAPE", -3: "KBE_ERR_HIP", -4: "KBE_ERR_STATE",
+          -5: "KBE_ERR_NONFINITE", -6: "KBE_ERR_NOT_CONVERGED"}
+NOBS = 17
+OBS_NAMES = ["t", "N", "Ekin", "EHF", "Ecorr", "Etot", "Jx", "Jy", "A",
+             "n_orb0", "n_orb1", "n_orb2", "n_orb3", "n_band0", "n_band1", "n_band2", "n_band3"]
+OBS = {n: i for i, n in enumerate(OBS_NAMES)}
+
+BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_CUR, BUF_PROP, \
+    BUF_COL0, BUF_DIAG = range(10)
+
+
+class KbeConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision")] + \
+               [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling")]
+
+
+class KbePulse(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("omega", ctypes.c_double), ("t0", ctypes.c_double),
+                ("width", ctypes.c_double), ("pol", ctypes.c_double * 2)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_lib.kbe_workspace_query.argtypes = [ctypes.POINTER(KbeConfig), _szp, _szp, _szp]
+_lib.kbe_create.argtypes = [ctypes.POINTER(KbeConfig), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(KbePulse),
+                            _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+_lib.kbe_step.argtypes = [_vp, _i32]
+_lib.kbe_current_step.argtypes = [_vp]
+_lib.kbe_current_step.restype = _i32
+_lib.kbe_observables.argtypes = [_vp, _i32, _i32, ctypes.POINTER(ctypes.c_double)]
+_lib.kbe_destroy.argtypes = [_vp]
+_lib.kbe_destroy.restype = None
+_lib.kbe_last_error.argtypes = [_vp]
+_lib.kbe_last_error.restype = ctypes.c_char_p
+_lib.kbe_buffer.argtypes = [_vp, _i32, ctypes.POINTER(_vp), _szp]
+for _n in ("kbe_stage_propagators", "kbe_stage_update"):
+    getattr(_lib, _n).argtypes = [_vp, _i32, _i32]
+for _n in ("kbe_stage_sigma", "kbe_stage_collision", "kbe_stage_observables", "kbe_stage_commit",
+           "kbe_rebuild_aux", "kbe_timing"):
+    getattr(_lib, _n).argtypes = [_vp, _i32]
+_lib.kbe_timing_query.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+
+EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_observables",
+           "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma",
+           "kbe_stage_collision", "kbe_stage_update", "kbe_stage_observables", "kbe_stage_commit",
+           "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query"]
+
+
+class KbeError(RuntimeError):
+    pass
+
+
+def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
+    return KbeConfig(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg, interaction=cfg.interaction,
+                     hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
+                     nt_max=cfg.nt if nt_max is None else nt_max, precision=cfg.precision,
+                     dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
+
+
+def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
+    c = _c_config(cfg, nt_max)
+    h, w, o = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    rc = _lib.kbe_workspace_query(ctypes.byref(c), ctypes.byref(h), ctypes.byref(w), ctypes.byref(o))
+    if rc != KBE_OK:
+        raise KbeError(f"kbe_workspace_query: {ERRORS.get(rc, rc)}")
+    return h.value, w.value, o.value
+
+
+def row_off(j: int) -> int:
+    """Start of row j inside a (k, component) plane of the packed history (include/kbe.h)."""
+    Q, r = j >> 3, j & 7
+    return 32 * Q * (Q + 1) + 8 * r * (Q + 1)
+
+
+class System:
+    """One propagation context: caller-owned (torch) device buffers + the library context."""
+
+    def __init__(self, cfg: _inputs.Config, nt_max: int | None = None, device: str = "cuda",
+                 stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.nt_max = cfg.nt if nt_max is None else nt_max
+        hb, wb, ob = workspace_query(cfg, self.nt_max)
+        dev = torch.device(device)
+        self.history = torch.empty(hb // 16, dtype=torch.complex128, device=dev)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=dev)
+        self.obs = torch.empty(ob // 8, dtype=torch.float64, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.nk, self.nb = cfg.nk, cfg.nb
+        self.C = 2 * cfg.nb * cfg.nb
+        self.P = row_off(self.nt_max + 1)
+        self.Tp = ((self.nt_max + 1 + 7) // 8) * 8
+        self._ctx = None
+        self._create()
+
+    def _create(self):
+        cfg = self.cfg
+        c = _c_config(cfg, self.nt_max)
+        hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
+        pu = cfg.pulse
+        p = KbePulse(amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
+                     pol=(ctypes.c_double * 2)(pu.pol[0], pu.pol[1]))
+        ctx = _vp()
+        rc = _lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(p),
+                             _vp(self.history.data_ptr()), _vp(self.workspace.data_ptr()), _vp(self.obs.data_ptr()),
+                             _vp(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != KBE_OK:
+            raise KbeError(f"kbe_create: {ERRORS.get(rc, rc)}")
+        self._ctx = ctx
+
+    def reset(self):
+        """Re-create the library context on the same device buffers (back to t = 0)."""
+        self.close()
+        self._create()
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.kbe_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != KBE_OK:
+            msg = _lib.kbe_last_error(self._ctx).decode()
+            raise KbeError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+    # ------------------------------------------------------------------ propagation
+    def step(self, n: int = 1):
+        self._check(_lib.kbe_step(self._ctx, n), "kbe_step")
+
+    @property
+    def current_step(self) -> int:
+        return int(_lib.kbe_current_step(self._ctx))
+
+    def observables(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = self.current_step + 1 - first
+        out = np.zeros((count, NOBS))
+        self._check(_lib.kbe_observables(self._ctx, first, count, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "kbe_observables")
+        return out
+
+    # ------------------------------------------------------------------ stages
+    def stage_propagators(self, m, mode):
+        self._check(_lib.kbe_stage_propagators(self._ctx, m, mode), "kbe_stage_propagators")
+
+    def stage_sigma(self, m):
+        self._check(_lib.kbe_stage_sigma(self._ctx, m), "kbe_stage_sigma")
+
+    def stage_collision(self, m):
+        self._check(_lib.kbe_stage_collision(self._ctx, m), "kbe_stage_collision")
+
+    def stage_update(self, m, mode):
+        self._check(_lib.kbe_stage_update(self._ctx, m, mode), "kbe_stage_update")
+
+    def stage_observables(self, m):
+        self._check(_lib.kbe_stage_observables(self._ctx, m), "kbe_stage_observables")
+
+    def stage_commit(self, m):
+        self._check(_lib.kbe_stage_commit(self._ctx, m), "kbe_stage_commit")
+
+    def rebuild_aux(self, m):
+        self._check(_lib.kbe_rebuild_aux(self._ctx, m), "kbe_rebuild_aux")
+
+    # ------------------------------------------------------------------ buffers
+    def buffer(self, which: int) -> torch.Tensor:
+        """complex128 view of a workspace sub-buffer (current role)."""
+        ptr, nbytes = _vp(), ctypes.c_size_t()
+        self._check(_lib.kbe_buffer(self._ctx, which, ctypes.byref(ptr), ctypes.byref(nbytes)), "kbe_buffer")
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off:off + nbytes.value].view(torch.complex128)
+
+    def history_planes(self) -> torch.Tensor:
+        """History as [k][component][P] complex128 (component c = s*nb^2 + a*nb + b)."""
+        return self.history.view(self.nk, self.C, self.P)
+
+    def history_row(self, j: int) -> torch.Tensor:
+        """Row j as a [t'][k][</>][a][b] tensor (copy)."""
+        nb = self.nb
+        h = self.history_planes()[:, :, row_off(j):row_off(j) + j + 1]   # [k][c][t']
+        return h.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
+
+    def set_history_row(self, j: int, row: torch.Tensor):
+        """Write row j from a [t'][k][</>][a][b] tensor."""
+        nb = self.nb
+        src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0)
+        self.history_planes()[:, :, row_off(j):row_off(j) + j + 1].copy_(src)
+
+    def rowbuf(self, which: int) -> torch.Tensor:
+        """A [k][C][Tp] row buffer (I rows, COL0, DIAG) as a [t'][k][</>][a][b] view helper."""
+        return self.buffer(which).view(self.nk, self.C, self.Tp)
+
+    def sigma_planes(self) -> torch.Tensor:
+        """Sigma row buffer as [k][3][nb^2][Tp]: Sigma^<, Sigma^>, Sigma^> - Sigma^<."""
+        return self.buffer(BUF_SIGMA).view(self.nk, 3, self.nb * self.nb, self.Tp)
+
+    def sigma_row(self, m: int) -> torch.Tensor:
+        """Sigma row of t_m as [j][k][</>][a][b] (copy)."""
+        nb = self.nb
+        s = self.buffer(BUF_SIGMA).view(self.nk, 3, nb * nb, self.Tp)[:, :2, :, :m + 1]
+        return s.permute(3, 0, 1, 2).reshape(m + 1, self.nk, 2, nb, nb).contiguous()
+
+    def collision_row(self, m: int, which: int = BUF_I_CUR) -> torch.Tensor:
+        nb = self.nb
+        r = self.rowbuf(which)[:, :, :m + 1]
+        return r.permute(2, 0, 1).reshape(m + 1, self.nk, 2, nb, nb).contiguous()
+
+    def rho(self, which: int = BUF_RHO_CUR) -> torch.Tensor:
+        return self.buffer(which).view(self.nk, self.nb, self.nb)
+
+    # ------------------------------------------------------------------ timing
+    def timing(self, enable: bool):
+        self._check(_lib.kbe_timing(self._ctx, 1 if enable else 0), "kbe_timing")
+
+    def timing_query(self):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.kbe_timing_query(self._ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+                    "kbe_timing_query")
+        return n.value, ms.value, by.value

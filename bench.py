@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=60, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run one device-to-device copy of GIB GiB (to scale HBM byte counters) and exit")
     args = ap.parse_args()
@@ -91,29 +92,57 @@ def main():
     print(f"[bench] workload {cfg.name}: nk={cfg.nk} nb={cfg.nb} nt={cfg.nt} dt={cfg.dt} K={cfg.n_corr}; "
           f"timing {K} steps after {W} warm-up steps", file=sys.stderr, flush=True)
 
-    S = kbe.System(cfg)
-    hist_gb = S.history.numel() * 16 / 1e9
-    if W:
-        S.step(W)
-        S.observables()
-    S.reset()   # fresh context on the same buffers: t = 0 again
-    S.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.step(K)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    launches, kms, kbytes = S.timing_query()
-    obs = S.observables(0, K + 1)
+    def run(c):
+        S = kbe.System(c)
+        gb = S.history.numel() * S.history.element_size() / 1e9
+        if W:
+            S.step(W)
+            S.observables()
+        S.reset()   # fresh context on the same buffers: t = 0 again
+        S.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(K)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        launches, kms, kbytes = S.timing_query()
+        obs = S.observables(0, K + 1)
+        return S, dict(elapsed=el, launches=launches, kms=kms, kbytes=kbytes, obs=obs, hist_gb=gb)
 
+    S, r64 = run(cfg)
+    elapsed, obs, hist_gb = r64["elapsed"], r64["obs"], r64["hist_gb"]
+    launches, kms, kbytes = r64["launches"], r64["kms"], r64["kbytes"]
     steps_per_s = K / elapsed
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     n_drift = float(np.abs(obs[:, 1] - obs[0, 1]).max())
     e_bal = float(np.abs(_energy_balance(obs, cfg)).max())
     finite = bool(np.isfinite(obs).all())
-    print(f"[bench] {K} steps in {elapsed:.3f} s = {steps_per_s:.1f} steps/s; history sums: {launches} launches, "
+    print(f"[bench] FP64: {K} steps in {elapsed:.3f} s = {steps_per_s:.1f} steps/s; history sums: {launches} launches, "
           f"{kms:.1f} ms, {kbytes / 1e12:.3f} TB algorithmic -> {achieved:.0f} GB/s; "
           f"N drift {n_drift:.1e}, energy balance {e_bal:.1e}", file=sys.stderr, flush=True)
+
+    fp32 = None
+    if not args.no_fp32:
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        c32 = cfg.replace(precision=inputs.PRECISION_FP32)
+        S, r32 = run(c32)
+        o32 = r32["obs"]
+        names = {"n_band1": 14, "n_band0": 13, "n_orb0": 9, "n_orb1": 10, "Jx": 6, "Etot": 5, "N": 1}
+        err = {n: float(np.abs(o32[:, i] - obs[:, i]).max() / np.abs(obs[:, i]).max()) for n, i in names.items()}
+        ach32 = r32["kbytes"] / (r32["kms"] * 1e-3) / 1e9 if r32["kms"] > 0 else None
+        fp32 = {"value": K / r32["elapsed"], "unit": "steps/s", "speedup_vs_fp64": elapsed / r32["elapsed"],
+                "history_sums_GBs": ach32, "history_sums_frac": ach32 / HBM_PEAK_GBS if ach32 else None,
+                "history_GB": round(r32["hist_gb"], 2),
+                "max_rel_err_vs_fp64": err, "workload": f"{c32.name}: history stored and summed in FP32"}
+        print(f"[bench] FP32 form: {K} steps in {r32['elapsed']:.3f} s = {K / r32['elapsed']:.1f} steps/s "
+              f"({elapsed / r32['elapsed']:.2f}x); history sums {ach32:.0f} GB/s; max rel err vs FP64 "
+              f"{max(err.values()):.1e}", file=sys.stderr, flush=True)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        S = kbe.System(cfg)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -154,6 +183,7 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
                      "kernel": "k_hist_bulk", "launches": launches, "kernel_ms": kms},
         "cpu_baseline": cpu,
+        "fp32_form": fp32,
         "checks": {"N_drift": n_drift, "energy_balance_max": e_bal, "finite": finite},
     }
     print(json.dumps(line), flush=True)

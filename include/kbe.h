@@ -81,7 +81,7 @@ typedef struct {
   int32_t corr;         /* 1: include the second-Born correlation self-energy */
   int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes */
   int32_t nt_max;       /* largest step index the buffers hold */
-  int32_t precision;    /* KBE_FP64 (KBE_FP32 reserved for the split-precision form) */
+  int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
   double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
 } kbe_config;
 
@@ -99,6 +99,11 @@ typedef struct kbe_ctx kbe_ctx;
  *               elem(k, c, j, t') = (k * C + c) * P + rowoff(j) + t'
  *             C = 2 nb^2, c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>),
  *             rowoff(j) = 32 Q (Q+1) + 8 r (Q+1) with Q = j / 8, r = j % 8, P = rowoff(nt_max + 1).
+ *             KBE_FP32: complex64 elements, rows padded to 16 elements:
+ *             rowoff(j) = 128 Q (Q+1) + 16 r (Q+1) with Q = j / 16, r = j % 16. In this form the
+ *             history sums read the FP32 history and compute in FP32 (FP32 accumulation over
+ *             tiles of 16 rows, FP64 across tiles and strips); rows m-1 and m, the end-point
+ *             terms, the update, the density matrix and the observables stay FP64.
  *   workspace: the per-step rows (self-energy row, collision rows, density matrices,
  *             propagators, partial sums); sub-buffers are located with kbe_buffer.
  *   obs     : (nt_max + 1) x KBE_NOBS doubles, row m written when step m completes.
@@ -154,7 +159,8 @@ enum {
   KBE_BUF_PROP = 7,     /* [k][3][nb^2]: V = e^{-i hbar dt}, Vh = e^{-i hbar dt/2}, Phi = (V-1) hbar^{-1} */
   KBE_BUF_COL0 = 8,     /* [k][C][Tp]: G(t_j, t_0) copy of history column 0 */
   KBE_BUF_DIAG = 9,     /* [k][C][Tp]: G(t_j, t_j) copy of the history diagonal */
-  KBE_NBUF = 10
+  KBE_BUF_ROWS = 10,    /* [2][k][C][Tp]: FP64 copies of history rows m-1 and m, slot = row & 1 */
+  KBE_NBUF = 11
 };
 /* Tp = 8 * ceil((nt_max + 1) / 8). Current device pointer and size of a sub-buffer (the
  * _PREV/_CUR roles swap at every completed step). */
@@ -186,8 +192,8 @@ int kbe_stage_observables(kbe_ctx* ctx, int32_t m);
  * its evaluation pass. */
 int kbe_stage_commit(kbe_ctx* ctx, int32_t m);
 
-/* Refresh the COL0 and DIAG copies from history rows 0..m (after the caller wrote
- * history rows directly). */
+/* Refresh the FP64 working copies (COL0, DIAG, ROWS for rows m-1 and m) from history rows
+ * 0..m (after the caller wrote history rows directly). */
 int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m);
 
 /* Per-launch timing of the history-sum kernel with HIP events on the context's stream.

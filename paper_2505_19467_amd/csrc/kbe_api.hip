@@ -20,7 +20,7 @@ namespace {
 
 enum {
   B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
-  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_COUNT
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_COUNT
 };
 
 struct Layout {
@@ -46,7 +46,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
     *why = "only the Hubbard interaction preset is implemented on the GPU";
     return KBE_ERR_SHAPE;
   }
-  if (c->precision != KBE_FP64) { *why = "only the FP64 form is implemented"; return KBE_ERR_SHAPE; }
+  if (c->precision != KBE_FP64 && c->precision != KBE_FP32) { *why = "precision must be KBE_FP64 or KBE_FP32"; return KBE_ERR_INVALID_ARG; }
   if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
   if (!(c->dt > 0.0) || !(c->temp > 0.0) || !std::isfinite(c->U) || c->spin_deg < 1 || c->spin_deg > 2) {
     *why = "dt and temp must be positive, U finite, spin_deg 1 or 2";
@@ -61,7 +61,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.C = 2 * d.nbb;
   d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
   d.Smax = (c->nt_max + 63) / 64;
-  d.P = kbe::row_off((int64_t)c->nt_max + 1);
+  d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
+  d.P = d.fp32 ? kbe::row_off16((int64_t)c->nt_max + 1) : kbe::row_off((int64_t)c->nt_max + 1);
   const size_t cz = sizeof(cplx);
   size_t nk = d.nk;
   size_t sz[B_COUNT];
@@ -76,6 +77,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_EIGW] = nk * d.nb * sizeof(double);
   sz[B_EIGU] = nk * d.nbb * cz;
   sz[B_MU] = sizeof(double);
+  sz[B_ROW64] = 2 * nk * d.C * d.Tp * cz;
   size_t off = 0;
   for (int i = 0; i < B_COUNT; ++i) {
     L->off[i] = off;
@@ -83,7 +85,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
     off += (sz[i] + 255) / 256 * 256;
   }
   L->ws_bytes = off;
-  L->hist_bytes = (size_t)nk * d.C * (size_t)d.P * cz;
+  L->hist_bytes = (size_t)nk * d.C * (size_t)d.P * (d.fp32 ? sizeof(float2) : cz);
   L->obs_bytes = (size_t)(c->nt_max + 1) * KBE_NOBS * sizeof(double);
   return KBE_OK;
 }
@@ -102,7 +104,7 @@ struct kbe_ctx {
   Layout L;
   hipStream_t st;
   char* ws;
-  cplx* hist;
+  void* hist;
   double* obs;
   int cur;   // slot holding the *_prev role
   int step;  // last completed step
@@ -120,6 +122,7 @@ struct kbe_ctx {
   LaunchArgs args() const {
     LaunchArgs a;
     a.hist = hist;
+    a.row64 = buf<cplx>(B_ROW64);
     a.sig = buf<cplx>(B_SIGMA);
     a.I_prev = buf<cplx>(cur == 0 ? B_IA : B_IB);
     a.I_cur = buf<cplx>(cur == 0 ? B_IB : B_IA);
@@ -253,7 +256,7 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   }
   c->st = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
-  c->hist = (cplx*)d_history;
+  c->hist = d_history;
   c->obs = (double*)d_obs;
   c->cur = 0;
   c->step = 0;
@@ -336,6 +339,7 @@ int kbe_buffer(const kbe_ctx* ctx, int32_t which, void** ptr, size_t* bytes) {
     case KBE_BUF_PROP: b = B_PROP; break;
     case KBE_BUF_COL0: b = B_COL0; break;
     case KBE_BUF_DIAG: b = B_DIAG; break;
+    case KBE_BUF_ROWS: b = B_ROW64; break;
     default: return KBE_ERR_INVALID_ARG;
   }
   *ptr = ctx->ws + ctx->L.off[b];
@@ -424,7 +428,7 @@ int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* 
     if (rc) return rc;
     ms_sum += ms;
     double m = ctx->ev_m[i];
-    bytes += 0.5 * m * (m + 1.0) * d.nk * d.C * sizeof(cplx);
+    bytes += 0.5 * m * (m + 1.0) * d.nk * d.C * (d.fp32 ? sizeof(float2) : sizeof(cplx));
   }
   if (launches) *launches = (int64_t)ctx->ev_m.size();
   if (total_ms) *total_ms = ms_sum;

@@ -72,18 +72,37 @@ __host__ __device__ __forceinline__ int64_t row_off(int64_t j) {
   int64_t Q = j >> 3, r = j & 7;
   return 32 * Q * (Q + 1) + 8 * r * (Q + 1);
 }
+// The FP32 history pads rows to 16 elements (also 128 B):
+//   rowoff16(j) = 128 Q (Q+1) + 16 r (Q+1),  Q = j/16, r = j%16.
+__host__ __device__ __forceinline__ int64_t row_off16(int64_t j) {
+  int64_t Q = j >> 4, r = j & 15;
+  return 128 * Q * (Q + 1) + 16 * r * (Q + 1);
+}
+template <typename T>
+__host__ __device__ __forceinline__ int64_t row_off_t(int64_t j) {
+  if constexpr (sizeof(T) == 8) return row_off(j);
+  else return row_off16(j);
+}
 
 struct Dims {
   int nkx, nky, nk, nb;
   int nbb, C;      // nb^2, 2 nb^2 complex components per two-time block
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
-  int64_t P;       // padded length of one (k, component) plane of the history
+  int fp32;        // 1: the packed history is stored in FP32 (complex64)
+  int64_t P;       // padded length of one (k, component) plane of the history (elements)
 };
 
 // Element index helpers (complex units).
 __host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
   return ((int64_t)k * d.C + c) * d.P + row_off(j) + tp;
+}
+__host__ __device__ __forceinline__ int64_t hist32_idx(const Dims& d, int k, int c, int j, int tp) {
+  return ((int64_t)k * d.C + c) * d.P + row_off16(j) + tp;
+}
+// FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
+__host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {
+  return (((int64_t)(row & 1) * d.nk + k) * d.C + c) * d.Tp + t;
 }
 __host__ __device__ __forceinline__ int64_t rowbuf_idx(const Dims& d, int k, int c, int t) {
   return ((int64_t)k * d.C + c) * d.Tp + t;

@@ -48,6 +48,21 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
+// Write one element of the packed history in its storage precision.
+__device__ __forceinline__ void commit_store(const Dims& d, void* hist, int k, int c, int j, int tp, cplx v) {
+  if (d.fp32)
+    reinterpret_cast<float2*>(hist)[hist32_idx(d, k, c, j, tp)] = make_float2((float)v.x, (float)v.y);
+  else
+    reinterpret_cast<cplx*>(hist)[hist_idx(d, k, c, j, tp)] = v;
+}
+__device__ __forceinline__ cplx history_load(const Dims& d, const void* hist, int k, int c, int j, int tp) {
+  if (d.fp32) {
+    float2 v = reinterpret_cast<const float2*>(hist)[hist32_idx(d, k, c, j, tp)];
+    return make_double2((double)v.x, (double)v.y);
+  }
+  return reinterpret_cast<const cplx*>(hist)[hist_idx(d, k, c, j, tp)];
+}
+
 // ------------------------------------------------------------------ initial state
 // Eigen-decomposition of h0(k - A(0)) per k (one thread per k).
 template <int NB>
@@ -117,8 +132,8 @@ template <int NB>
 __global__ __launch_bounds__(64) void k_init_rho(Dims d, const double* __restrict__ w, const cplx* __restrict__ U,
                                                  const double* __restrict__ mu, double temp,
                                                  cplx* __restrict__ rhoA, cplx* __restrict__ rhoB,
-                                                 cplx* __restrict__ hist, cplx* __restrict__ col0,
-                                                 cplx* __restrict__ diag) {
+                                                 void* __restrict__ hist, cplx* __restrict__ row64,
+                                                 cplx* __restrict__ col0, cplx* __restrict__ diag) {
   constexpr int NBB = NB * NB;
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= d.nk) return;
@@ -136,15 +151,17 @@ __global__ __launch_bounds__(64) void k_init_rho(Dims d, const double* __restric
       int e = a * NB + b;
       rhoA[(int64_t)k * NBB + e] = s;
       rhoB[(int64_t)k * NBB + e] = s;
-      cplx gl = cmuli(s);
-      cplx one_minus = csub(cmk(a == b ? 1.0 : 0.0, 0.0), s);
-      cplx gg = cneg(cmuli(one_minus));
-      hist[hist_idx(d, k, e, 0, 0)] = gl;
-      hist[hist_idx(d, k, NBB + e, 0, 0)] = gg;
-      col0[rowbuf_idx(d, k, e, 0)] = gl;
-      col0[rowbuf_idx(d, k, NBB + e, 0)] = gg;
-      diag[rowbuf_idx(d, k, e, 0)] = gl;
-      diag[rowbuf_idx(d, k, NBB + e, 0)] = gg;
+      cplx g[2];
+      g[0] = cmuli(s);
+      g[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), s)));
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+        int c = sc * NBB + e;
+        commit_store(d, hist, k, c, 0, 0, g[sc]);
+        row64[row64_idx(d, 0, k, c, 0)] = g[sc];
+        col0[rowbuf_idx(d, k, c, 0)] = g[sc];
+        diag[rowbuf_idx(d, k, c, 0)] = g[sc];
+      }
     }
 }
 
@@ -269,7 +286,7 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
 // Block-to-work mapping gives each XCD a contiguous range of t_j, so the cache lines of
 // row m that several t_j share stay in one L2.
 template <int NB>
-__global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ sig,
+__global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ row64, cplx* __restrict__ sig,
                                                int m, double UU, int corr) {
   constexpr int NBB = NB * NB;
   extern __shared__ cplx lds[];
@@ -296,10 +313,9 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
     sincospi(2.0 * p / ny, &sn, &cs);
     twy[p] = cmk(cs, sn);
   }
-  int64_t roff = row_off(m) + j;
   for (int k = t; k < nk; k += 256) {
-    gl[k] = hist[((int64_t)k * d.C + ab) * d.P + roff];
-    gg[k] = hist[((int64_t)k * d.C + NBB + ab) * d.P + roff];
+    gl[k] = row64[row64_idx(d, m, k, ab, j)];
+    gg[k] = row64[row64_idx(d, m, k, NBB + ab, j)];
   }
   __syncthreads();
   // k -> R along y: t[ix][ry] = sum_iy e^{+2 pi i iy ry / ny} g[ix][iy]
@@ -364,10 +380,11 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
 }
 
 // ------------------------------------------------------------------ equal-time collision
-// I^<(t_m, t_m) = dt sum_j a_j [Sigma^>_mj G^<_jm - Sigma^<_mj G^>_jm],  G_jm = -(G_mj)^dag,
-// a_j the trapezoid weights on [0, t_m]; I^> (t_m, t_m) is the same matrix. One block per k.
+// I^<(t_m, t_m) = dt sum_j a_j [Sigma^>_mj G^<_jm - Sigma^<_mj G^>_jm],  G_jm = -(G_mj)^dag
+// for j < m, a_j the trapezoid weights on [0, t_m]; I^>(t_m, t_m) is the same matrix (both
+// integrals of eq. (CI) run over [0, t_m] and combine term by term). One block per k.
 template <int NB>
-__global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ hist,
+__global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ row64,
                                                 const cplx* __restrict__ sig, cplx* __restrict__ Icur,
                                                 cplx* __restrict__ Dcur, int m, double dt) {
   constexpr int NBB = NB * NB;
@@ -381,17 +398,23 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
       cplx Gl[NBB], Gg[NBB], Sl[NBB], Sg[NBB], t[NBB];
 #pragma unroll
       for (int e = 0; e < NBB; ++e) {
-        Gl[e] = hist[hist_idx(d, k, e, m, j)];
-        Gg[e] = hist[hist_idx(d, k, NBB + e, m, j)];
+        Gl[e] = row64[row64_idx(d, m, k, e, j)];
+        Gg[e] = row64[row64_idx(d, m, k, NBB + e, j)];
         Sl[e] = sig[sig_idx(d, k, 0, e, j)];
         Sg[e] = sig[sig_idx(d, k, 1, e, j)];
       }
-      // G_jm = -G_mj^dag:  Sg G^<_jm - Sl G^>_jm = -Sg Gl^dag + Sl Gg^dag
-      mat_zero<NB>(t);
-      mm_acc_bdag<NB>(t, Sl, Gg);
+      // j < m: G_jm = -G_mj^dag, so Sg G^<_jm - Sl G^>_jm = Sl Gg^dag - Sg Gl^dag;
+      // j = m: the stored equal-time block, Sg Gl - Sl Gg.
       cplx u[NBB];
+      mat_zero<NB>(t);
       mat_zero<NB>(u);
-      mm_acc_bdag<NB>(u, Sg, Gl);
+      if (j < m) {
+        mm_acc_bdag<NB>(t, Sl, Gg);
+        mm_acc_bdag<NB>(u, Sg, Gl);
+      } else {
+        mm_acc<NB>(t, Sg, Gl);
+        mm_acc<NB>(u, Sl, Gg);
+      }
 #pragma unroll
       for (int e = 0; e < NBB; ++e) acc[e] = cadd(acc[e], cscal(csub(t[e], u[e]), wgt));
     }
@@ -411,22 +434,82 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
 }
 
 // ------------------------------------------------------------------ history sums (hot loop)
+// Cross-lane helpers on doubles (two 32-bit halves). gfx950's permlane swaps exchange
+// half-waves / 16-lane rows between two registers on the VALU, DPP moves within rows.
+__device__ __forceinline__ void dsplit(double x, unsigned& lo, unsigned& hi) {
+  unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  lo = (unsigned)u;
+  hi = (unsigned)(u >> 32);
+}
+__device__ __forceinline__ double djoin(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// a <- [a_lo + a_hi | b_lo + b_hi] over the two half-waves (lanes l and l+32)
+__device__ __forceinline__ double rs_half(double a, double b) {
+  unsigned al, ah, bl, bh;
+  dsplit(a, al, ah);
+  dsplit(b, bl, bh);
+  auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+  auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
+}
+// rows of 16 lanes: a = [a0 a1 a2 a3], b = [b0 b1 b2 b3] -> [a0+a1, b0+b1, a2+a3, b2+b3]
+__device__ __forceinline__ double rs_row(double a, double b) {
+  unsigned al, ah, bl, bh;
+  dsplit(a, al, ah);
+  dsplit(b, bl, bh);
+  auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+  auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  unsigned lo, hi;
+  dsplit(x, lo, hi);
+  lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xF, 0xF, false);
+  hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xF, 0xF, false);
+  return djoin(lo, hi);
+}
+// sum over the 16 lanes of each row, result in every lane of the row
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_d<0x141>(x);  // row_half_mirror
+  x += dpp_d<0x140>(x);  // row_mirror
+  return x;
+}
+
+// History blocks are read once per pass: stream them past the caches.
+typedef double kbe_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx load_stream(const cplx* p) {
+#if KBE_BULK_NT
+  kbe_d2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_d2v*>(p));
+  return make_double2(v.x, v.y);
+#else
+  return *p;
+#endif
+}
+
 // Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
 // each with weight 1 (end-point weights are corrected in k_row):
 //   column term -> output t':  SR_j G^{<,>}_{j t'}                    (SR = Sigma^> - Sigma^<)
 //   row term    -> output j:   -Sigma^>_{t'} (G^<_{j t'})^dag + Sigma^<_{t'} (G^>_{j t'})^dag,
 //                               t' < j, shared by I^< and I^>    (G_{t' j} = -G_{j t'}^dag)
-// Block = (64-column strip s, k). Lane l owns column t' = 64 s + l and keeps its column
-// sums in registers while the 4 wavefronts walk the rows j >= 64 s (interleaved), so every
-// block of the strip is read from HBM exactly once with 1 KB-contiguous loads per
-// component plane. Each row term is reduced across the 64 lanes with shuffles and stored
-// per strip (rowpart); the 4 wavefronts' column sums are combined in LDS.
+// Block = (64-column strip s, k); strips with the most rows are launched first. Lane l owns
+// column t' = 64 s + l and keeps its column sums in registers; each wavefront takes R
+// consecutive rows per iteration (R x 2nb^2 loads of 1 KB-contiguous data in flight, one per
+// row and component plane; R = 4, 2, 1 for nb = 1, 2, >= 3 to stay within the register
+// file), so every stored block is read from HBM exactly once. The R rows' row terms are
+// reduced over the 64 lanes with a reduce-scatter (half-wave and 16-lane-row permlane swaps,
+// then DPP within rows) and stored per strip (rowpart); the 4 wavefronts' column sums are
+// combined in LDS. Deterministic: no atomics.
 template <int NB>
 __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restrict__ hist,
                                                    const cplx* __restrict__ sig, cplx* __restrict__ colsum,
                                                    cplx* __restrict__ rowpart, int m) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int CH = (C < 8) ? C : 8;  // components per LDS combine round
+  constexpr int R = NB == 1 ? 4 : (NB == 2 ? 2 : 1);  // rows per wavefront iteration
   __shared__ cplx red[3][CH][64];
   int s = blockIdx.x / d.nk;  // strips with the most rows first
   int k = blockIdx.x - s * d.nk;
@@ -443,40 +526,244 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
   cplx acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
-  const cplx* hk = hist + (int64_t)k * C * d.P;
+  const cplx* hk = hist + (int64_t)k * C * d.P + tp;
   cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
-  for (int j = 64 * s + wv; j < m; j += 4) {
-    bool v = colv && tp <= j;
-    int64_t off = row_off(j) + tp;
-    cplx G[C];
+  for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
+    cplx G[R][C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) G[c] = v ? hk[(int64_t)c * d.P + off] : czero();
-    cplx SR[NBB];
+    for (int r = 0; r < R; ++r) {
+      int j = jb + r;
+      bool v = colv && tp <= j && j < m;
+      int64_t off = row_off(j);
 #pragma unroll
-    for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + j];
-    mm_acc<NB>(acc, SR, G);
-    mm_acc<NB>(acc + NBB, SR, G + NBB);
-    cplx rt[NBB];
-    mat_zero<NB>(rt);
-    if (tp < j) {
-      cplx u[NBB];
+      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream(hk + (int64_t)c * d.P + off) : czero();
+    }
+    double rt[R][2 * NBB];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int j = jb + r;
+      int jc = j < m ? j : m - 1;
+      cplx SR[NBB];
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
+      mm_acc<NB>(acc, SR, G[r]);
+      mm_acc<NB>(acc + NBB, SR, G[r] + NBB);
+      cplx a[NBB], u[NBB];
+      mat_zero<NB>(a);
       mat_zero<NB>(u);
-      mm_acc_bdag<NB>(rt, Sl, G + NBB);
-      mm_acc_bdag<NB>(u, Sg, G);
+      mm_acc_bdag<NB>(a, Sl, G[r] + NBB);
+      mm_acc_bdag<NB>(u, Sg, G[r]);
+      bool rv = tp < j;
 #pragma unroll
-      for (int e = 0; e < NBB; ++e) rt[e] = csub(rt[e], u[e]);
+      for (int e = 0; e < NBB; ++e) {
+        rt[r][2 * e] = rv ? a[e].x - u[e].x : 0.0;
+        rt[r][2 * e + 1] = rv ? a[e].y - u[e].y : 0.0;
+      }
     }
+    // reduce-scatter over the 64 lanes; afterwards lane groups hold whole-row sums:
+    //   R = 4: lanes 0-15 row 0, 32-47 row 1, 16-31 row 2, 48-63 row 3
+    //   R = 2: lanes 0-31 row 0, 32-63 row 1;   R = 1: every lane row 0
 #pragma unroll
-    for (int e = 0; e < NBB; ++e) {
-      rt[e].x = wave_sum(rt[e].x);
-      rt[e].y = wave_sum(rt[e].y);
+    for (int q = 0; q < 2 * NBB; ++q) {
+      double y;
+      if constexpr (R == 4) {
+        y = rs_row(rs_half(rt[0][q], rt[1][q]), rs_half(rt[2][q], rt[3][q]));
+      } else if constexpr (R == 2) {
+        double x = rs_half(rt[0][q], rt[1][q]);
+        y = rs_row(x, x);
+      } else {
+        double x = rs_half(rt[0][q], rt[0][q]);
+        y = rs_row(x, x);
+      }
+      rt[0][q] = row16_sum(y);
     }
-    if (lane == 0) {
+    int rsel = -1;
+    if constexpr (R == 4) {
+      if ((lane & 15) == 0) rsel = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
+    } else if constexpr (R == 2) {
+      if ((lane & 31) == 0) rsel = lane >> 5;
+    } else {
+      if (lane == 0) rsel = 0;
+    }
+    if (rsel >= 0 && jb + rsel < m) {
 #pragma unroll
-      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + j] = rt[e];
+      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + jb + rsel] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
     }
   }
   // combine the 4 wavefronts' column sums
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    if (wv > 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) red[wv - 1][c][lane] = acc[c0 + c];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        cplx a = acc[c0 + c];
+        a = cadd(a, red[0][c][lane]);
+        a = cadd(a, red[1][c][lane]);
+        a = cadd(a, red[2][c][lane]);
+        if (colv) colsum[rowbuf_idx(d, k, c0 + c, tp)] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ history sums, FP32 form
+// Same structure as k_hist_bulk over an FP32-stored history (complex64, half the bytes):
+// products and the 64-lane row reductions in FP32; the column sums accumulate in FP32 over
+// tiles of 16 rows per wavefront and are then added into FP64 registers; row partials and
+// column sums leave the kernel in FP64 (the cross-strip reduction, the end points, the
+// update and the density matrix stay FP64).
+typedef float2 cplx32;
+__device__ __forceinline__ void cmac32(cplx32& acc, cplx32 a, cplx32 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cmacc32(cplx32& acc, cplx32 a, cplx32 b) {  // acc += a conj(b)
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  acc.y = fmaf(-a.x, b.y, acc.y);
+}
+__device__ __forceinline__ cplx32 to32(cplx v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ float rs_half32(float a, float b) {
+  auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                            false, false);
+  return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ float rs_row32(float a, float b) {
+  auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                            false, false);
+  return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum32(float x) {
+  x += dpp_f<0xB1>(x);
+  x += dpp_f<0x4E>(x);
+  x += dpp_f<0x141>(x);
+  x += dpp_f<0x140>(x);
+  return x;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __restrict__ hist,
+                                                     const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+                                                     cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  constexpr int CH = (C < 8) ? C : 8;
+  constexpr int R = NB <= 2 ? 4 : 2;  // rows per wavefront iteration
+  constexpr int FLUSH = 16 / R;       // iterations per FP32 accumulation tile (16 rows)
+  __shared__ cplx red[3][CH][64];
+  int s = blockIdx.x / d.nk;
+  int k = blockIdx.x - s * d.nk;
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int tp = 64 * s + lane;
+  bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  cplx32 Sl[NBB], Sg[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) {
+    Sl[e] = to32(colv ? sk[(0 * NBB + e) * d.Tp + tp] : czero());
+    Sg[e] = to32(colv ? sk[(1 * NBB + e) * d.Tp + tp] : czero());
+  }
+  cplx acc[C];
+  cplx32 acc32[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    acc[c] = czero();
+    acc32[c] = make_float2(0.f, 0.f);
+  }
+  const cplx32* hk = hist + (int64_t)k * C * d.P + tp;
+  cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+  int it = 0;
+  for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
+    cplx32 G[R][C];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int j = jb + r;
+      bool v = colv && tp <= j && j < m;
+      int64_t off = row_off16(j);
+#pragma unroll
+      for (int c = 0; c < C; ++c) G[r][c] = v ? hk[(int64_t)c * d.P + off] : make_float2(0.f, 0.f);
+    }
+    float rt[R][2 * NBB];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int j = jb + r;
+      int jc = j < m ? j : m - 1;
+      cplx32 SR[NBB];
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) SR[e] = to32(sk[(2 * NBB + e) * d.Tp + jc]);
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) cmac32(acc32[sc * NBB + i * NB + jj], SR[i * NB + l], G[r][sc * NBB + l * NB + jj]);
+      bool rv = tp < j;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {
+          cplx32 a = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int l = 0; l < NB; ++l) {
+            cmacc32(a, Sl[i * NB + l], G[r][NBB + jj * NB + l]);
+            cmacc32(u, Sg[i * NB + l], G[r][jj * NB + l]);
+          }
+          int e = i * NB + jj;
+          rt[r][2 * e] = rv ? a.x - u.x : 0.f;
+          rt[r][2 * e + 1] = rv ? a.y - u.y : 0.f;
+        }
+    }
+    if (++it == FLUSH) {
+      it = 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[c].x += (double)acc32[c].x;
+        acc[c].y += (double)acc32[c].y;
+        acc32[c] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * NBB; ++q) {
+      float y;
+      if constexpr (R == 4) {
+        y = rs_row32(rs_half32(rt[0][q], rt[1][q]), rs_half32(rt[2][q], rt[3][q]));
+      } else {
+        float x = rs_half32(rt[0][q], rt[1][q]);
+        y = rs_row32(x, x);
+      }
+      rt[0][q] = row16_sum32(y);
+    }
+    int rsel = -1;
+    if constexpr (R == 4) {
+      if ((lane & 15) == 0) rsel = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
+    } else {
+      if ((lane & 31) == 0) rsel = lane >> 5;
+    }
+    if (rsel >= 0 && jb + rsel < m) {
+#pragma unroll
+      for (int e = 0; e < NBB; ++e)
+        rp[(int64_t)e * d.Tp + jb + rsel] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    acc[c].x += (double)acc32[c].x;
+    acc[c].y += (double)acc32[c].y;
+  }
 #pragma unroll
   for (int c0 = 0; c0 < C; c0 += CH) {
     if (wv > 0) {
@@ -509,13 +796,14 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
 //  PREDICT/CORRECT, t' = m: rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag and the
 //   equal-time block G^< = i rho_m, G^> = -i (1 - rho_m).
 template <int NB, int MODE>
-__global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, const cplx* __restrict__ sig,
-                                             const cplx* __restrict__ colsum, const cplx* __restrict__ rowpart,
-                                             cplx* __restrict__ col0, cplx* __restrict__ diag,
-                                             const cplx* __restrict__ Iprev, cplx* __restrict__ Icur,
-                                             const cplx* __restrict__ props, const cplx* __restrict__ rho_prev,
-                                             cplx* __restrict__ rho_cur, const cplx* __restrict__ Dprev,
-                                             const cplx* __restrict__ Dcur, int m, double dt) {
+__global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cplx* __restrict__ row64,
+                                             const cplx* __restrict__ sig, const cplx* __restrict__ colsum,
+                                             const cplx* __restrict__ rowpart, cplx* __restrict__ col0,
+                                             cplx* __restrict__ diag, const cplx* __restrict__ Iprev,
+                                             cplx* __restrict__ Icur, const cplx* __restrict__ props,
+                                             const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
+                                             const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
+                                             double dt) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   int k = blockIdx.y;
   int tp = blockIdx.x * 256 + threadIdx.x;
@@ -548,7 +836,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, co
         SRm0[e] = sig[sig_idx(d, k, 2, e, 0)];
       }
 #pragma unroll
-      for (int c = 0; c < C; ++c) Gm[c] = hist[hist_idx(d, k, c, m, tp)];
+      for (int c = 0; c < C; ++c) Gm[c] = row64[row64_idx(d, m, k, c, tp)];
       if (tp == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c) G0[c] = col0[rowbuf_idx(d, k, c, 0)];
@@ -609,7 +897,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, co
       for (int c = 0; c < C; ++c) {
         cplx ip = Iprev[rowbuf_idx(d, k, c, tp)];
         Ib[c] = (MODE == KBE_ROW_PREDICT) ? ip : cscal(cadd(ip, In[c]), 0.5);
-        Go[c] = hist[hist_idx(d, k, c, m - 1, tp)];
+        Go[c] = row64[row64_idx(d, m - 1, k, c, tp)];
       }
       cplx V[NBB], Phi[NBB];
 #pragma unroll
@@ -625,8 +913,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, co
         mm_acc<NB>(g, Phi, Ib + sc * NBB);
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
-          hist[hist_idx(d, k, sc * NBB + e, m, tp)] = g[e];
-          if (tp == 0) col0[rowbuf_idx(d, k, sc * NBB + e, m)] = g[e];
+          int c = sc * NBB + e;
+          row64[row64_idx(d, m, k, c, tp)] = g[e];
+          commit_store(d, hist, k, c, m, tp, g[e]);
+          if (tp == 0) col0[rowbuf_idx(d, k, c, m)] = g[e];
         }
       }
     }
@@ -656,12 +946,16 @@ __global__ __launch_bounds__(256) void k_row(Dims d, cplx* __restrict__ hist, co
         int e = a * NB + b;
         cplx rv = csub(rho[e], cscal(t2[e], dt));
         rho_cur[(int64_t)k * NBB + e] = rv;
-        cplx gl = cmuli(rv);
-        cplx gg = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
-        hist[hist_idx(d, k, e, m, m)] = gl;
-        hist[hist_idx(d, k, NBB + e, m, m)] = gg;
-        diag[rowbuf_idx(d, k, e, m)] = gl;
-        diag[rowbuf_idx(d, k, NBB + e, m)] = gg;
+        cplx g[2];
+        g[0] = cmuli(rv);
+        g[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
+#pragma unroll
+        for (int sc = 0; sc < 2; ++sc) {
+          int c = sc * NBB + e;
+          row64[row64_idx(d, m, k, c, m)] = g[sc];
+          commit_store(d, hist, k, c, m, m, g[sc]);
+          diag[rowbuf_idx(d, k, c, m)] = g[sc];
+        }
       }
   }
 }
@@ -781,15 +1075,18 @@ __global__ __launch_bounds__(256) void k_obs(Dims d, const cplx* __restrict__ ho
 }
 
 // ------------------------------------------------------------------ aux copies
+// Refresh the FP64 working copies from history rows 0..m: column 0, diagonal, rows m-1, m.
 template <int NB>
-__global__ void k_aux(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ col0, cplx* __restrict__ diag,
-                      int m) {
+__global__ void k_aux(Dims d, const void* __restrict__ hist, cplx* __restrict__ row64, cplx* __restrict__ col0,
+                      cplx* __restrict__ diag, int m) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int kc = blockIdx.y;
   if (j > m) return;
   int k = kc / d.C, c = kc - (kc / d.C) * d.C;
-  col0[rowbuf_idx(d, k, c, j)] = hist[hist_idx(d, k, c, j, 0)];
-  diag[rowbuf_idx(d, k, c, j)] = hist[hist_idx(d, k, c, j, j)];
+  col0[rowbuf_idx(d, k, c, j)] = history_load(d, hist, k, c, j, 0);
+  diag[rowbuf_idx(d, k, c, j)] = history_load(d, hist, k, c, j, j);
+  row64[row64_idx(d, m, k, c, j)] = history_load(d, hist, k, c, m, j);
+  if (m >= 1 && j < m) row64[row64_idx(d, m - 1, k, c, j)] = history_load(d, hist, k, c, m - 1, j);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -802,7 +1099,7 @@ struct Launch {
                        a.target, a.mu);
     hipLaunchKernelGGL(k_init_rho<NB>, dim3(nb64), dim3(64), 0, st, d, (const double*)a.eig_w,
                        (const cplx*)a.eig_U, (const double*)a.mu, a.temp, a.rho_prev, a.rho_cur, a.hist,
-                       a.col0, a.diag);
+                       a.row64, a.col0, a.diag);
     return hipGetLastError();
   }
   static hipError_t hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t st) {
@@ -819,26 +1116,30 @@ struct Launch {
     int total = (m + 1) * NB * NB;
     int per = (total + 7) / 8;
     size_t shm = (size_t)(4 * d.nk + d.nkx + d.nky) * sizeof(cplx);
-    hipLaunchKernelGGL(k_sigma<NB>, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.hist, a.sig, m, a.UU,
+    hipLaunchKernelGGL(k_sigma<NB>, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.row64, a.sig, m, a.UU,
                        a.corr);
     return hipGetLastError();
   }
   static hipError_t diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
-    hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.hist, (const cplx*)a.sig,
+    hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.row64, (const cplx*)a.sig,
                        a.I_cur, a.D_cur, m, a.dt);
     return hipGetLastError();
   }
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     if (m < 1) return hipSuccess;
     int ns = (m + 63) / 64;
-    hipLaunchKernelGGL(k_hist_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
-                       (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    if (d.fp32)
+      hipLaunchKernelGGL(k_hist_bulk32<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
+                         (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    else
+      hipLaunchKernelGGL(k_hist_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                         (const cplx*)a.sig, a.colsum, a.rowpart, m);
     return hipGetLastError();
   }
   static hipError_t row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
     dim3 grid((m + 1 + 255) / 256, d.nk);
 #define KBE_ROW_ARGS                                                                                      \
-  d, a.hist, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag,          \
+  d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
       (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt
     if (mode == KBE_ROW_PREDICT)
@@ -857,7 +1158,7 @@ struct Launch {
   }
   static hipError_t aux(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     dim3 grid((m + 1 + 255) / 256, d.nk * d.C);
-    hipLaunchKernelGGL(k_aux<NB>, grid, dim3(256), 0, st, d, (const cplx*)a.hist, a.col0, a.diag, m);
+    hipLaunchKernelGGL(k_aux<NB>, grid, dim3(256), 0, st, d, (const void*)a.hist, a.row64, a.col0, a.diag, m);
     return hipGetLastError();
   }
 };

@@ -18,7 +18,8 @@ namespace kbe {
 // Device pointers and scalars a launch needs (the roles *_prev / *_cur are resolved by
 // the caller for the current step).
 struct LaunchArgs {
-  cplx* hist;
+  void* hist;      // packed history, FP64 (cplx) or FP32 (float2) elements
+  cplx* row64;     // FP64 working copies of history rows m-1 and m
   cplx* sig;
   cplx* I_prev;
   cplx* I_cur;

@@ -32,7 +32,7 @@ OBS_NAMES = ["t", "N", "Ekin", "EHF", "Ecorr", "Etot", "Jx", "Jy", "A",
 OBS = {n: i for i, n in enumerate(OBS_NAMES)}
 
 BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_CUR, BUF_PROP, \
-    BUF_COL0, BUF_DIAG = range(10)
+    BUF_COL0, BUF_DIAG, BUF_ROWS = range(11)
 
 
 class KbeConfig(ctypes.Structure):
@@ -95,8 +95,12 @@ def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
     return h.value, w.value, o.value
 
 
-def row_off(j: int) -> int:
-    """Start of row j inside a (k, component) plane of the packed history (include/kbe.h)."""
+def row_off(j: int, fp32: bool = False) -> int:
+    """Start of row j inside a (k, component) plane of the packed history (include/kbe.h):
+    rows padded to 8 complex128 (FP64 form) or 16 complex64 (FP32 form) elements."""
+    if fp32:
+        Q, r = j >> 4, j & 15
+        return 128 * Q * (Q + 1) + 16 * r * (Q + 1)
     Q, r = j >> 3, j & 7
     return 32 * Q * (Q + 1) + 8 * r * (Q + 1)
 
@@ -110,13 +114,15 @@ class System:
         self.nt_max = cfg.nt if nt_max is None else nt_max
         hb, wb, ob = workspace_query(cfg, self.nt_max)
         dev = torch.device(device)
-        self.history = torch.empty(hb // 16, dtype=torch.complex128, device=dev)
+        self.fp32 = cfg.precision == _inputs.PRECISION_FP32
+        hdt = torch.complex64 if self.fp32 else torch.complex128
+        self.history = torch.empty(hb // (8 if self.fp32 else 16), dtype=hdt, device=dev)
         self.workspace = torch.empty(wb, dtype=torch.uint8, device=dev)
         self.obs = torch.empty(ob // 8, dtype=torch.float64, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.nk, self.nb = cfg.nk, cfg.nb
         self.C = 2 * cfg.nb * cfg.nb
-        self.P = row_off(self.nt_max + 1)
+        self.P = row_off(self.nt_max + 1, self.fp32)
         self.Tp = ((self.nt_max + 1 + 7) // 8) * 8
         self._ctx = None
         self._create()
@@ -205,20 +211,29 @@ class System:
         return self.workspace[off:off + nbytes.value].view(torch.complex128)
 
     def history_planes(self) -> torch.Tensor:
-        """History as [k][component][P] complex128 (component c = s*nb^2 + a*nb + b)."""
+        """History as [k][component][P] (component c = s*nb^2 + a*nb + b), complex128 or
+        complex64 (FP32 form)."""
         return self.history.view(self.nk, self.C, self.P)
 
     def history_row(self, j: int) -> torch.Tensor:
-        """Row j as a [t'][k][</>][a][b] tensor (copy)."""
+        """Row j as a [t'][k][</>][a][b] tensor (copy, in the storage precision)."""
         nb = self.nb
-        h = self.history_planes()[:, :, row_off(j):row_off(j) + j + 1]   # [k][c][t']
+        o = row_off(j, self.fp32)
+        h = self.history_planes()[:, :, o:o + j + 1]   # [k][c][t']
         return h.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
 
     def set_history_row(self, j: int, row: torch.Tensor):
-        """Write row j from a [t'][k][</>][a][b] tensor."""
-        nb = self.nb
+        """Write row j from a [t'][k][</>][a][b] tensor (cast to the storage precision)."""
+        o = row_off(j, self.fp32)
         src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0)
-        self.history_planes()[:, :, row_off(j):row_off(j) + j + 1].copy_(src)
+        self.history_planes()[:, :, o:o + j + 1].copy_(src)
+
+    def row64(self, j: int) -> torch.Tensor:
+        """FP64 working copy of history row j (j = m-1 or m of the current step), as a
+        [t'][k][</>][a][b] tensor (copy)."""
+        nb = self.nb
+        r = self.buffer(BUF_ROWS).view(2, self.nk, self.C, self.Tp)[j & 1, :, :, :j + 1]
+        return r.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
 
     def rowbuf(self, which: int) -> torch.Tensor:
         """A [k][C][Tp] row buffer (I rows, COL0, DIAG) as a [t'][k][</>][a][b] view helper."""

@@ -37,7 +37,12 @@ def relerr(got, ref):
     got = np.asarray(got)
     ref = np.asarray(ref)
     scale = np.abs(ref).max()
-    return np.abs(got - ref).max() / (scale if scale > 0 else 1.0)
+    diff = np.abs(got - ref)
+    r = diff.max() / (scale if scale > 0 else 1.0)
+    if not r < KERNEL_TOL:
+        idx = np.unravel_index(np.argmax(diff), diff.shape)
+        _say(f"  worst element at {tuple(int(i) for i in idx)}: got {got[idx]} ref {ref[idx]} (rel {r:.2e})")
+    return r
 
 
 def _cfg(nkx, nky, nb, nt, **kw):
@@ -73,6 +78,7 @@ def test_sigma_row_parity(K, nkx, nky, nb, m):
     S = K.System(cfg)
     row = inputs.random_complex((m + 1, cfg.nk, 2, nb, nb), 100 + m, scale=0.5)
     S.set_history_row(m, torch.from_numpy(row).cuda())
+    S.rebuild_aux(m)
     S.stage_sigma(m)
     got = S.sigma_row(m).cpu().numpy()
     ref = O.sigma_row(cfg, m, row)
@@ -153,8 +159,10 @@ def _compare_run(K, cfg, nsteps):
     for name in SERIES:
         i = O.OBS[name]
         x, r = obs[:, i], ref["obs"][:, i]
-        if np.abs(r).max() == 0.0:
-            assert np.abs(x).max() < 1e-14, name
+        if np.abs(r).max() < 1e-12:
+            # identically zero by symmetry (e.g. J_y for a pulse along x, unused orbitals):
+            # both sides must stay at rounding level
+            assert np.abs(x).max() < 1e-12, name
             continue
         worst[name] = relerr(x, r)
     assert np.abs(obs[:, 0] - ref["obs"][:, 0]).max() < 1e-12
@@ -245,6 +253,7 @@ def test_collision_full_size_sampled(K):
     nb = cfg.nb
     for k in (0, 313, cfg.nk - 1):
         planes = S.history_planes()[k].cpu().numpy()  # [C][P]
+        assert planes.dtype == np.complex128
         rows = []
         for j in range(m + 1):
             o = K.row_off(j)
@@ -266,6 +275,7 @@ def test_sigma_full_size_sampled(K):
     S = K.System(cfg)
     row = S.history_planes()[:, :, K.row_off(m):K.row_off(m) + m + 1]
     inputs.fill_normal_(row, seed=77, scale=0.4)
+    S.rebuild_aux(m)
     S.stage_sigma(m)
     sig = S.sigma_row(m).cpu().numpy()
     rowh = S.history_row(m).cpu().numpy()

@@ -93,17 +93,19 @@ typedef struct {
 typedef struct kbe_ctx kbe_ctx;
 
 /*
- * Device layout (all complex128):
+ * Device layout:
  *   history : G^{<,>}_{ab}(k; t_j, t') for 0 <= t' <= j <= nt_max, packed lower triangle per
- *             k and per component, contiguous in t', rows padded to 8 elements (128 B):
- *               elem(k, c, j, t') = (k * C + c) * P + rowoff(j) + t'
- *             C = 2 nb^2, c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>),
- *             rowoff(j) = 32 Q (Q+1) + 8 r (Q+1) with Q = j / 8, r = j % 8, P = rowoff(nt_max + 1).
- *             KBE_FP32: complex64 elements, rows padded to 16 elements:
- *             rowoff(j) = 128 Q (Q+1) + 16 r (Q+1) with Q = j / 16, r = j % 16. In this form the
- *             history sums read the FP32 history and compute in FP32 (FP32 accumulation over
- *             tiles of 16 rows, FP64 across tiles and strips); rows m-1 and m, the end-point
- *             terms, the update, the density matrix and the observables stay FP64.
+ *             k and per component, strip-major: the columns t' are grouped in strips of 64, and
+ *             strip s holds rows j = 64 s .. N-1 (N = nt_max + 1) as consecutive 64-wide
+ *             segments, contiguous in t':
+ *               elem(k, c, j, t') = (k * C + c) * P + base(s) + 64 (j - 64 s) + (t' - 64 s),
+ *               s = t' / 64,  base(s) = 64 s N - 2048 s (s - 1),  P = base(ceil(N / 64)),
+ *             C = 2 nb^2, c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). Entries above the
+ *             diagonal in a strip's first 64 rows are unused. Elements are complex128 (KBE_FP64)
+ *             or complex64 (KBE_FP32). In the FP32 form the history sums read the FP32 history
+ *             and compute in FP32 (FP32 accumulation over tiles of 16 rows, FP64 across tiles
+ *             and strips); rows m-1 and m, the end-point terms, the update, the density matrix
+ *             and the observables stay FP64.
  *   workspace: the per-step rows (self-energy row, collision rows, density matrices,
  *             propagators, partial sums); sub-buffers are located with kbe_buffer.
  *   obs     : (nt_max + 1) x KBE_NOBS doubles, row m written when step m completes.

@@ -26,6 +26,11 @@
 // Storage (oracle-private): row j of the two-time lower triangle is an array
 // [t'=0..j][k][comp(0:<,1:>)][a][b] of complex numbers.
 //
+// Every routine is written once for a generic real type R. R = double is the oracle;
+// R = Dual<3> (value + three directional derivatives, forward-mode automatic
+// differentiation) gives the tangent-linear model: the exact derivatives of the same
+// computation with respect to the pulse amplitude, the pulse frequency and U.
+//
 // Pins (tests/test_oracle_pins.py, CPU only):
 //   sigma_row ....... eq. (2BSE) direct double momentum sums (interband preset, with the
 //                     paper's allind_kpk index map) and the Hubbard momentum convolution;
@@ -36,6 +41,9 @@
 //   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
 //                     dt-convergence ratio 4, TDHF limit vs RK4
 
+//   tangent-linear .. R = double run reproduced bit-for-bit by the value part; derivatives
+//                     against central finite differences of the double oracle
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -44,7 +52,62 @@
 
 namespace {
 
-// ---------------------------------------------------------------- scalar types
+// ---------------------------------------------------------------- real types
+// Forward-mode dual number: value and N directional derivatives.
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
+  Dual(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
+};
+template <int N> inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r;
+}
+template <int N> inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r;
+}
+template <int N> inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r; r.v = a.v / b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+template <int N> inline Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
+template <int N> inline Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
+template <int N> inline Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
+template <int N> inline Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
+template <int N> inline Dual<N> operator*(const Dual<N>& a, double b) {
+  Dual<N> r; r.v = a.v * b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b; return r;
+}
+template <int N> inline Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
+template <int N> inline Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> inline Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> inline Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
+template <int N> inline Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) { a = a - b; return a; }
+template <int N> inline Dual<N> chain(const Dual<N>& a, double f, double df) {
+  Dual<N> r; r.v = f; for (int i = 0; i < N; ++i) r.d[i] = df * a.d[i]; return r;
+}
+template <int N> inline Dual<N> sqrt(const Dual<N>& a) { double s = std::sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int N> inline Dual<N> exp(const Dual<N>& a) { double e = std::exp(a.v); return chain(a, e, e); }
+template <int N> inline Dual<N> sin(const Dual<N>& a) { return chain(a, std::sin(a.v), std::cos(a.v)); }
+template <int N> inline Dual<N> cos(const Dual<N>& a) { return chain(a, std::cos(a.v), -std::sin(a.v)); }
+template <int N> inline Dual<N> fabs(const Dual<N>& a) { return a.v < 0 ? -a : a; }
+using std::cos;
+using std::exp;
+using std::fabs;
+using std::sin;
+using std::sqrt;
+inline double val(double x) { return x; }
+template <int N> inline double val(const Dual<N>& x) { return x.v; }
+
+typedef Dual<3> D3;
+
 template <class R>
 struct Cx {
   R re, im;
@@ -65,10 +128,7 @@ template <class R> inline Cx<R>& operator+=(Cx<R>& a, Cx<R> b) { a.re += b.re; a
 template <class R> inline Cx<R>& operator-=(Cx<R>& a, Cx<R> b) { a.re -= b.re; a.im -= b.im; return a; }
 template <class R> inline Cx<R> cexpi(R x) { using std::cos; using std::sin; return {cos(x), sin(x)}; }
 template <class R> inline R abs2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
-
-typedef double R;
-typedef Cx<R> C;
-const C I1(0.0, 1.0);
+template <class R> inline Cx<R> imag_unit() { return Cx<R>(R(0.0), R(1.0)); }
 
 // ---------------------------------------------------------------- parameters
 // Mirrors OracleParams in oracle/oracle.py (ctypes); plain data.
@@ -80,6 +140,12 @@ enum { INT_HUBBARD = 0, INT_INTERBAND = 1 };
 enum {
   OBS_T = 0, OBS_N, OBS_EKIN, OBS_EHF, OBS_ECORR, OBS_ETOT, OBS_JX, OBS_JY, OBS_A,
   OBS_NORB = 9, OBS_NBAND = 13, NOBS = 17
+};
+
+// The three parameters a gradient is taken with respect to, in the run's real type.
+template <class R>
+struct Theta {
+  R amp, omega, U;
 };
 
 struct Grid {
@@ -99,15 +165,17 @@ struct Grid {
 
 // ---------------------------------------------------------------- small dense matrices
 // n x n complex matrices in row-major arrays.
-void mm(int n, const C* A, const C* B, C* out) {
+template <class R>
+void mm(int n, const Cx<R>* A, const Cx<R>* B, Cx<R>* out) {
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      C s;
+      Cx<R> s;
       for (int l = 0; l < n; ++l) s += A[i * n + l] * B[l * n + j];
       out[i * n + j] = s;
     }
 }
-void adjoint(int n, const C* A, C* out) {
+template <class R>
+void adjoint(int n, const Cx<R>* A, Cx<R>* out) {
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) out[j * n + i] = conj(A[i * n + j]);
 }
@@ -115,26 +183,28 @@ void adjoint(int n, const C* A, C* out) {
 // Eigen-decomposition of a Hermitian matrix by cyclic complex Jacobi rotations.
 // On exit w holds the eigenvalues in ascending order and the columns of Vec the
 // eigenvectors (A = Vec diag(w) Vec^dag).
-void eigh(int n, const C* Ain, double* w, C* Vec) {
+template <class R>
+void eigh(int n, const Cx<R>* Ain, R* w, Cx<R>* Vec) {
+  typedef Cx<R> C;
   std::vector<C> A(Ain, Ain + n * n);
   for (int i = 0; i < n * n; ++i) Vec[i] = C();
   for (int i = 0; i < n; ++i) Vec[i * n + i] = C(1.0);
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int p = 0; p < n; ++p)
-      for (int q = 0; q < n; ++q) (p == q ? dia : off) += abs2(A[p * n + q]);
+      for (int q = 0; q < n; ++q) (p == q ? dia : off) += val(abs2(A[p * n + q]));
     if (off <= 1e-34 * (dia + 1e-300)) break;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         C apq = A[p * n + q];
-        double r = std::sqrt(abs2(apq));
-        if (r < 1e-300) continue;
-        C ph = scale(apq, 1.0 / r);  // e^{i phi}
-        double a = A[p * n + p].re, b = A[q * n + q].re;
+        if (std::sqrt(val(abs2(apq))) < 1e-300) continue;
+        R r = sqrt(abs2(apq));
+        C ph = scale(apq, R(1.0) / r);  // e^{i phi}
+        R a = A[p * n + p].re, b = A[q * n + q].re;
         // rotate the real symmetric problem [[a, r], [r, b]]
-        double theta = (b - a) / (2.0 * r);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        R theta = (b - a) / (2.0 * r);
+        R t = (val(theta) >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        R c = 1.0 / sqrt(t * t + 1.0), s = t * c;
         // W = diag(1, e^{-i phi}) * [[c, s], [-s, c]] on the (p, q) plane
         C wpp(c), wpq(s), wqp = scale(conj(ph), -s), wqq = scale(conj(ph), c);
         for (int i = 0; i < n; ++i) {  // A <- A W
@@ -161,9 +231,9 @@ void eigh(int n, const C* Ain, double* w, C* Vec) {
   // sort ascending
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
-  std::vector<double> d(n);
+  std::vector<R> d(n);
   for (int i = 0; i < n; ++i) d[i] = A[i * n + i].re;
-  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return val(d[x]) < val(d[y]); });
   std::vector<C> V2(n * n);
   for (int c = 0; c < n; ++c) {
     w[c] = d[idx[c]];
@@ -173,14 +243,14 @@ void eigh(int n, const C* Ain, double* w, C* Vec) {
 }
 
 // f(h) = U diag(f(w)) U^dag for a Hermitian h.
-template <class F>
-void matfun(int n, const C* h, F f, C* out) {
-  std::vector<double> w(n);
-  std::vector<C> U(n * n);
+template <class R, class F>
+void matfun(int n, const Cx<R>* h, F f, Cx<R>* out) {
+  std::vector<R> w(n);
+  std::vector<Cx<R>> U(n * n);
   eigh(n, h, w.data(), U.data());
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      C s;
+      Cx<R> s;
       for (int b = 0; b < n; ++b) s += U[i * n + b] * f(w[b]) * conj(U[j * n + b]);
       out[i * n + j] = s;
     }
@@ -188,15 +258,18 @@ void matfun(int n, const C* h, F f, C* out) {
 
 // ---------------------------------------------------------------- model
 // Pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2), along pol.
-double pulse_A(const Params& p, double t) {
+template <class R>
+R pulse_A(const Params& p, const Theta<R>& th, double t) {
   double x = (t - p.t0) / p.width;
-  return p.amp * std::sin(p.omega * t) * std::exp(-x * x);
+  return th.amp * sin(th.omega * t) * std::exp(-x * x);
 }
 
 // h0(k - A pol) = T0 + sum_d [T_d e^{i q_d} + T_d^dag e^{-i q_d}], q = k - A pol.
-void h0(const Params& p, const Grid& g, const C* hop, int k, double A, C* out) {
+template <class R>
+void h0(const Params& p, const Grid& g, const Cx<R>* hop, int k, R A, Cx<R>* out) {
+  typedef Cx<R> C;
   int nb = g.nb;
-  double q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
+  R q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
   for (int a = 0; a < nb; ++a)
     for (int b = 0; b < nb; ++b) {
       C s = hop[a * nb + b];
@@ -209,14 +282,16 @@ void h0(const Params& p, const Grid& g, const C* hop, int k, double A, C* out) {
 }
 
 // velocity d h0 / d k_d at k - A pol: i (T_d e^{i q_d} - T_d^dag e^{-i q_d})
-void vel(const Params& p, const Grid& g, const C* hop, int k, double A, int d, C* out) {
+template <class R>
+void vel(const Params& p, const Grid& g, const Cx<R>* hop, int k, R A, int d, Cx<R>* out) {
+  typedef Cx<R> C;
   int nb = g.nb;
-  double q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
+  R q[2] = {g.kx[g.ix(k)] - A * p.polx, g.ky[g.iy(k)] - A * p.poly};
   for (int a = 0; a < nb; ++a)
     for (int b = 0; b < nb; ++b) {
       if (d >= g.dim) { out[a * nb + b] = C(); continue; }
       const C* T = hop + (1 + d) * nb * nb;
-      out[a * nb + b] = I1 * (T[a * nb + b] * cexpi(q[d]) - conj(T[b * nb + a]) * cexpi(-q[d]));
+      out[a * nb + b] = imag_unit<R>() * (T[a * nb + b] * cexpi(q[d]) - conj(T[b * nb + a]) * cexpi(-q[d]));
     }
 }
 
@@ -225,7 +300,9 @@ void vel(const Params& p, const Grid& g, const C* hop, int k, double A, int d, C
 //  Hubbard (intra-orbital U, opposite spins): Sigma_ab = delta_ab U rho_loc,aa.
 //  Interband, eq. (ham): Hartree U n_c on v and U n_v on c, Fock -U rho_loc,vc on
 //  the off-diagonal.
-void hf_field(const Params& p, const Grid& g, const std::vector<C>& rho, C* out) {
+template <class R>
+void hf_field(const Params& p, const Theta<R>& th, const Grid& g, const std::vector<Cx<R>>& rho, Cx<R>* out) {
+  typedef Cx<R> C;
   int nb = g.nb, nbb = nb * nb;
   std::vector<C> loc(nbb);
   for (int k = 0; k < g.nk; ++k)
@@ -234,24 +311,28 @@ void hf_field(const Params& p, const Grid& g, const std::vector<C>& rho, C* out)
   for (int i = 0; i < nbb; ++i) out[i] = C();
   if (!p.hf) return;
   if (p.interaction == INT_HUBBARD) {
-    for (int a = 0; a < nb; ++a) out[a * nb + a] = C(p.U * loc[a * nb + a].re);
+    for (int a = 0; a < nb; ++a) out[a * nb + a] = C(th.U * loc[a * nb + a].re);
   } else {
-    out[0] = C(p.U * loc[3].re);
-    out[3] = C(p.U * loc[0].re);
-    out[1] = loc[1] * (-p.U);
-    out[2] = loc[2] * (-p.U);
+    out[0] = C(th.U * loc[3].re);
+    out[3] = C(th.U * loc[0].re);
+    out[1] = scale(loc[1], -th.U);
+    out[2] = scale(loc[2], -th.U);
   }
 }
 
 // k-independent one-body term: the -U c_c^dag c_c term of eq. (ham) (interband only).
-void onebody_extra(const Params& p, int nb, C* out) {
-  for (int i = 0; i < nb * nb; ++i) out[i] = C();
-  if (p.interaction == INT_INTERBAND) out[3] = C(-p.U);
+template <class R>
+void onebody_extra(const Params& p, const Theta<R>& th, int nb, Cx<R>* out) {
+  for (int i = 0; i < nb * nb; ++i) out[i] = Cx<R>();
+  if (p.interaction == INT_INTERBAND) out[3] = Cx<R>(-th.U);
 }
 
 // ---------------------------------------------------------------- state
+template <class R>
 struct State {
+  typedef Cx<R> C;
   const Params& p;
+  Theta<R> th;
   Grid g;
   std::vector<C> hop;
   int nbb, blk;                    // nb^2, 2 nb^2 (one (t,t') block: lesser then greater)
@@ -259,8 +340,7 @@ struct State {
   std::vector<C> rho_prev, rho_cur, D_prev, D_cur;  // [k][a][b]
   std::vector<C> I_prev, I_cur;    // [t'][k][comp][a][b], t' = 0..m
   std::vector<C> sig;              // [j][k][comp][a][b], j = 0..m
-  std::vector<double> obs;
-  State(const Params& pp, const double* hopd) : p(pp), g(pp) {
+  State(const Params& pp, const Theta<R>& t, const double* hopd) : p(pp), th(t), g(pp) {
     nbb = g.nb * g.nb;
     blk = 2 * nbb;
     hop.resize(3 * nbb);
@@ -270,7 +350,10 @@ struct State {
 };
 
 // Equal-time block of G from rho: G^< = i rho, G^> = -i (1 - rho).
-void set_diag_block(int nb, const C* rho, C* blk) {
+template <class R>
+void set_diag_block(int nb, const Cx<R>* rho, Cx<R>* blk) {
+  typedef Cx<R> C;
+  const C I1 = imag_unit<R>();
   for (int a = 0; a < nb; ++a)
     for (int b = 0; b < nb; ++b) {
       C r = rho[a * nb + b];
@@ -283,12 +366,15 @@ void set_diag_block(int nb, const C* rho, C* blk) {
 // Initial state: uncorrelated Fermi-Dirac density of h0(k - A(0)) at temperature T,
 // chemical potential by bisection so that N_k^{-1} sum_k tr rho = nb * filling.
 // (The paper starts from a given G; the configurations ask for an uncorrelated
-// state at half filling and temperature T.)
-double initial_state(const Params& p, const Grid& g, const C* hop, std::vector<C>& rho) {
+// state at half filling and temperature T.) Computed in double: it does not depend on
+// the pulse (A(0) = 0 for the sin pulse) nor on U.
+double initial_state(const Params& p, const Grid& g, const Cx<double>* hop, std::vector<Cx<double>>& rho) {
+  typedef Cx<double> C;
   int nb = g.nb, nbb = nb * nb;
   std::vector<double> w(g.nk * nb);
   std::vector<C> U(g.nk * nbb), h(nbb);
-  double A0 = pulse_A(p, 0.0);
+  Theta<double> th{p.amp, p.omega, p.U};
+  double A0 = pulse_A(p, th, 0.0);
   for (int k = 0; k < g.nk; ++k) {
     h0(p, g, hop, k, A0, h.data());
     eigh(nb, h.data(), &w[k * nb], &U[k * nbb]);
@@ -321,16 +407,18 @@ double initial_state(const Params& p, const Grid& g, const C* hop, std::vector<C
 // Real-space transforms over the k grid of eq. (kj):
 //   g(R) = N_k^{-1} sum_k e^{i k.R} G(k),     Sigma(k) = sum_R e^{-i k.R} Sigma(R).
 // Written as two 1D direct sums (the exponential factorises over the axes).
+template <class R>
 struct Dft {
+  typedef Cx<R> C;
   int nx, ny;
   std::vector<C> ex, ey;  // ex[j * nx + R] = e^{i kx_j R}
   explicit Dft(const Grid& g) : nx(g.nkx), ny(g.nky) {
     ex.resize(nx * nx);
     ey.resize(ny * ny);
     for (int j = 0; j < nx; ++j)
-      for (int r = 0; r < nx; ++r) ex[j * nx + r] = cexpi(g.kx[j] * r);
+      for (int r = 0; r < nx; ++r) ex[j * nx + r] = C(std::cos(g.kx[j] * r), std::sin(g.kx[j] * r));
     for (int j = 0; j < ny; ++j)
-      for (int r = 0; r < ny; ++r) ey[j * ny + r] = cexpi(g.ky[j] * r);
+      for (int r = 0; r < ny; ++r) ey[j * ny + r] = C(std::cos(g.ky[j] * r), std::sin(g.ky[j] * r));
   }
   // g(s R) = N_k^{-1} sum_k e^{i s k.R} G(k) for R = (rx, ry), rx in [0, nx), ry in [0, ny)
   // and s = +1 or -1 (the lattice vector R or -R); in indexed k = ix*ny + iy, out R = rx*ny + ry.
@@ -384,10 +472,12 @@ struct Dft {
 //                                                - G^<_{j mbar}(R) G^<_{jbar m}(R)],
 // with lesser and greater swapped for Sigma^>. U(t) is constant here.
 // row: [j][k][comp][a][b]; out: same layout.
-void sigma_row(const Params& p, const Grid& g, int m, const C* row, C* out) {
+template <class R>
+void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const Cx<R>* row, Cx<R>* out) {
+  typedef Cx<R> C;
   int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
-  Dft dft(g);
-  double UU = p.U * p.U;
+  Dft<R> dft(g);
+  R UU = th.U * th.U;
   if (!p.corr) {
     std::fill(out, out + (size_t)(m + 1) * nk * blk, C());
     return;
@@ -407,24 +497,24 @@ void sigma_row(const Params& p, const Grid& g, int m, const C* row, C* out) {
             in[k] = -conj(row[((size_t)j * nk + k) * blk + comp * nbb + b * nb + a]);
           dft.to_real(in.data(), &gb[((comp * nb + a) * nb + b) * nk], -1);
         }
-    auto G = [&](const std::vector<C>& v, int comp, int a, int b, int R) -> C {
-      return v[((comp * nb + a) * nb + b) * nk + R];
+    auto G = [&](const std::vector<C>& v, int comp, int a, int b, int Rv) -> C {
+      return v[((comp * nb + a) * nb + b) * nk + Rv];
     };
     for (int comp = 0; comp < 2; ++comp) {
       int oth = 1 - comp;  // Sigma^< uses G^> on the backward line, and vice versa
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b)
-          for (int R = 0; R < nk; ++R) {
+          for (int Rv = 0; Rv < nk; ++Rv) {
             C s;
             if (p.interaction == INT_HUBBARD) {
-              s = G(gf, comp, a, b, R) * G(gf, comp, a, b, R) * G(gb, oth, b, a, R);
+              s = G(gf, comp, a, b, Rv) * G(gf, comp, a, b, Rv) * G(gb, oth, b, a, Rv);
             } else {
               int ab = 1 - a, bb = 1 - b;
-              C back = G(gb, oth, bb, ab, R);
-              s = back * (G(gf, comp, ab, bb, R) * G(gf, comp, a, b, R) -
-                          G(gf, comp, a, bb, R) * G(gf, comp, ab, b, R));
+              C back = G(gb, oth, bb, ab, Rv);
+              s = back * (G(gf, comp, ab, bb, Rv) * G(gf, comp, a, b, Rv) -
+                          G(gf, comp, a, bb, Rv) * G(gf, comp, ab, b, Rv));
             }
-            sr[((comp * nb + a) * nb + b) * nk + R] = s * UU;
+            sr[((comp * nb + a) * nb + b) * nk + Rv] = scale(s, UU);
           }
     }
     for (int comp = 0; comp < 2; ++comp)
@@ -453,8 +543,9 @@ double trap(int j, int pend) {
 // on the grid with trapezoid weights, for t' = t_0 .. t_m.
 // hist(j, t', k) returns the stored block (j >= t'); blocks above the diagonal come from
 // G(j, t') = -[G(t', j)]^dag.
-template <class Hist>
-void collision_row(const Params& p, const Grid& g, int m, Hist hist, const C* sig, C* Iout) {
+template <class R, class Hist>
+void collision_row(const Params& p, const Grid& g, int m, Hist hist, const Cx<R>* sig, Cx<R>* Iout) {
+  typedef Cx<R> C;
   int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
   double dt = p.dt;
 #pragma omp parallel for schedule(dynamic)
@@ -502,35 +593,40 @@ void collision_row(const Params& p, const Grid& g, int m, Hist hist, const C* si
 //   V = e^{-i hbar dt},  Vh = e^{-i hbar dt/2},  Phi = (V - 1) hbar^{-1} = -i dt phi1(-i hbar dt),
 // so that y(dt) = V y(0) + Phi f solves i dy/dt = hbar y + f exactly for constant f.
 // Computed from the spectral decomposition of hbar.
-void propagators(int nb, double dt, const C* hbar, C* V, C* Vh, C* Phi) {
-  matfun(nb, hbar, [&](double e) { return cexpi(-e * dt); }, V);
-  matfun(nb, hbar, [&](double e) { return cexpi(-e * dt * 0.5); }, Vh);
-  matfun(nb, hbar, [&](double e) {
+template <class R>
+void propagators(int nb, double dt, const Cx<R>* hbar, Cx<R>* V, Cx<R>* Vh, Cx<R>* Phi) {
+  typedef Cx<R> C;
+  matfun(nb, hbar, [&](R e) { return cexpi(-e * dt); }, V);
+  matfun(nb, hbar, [&](R e) { return cexpi(-e * (dt * 0.5)); }, Vh);
+  matfun(nb, hbar, [&](R e) {
     // -i dt sum_n z^n/(n+1)!,  z = -i e dt
-    C z(0.0, -e * dt);
-    if (std::fabs(e * dt) < 1.0) {
+    C z(R(0.0), -e * dt);
+    if (std::fabs(val(e) * dt) < 1.0) {
       C term(1.0), s(1.0);
       for (int n = 1; n < 30; ++n) {
         term = term * z * (1.0 / (n + 1));
         s += term;
       }
-      return C(0.0, -dt) * s;
+      return C(R(0.0), R(-dt)) * s;
     }
-    return (cexpi(-e * dt) - C(1.0)) * (1.0 / e);
+    return scale(cexpi(-e * dt) - C(1.0), R(1.0) / e);
   }, Phi);
 }
 
 // ---------------------------------------------------------------- observables
-void observables(State& st, int m, double* o) {
+template <class R>
+void observables(State<R>& st, int m, R* o) {
+  typedef Cx<R> C;
   const Params& p = st.p;
   const Grid& g = st.g;
   int nb = g.nb, nbb = st.nbb, nk = g.nk;
-  double t = m * p.dt, A = pulse_A(p, t), s = p.spin_deg;
+  double t = m * p.dt, s = p.spin_deg;
+  R A = pulse_A(p, st.th, t);
   std::vector<C> h(nbb), v(nbb), hf(nbb), U(nbb);
-  std::vector<double> w(nb);
-  hf_field(p, g, st.rho_cur, hf.data());
-  double N = 0, Ekin = 0, Ehf = 0, Ecorr = 0, J[2] = {0, 0};
-  std::vector<double> norb(nb, 0.0), nband(nb, 0.0);
+  std::vector<R> w(nb);
+  hf_field(p, st.th, g, st.rho_cur, hf.data());
+  R N = 0.0, Ekin = 0.0, Ehf = 0.0, Ecorr = 0.0, J[2] = {0.0, 0.0};
+  std::vector<R> norb(nb, R(0.0)), nband(nb, R(0.0));
   for (int k = 0; k < nk; ++k) {
     const C* r = &st.rho_cur[k * nbb];
     h0(p, g, st.hop.data(), k, A, h.data());
@@ -544,7 +640,7 @@ void observables(State& st, int m, double* o) {
     }
     // E_corr from the equal-time collision integral I^<(t,t) (Galitskii-Migdal form)
     const C* Ik = &st.I_cur[((size_t)m * nk + k) * st.blk];
-    for (int a = 0; a < nb; ++a) Ecorr += (C(0.0, -0.5) * Ik[a * nb + a]).re;
+    for (int a = 0; a < nb; ++a) Ecorr += (C(R(0.0), R(-0.5)) * Ik[a * nb + a]).re;
     for (int d = 0; d < 2; ++d) {
       vel(p, g, st.hop.data(), k, A, d, v.data());
       for (int a = 0; a < nb; ++a)
@@ -560,20 +656,20 @@ void observables(State& st, int m, double* o) {
   }
   // the interband preset's one-body -U n_c term is part of the single-particle energy
   std::vector<C> ob(nbb);
-  onebody_extra(p, nb, ob.data());
+  onebody_extra(p, st.th, nb, ob.data());
   for (int k = 0; k < nk; ++k)
     for (int a = 0; a < nb; ++a)
       for (int b = 0; b < nb; ++b) Ekin += (ob[a * nb + b] * st.rho_cur[k * nbb + b * nb + a]).re;
   double inv = 1.0 / nk;
-  for (int i = 0; i < NOBS; ++i) o[i] = 0.0;
+  for (int i = 0; i < NOBS; ++i) o[i] = R(0.0);
   o[OBS_T] = t;
-  o[OBS_N] = s * N * inv;
-  o[OBS_EKIN] = s * Ekin * inv;
-  o[OBS_EHF] = 0.5 * s * Ehf * inv;
-  o[OBS_ECORR] = s * Ecorr * inv;
+  o[OBS_N] = N * (s * inv);
+  o[OBS_EKIN] = Ekin * (s * inv);
+  o[OBS_EHF] = Ehf * (0.5 * s * inv);
+  o[OBS_ECORR] = Ecorr * (s * inv);
   o[OBS_ETOT] = o[OBS_EKIN] + o[OBS_EHF] + o[OBS_ECORR];
-  o[OBS_JX] = s * J[0] * inv;
-  o[OBS_JY] = s * J[1] * inv;
+  o[OBS_JX] = J[0] * (s * inv);
+  o[OBS_JY] = J[1] * (s * inv);
   o[OBS_A] = A;
   for (int a = 0; a < nb && a < 4; ++a) o[OBS_NORB + a] = norb[a] * inv;
   for (int b = 0; b < nb && b < 4; ++b) o[OBS_NBAND + b] = nband[b] * inv;
@@ -590,15 +686,17 @@ void observables(State& st, int m, double* o) {
 // (predictor) or (rho_{m-1} + rho_m)/2 (corrector). After the last corrector pass
 // Sigma and I are evaluated once more on the accepted row; they feed the next
 // step's predictor (the algorithm's "Evaluate ... I(t_{n_t-1}, .)").
-void sigma_and_collision(State& st, int m) {
+template <class R>
+void sigma_and_collision(State<R>& st, int m) {
+  typedef Cx<R> C;
   int nk = st.g.nk, blk = st.blk;
   std::vector<C> row((size_t)(m + 1) * nk * blk);
   std::copy(st.rows[m].begin(), st.rows[m].end(), row.begin());
   st.sig.assign((size_t)(m + 1) * nk * blk, C());
-  sigma_row(st.p, st.g, m, row.data(), st.sig.data());
+  sigma_row(st.p, st.th, st.g, m, row.data(), st.sig.data());
   st.I_cur.assign((size_t)(m + 1) * nk * blk, C());
-  collision_row(st.p, st.g, m, [&](int j, int tp, int k) { return (const C*)st.at(j, tp, k); },
-                st.sig.data(), st.I_cur.data());
+  collision_row<R>(st.p, st.g, m, [&](int j, int tp, int k) { return (const C*)st.at(j, tp, k); },
+                   st.sig.data(), st.I_cur.data());
   int nb = st.g.nb, nbb = st.nbb;
   st.D_cur.assign(nk * nbb, C());
   for (int k = 0; k < nk; ++k) {
@@ -608,7 +706,9 @@ void sigma_and_collision(State& st, int m) {
   }
 }
 
-void update_row(State& st, int m, bool corrector) {
+template <class R>
+void update_row(State<R>& st, int m, bool corrector) {
+  typedef Cx<R> C;
   const Params& p = st.p;
   const Grid& g = st.g;
   int nb = g.nb, nbb = st.nbb, blk = st.blk, nk = g.nk;
@@ -616,10 +716,10 @@ void update_row(State& st, int m, bool corrector) {
   for (int i = 0; i < nk * nbb; ++i)
     rho_h[i] = corrector ? (st.rho_prev[i] + st.rho_cur[i]) * 0.5 : st.rho_prev[i];
   std::vector<C> hf(nbb), ob(nbb);
-  hf_field(p, g, rho_h, hf.data());
-  onebody_extra(p, nb, ob.data());
+  hf_field(p, st.th, g, rho_h, hf.data());
+  onebody_extra(p, st.th, nb, ob.data());
   for (int i = 0; i < nbb; ++i) hf[i] += ob[i];
-  double Amid = pulse_A(p, (m - 0.5) * p.dt);
+  R Amid = pulse_A(p, st.th, (m - 0.5) * p.dt);
   std::vector<C> new_rho(nk * nbb);
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < nk; ++k) {
@@ -655,7 +755,8 @@ void update_row(State& st, int m, bool corrector) {
   for (int k = 0; k < nk; ++k) set_diag_block(nb, &st.rho_cur[k * nbb], st.at(m, m, k));
 }
 
-void step(State& st, int m) {
+template <class R>
+void step(State<R>& st, int m) {
   int nk = st.g.nk, blk = st.blk;
   st.rows.emplace_back((size_t)(m + 1) * nk * blk);
   update_row(st, m, false);
@@ -669,9 +770,15 @@ void step(State& st, int m) {
   st.rho_prev = st.rho_cur;
 }
 
-void init(State& st) {
+template <class R>
+void init(State<R>& st) {
+  typedef Cx<R> C;
   int nk = st.g.nk, nbb = st.nbb, blk = st.blk;
-  initial_state(st.p, st.g, st.hop.data(), st.rho_cur);
+  std::vector<Cx<double>> hopd(st.hop.size()), rho0;
+  for (size_t i = 0; i < hopd.size(); ++i) hopd[i] = Cx<double>(val(st.hop[i].re), val(st.hop[i].im));
+  initial_state(st.p, st.g, hopd.data(), rho0);
+  st.rho_cur.assign(rho0.size(), C());
+  for (size_t i = 0; i < rho0.size(); ++i) st.rho_cur[i] = C(R(rho0[i].re), R(rho0[i].im));
   st.rows.clear();
   st.rows.emplace_back((size_t)nk * blk);
   for (int k = 0; k < nk; ++k) set_diag_block(st.g.nb, &st.rho_cur[k * nbb], st.at(0, 0, k));
@@ -680,6 +787,8 @@ void init(State& st) {
   st.I_prev = st.I_cur;
   st.D_prev = st.D_cur;
 }
+
+typedef Cx<double> C;
 
 void to_doubles(const C* src, size_t n, double* dst) {
   for (size_t i = 0; i < n; ++i) { dst[2 * i] = src[i].re; dst[2 * i + 1] = src[i].im; }
@@ -702,7 +811,8 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
                double* hist, double* rho_out) {
   if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
   if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
-  State st(*p, hop);
+  Theta<double> th{p->amp, p->omega, p->U};
+  State<double> st(*p, th, hop);
   init(st);
   if (obs) observables(st, 0, obs);
   for (int m = 1; m <= nsteps; ++m) {
@@ -721,13 +831,46 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
   return 0;
 }
 
+// Tangent-linear run: the same propagation in Dual<3> arithmetic, seeded with the unit
+// directions of (pulse amplitude, pulse frequency, U). obs: (nsteps+1) x NOBS values,
+// dobs: (nsteps+1) x NOBS x 3 derivatives d obs / d(amp, omega, U).
+int oracle_tlm_run(const Params* p, const double* hop, int32_t nsteps, double* obs, double* dobs) {
+  if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
+  if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  Theta<D3> th;
+  th.amp = D3(p->amp);
+  th.amp.d[0] = 1.0;
+  th.omega = D3(p->omega);
+  th.omega.d[1] = 1.0;
+  th.U = D3(p->U);
+  th.U.d[2] = 1.0;
+  State<D3> st(*p, th, hop);
+  init(st);
+  std::vector<D3> o(NOBS);
+  auto emit = [&](int m) {
+    observables(st, m, o.data());
+    for (int i = 0; i < NOBS; ++i) {
+      if (obs) obs[(size_t)m * NOBS + i] = o[i].v;
+      if (dobs)
+        for (int q = 0; q < 3; ++q) dobs[((size_t)m * NOBS + i) * 3 + q] = o[i].d[q];
+    }
+  };
+  emit(0);
+  for (int m = 1; m <= nsteps; ++m) {
+    step(st, m);
+    emit(m);
+  }
+  return 0;
+}
+
 // Sigma on row m: row and out are [j=0..m][k][comp][a][b] complex.
 int oracle_sigma_row(const Params* p, int32_t m, const double* row, double* out) {
   Grid g(*p);
+  Theta<double> th{p->amp, p->omega, p->U};
   size_t n = (size_t)(m + 1) * g.nk * 2 * g.nb * g.nb;
   std::vector<C> r(n), o(n);
   from_doubles(row, n, r.data());
-  sigma_row(*p, g, m, r.data(), o.data());
+  sigma_row(*p, th, g, m, r.data(), o.data());
   to_doubles(o.data(), n, out);
   return 0;
 }
@@ -742,9 +885,9 @@ int oracle_collision_row(const Params* p, int32_t m, const double* hist, const d
   std::vector<C> H(rowoff[m + 1]), S((size_t)(m + 1) * nk * blk), O((size_t)(m + 1) * nk * blk);
   from_doubles(hist, H.size(), H.data());
   from_doubles(sig, S.size(), S.data());
-  collision_row(*p, g, m,
-                [&](int j, int tp, int k) { return (const C*)&H[rowoff[j] + ((size_t)tp * nk + k) * blk]; },
-                S.data(), O.data());
+  collision_row<double>(*p, g, m,
+                        [&](int j, int tp, int k) { return (const C*)&H[rowoff[j] + ((size_t)tp * nk + k) * blk]; },
+                        S.data(), O.data());
   to_doubles(O.data(), O.size(), out);
   return 0;
 }

@@ -61,6 +61,7 @@ def lib():
         _lib.oracle_eigh.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp, dp]
         _lib.oracle_initial_state.argtypes = [P, dp, dp, dp]
         _lib.oracle_h0.argtypes = [P, dp, ctypes.c_double, dp]
+        _lib.oracle_tlm_run.argtypes = [P, dp, ctypes.c_int32, dp, dp]
     return _lib
 
 
@@ -110,6 +111,19 @@ def run(cfg, nsteps: int | None = None, history: bool = False):
             off += sz
         out["rows"] = rows
     return out
+
+
+def tlm_run(cfg, nsteps: int | None = None):
+    """Tangent-linear run (forward-mode dual numbers through the whole propagation).
+    Returns (obs, dobs) with dobs[m, i, q] = d obs[m, i] / d(amp, omega, U)[q]."""
+    n = cfg.nt if nsteps is None else nsteps
+    obs = np.zeros((n + 1, NOBS))
+    dobs = np.zeros((n + 1, NOBS, 3))
+    p = params(cfg)
+    rc = lib().oracle_tlm_run(ctypes.byref(p), _ptr(_hop(cfg)), n, _ptr(obs), _ptr(dobs))
+    if rc != 0:
+        raise ValueError(f"oracle_tlm_run rejected the configuration (rc={rc})")
+    return obs, dobs
 
 
 def sigma_row(cfg, m: int, row: np.ndarray) -> np.ndarray:

@@ -37,8 +37,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
     *why = "k grid must satisfy 1 <= nkx, nky <= 64 and nkx * nky <= 1024";
     return KBE_ERR_SHAPE;
   }
-  if ((4 * c->nkx * c->nky + c->nkx + c->nky) * 16 > 65536) {
-    *why = "k grid too large for the self-energy kernel's LDS tile (4 nk + nkx + nky <= 4096)";
+  if (4 * c->nkx * c->nky * 16 > 65536) {
+    *why = "k grid too large for the self-energy kernel's LDS tile (nkx * nky <= 1024)";
     return KBE_ERR_SHAPE;
   }
   if (c->nt_max < 1 || c->nt_max > 8192) { *why = "nt_max must be 1..8192"; return KBE_ERR_SHAPE; }
@@ -62,7 +62,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
   d.Smax = (c->nt_max + 63) / 64;
   d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
-  d.P = d.fp32 ? kbe::row_off16((int64_t)c->nt_max + 1) : kbe::row_off((int64_t)c->nt_max + 1);
+  d.N = c->nt_max + 1;
+  d.P = kbe::strip_base((d.N + 63) / 64, d.N);
   const size_t cz = sizeof(cplx);
   size_t nk = d.nk;
   size_t sz[B_COUNT];

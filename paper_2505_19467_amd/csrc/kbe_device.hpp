@@ -65,40 +65,33 @@ __device__ __forceinline__ void mm_acc_bdag(cplx* acc, const cplx* A, const cplx
 }
 
 // ------------------------------------------------------------------ layout
-// Packed two-time history: rows padded to 8 elements (128 B) so that every row of every
-// (k, component) plane starts on a cache-line boundary.
-//   rowoff(j) = sum_{i<j} 8 ceil((i+1)/8) = 32 Q (Q+1) + 8 r (Q+1),  Q = j/8, r = j%8.
-__host__ __device__ __forceinline__ int64_t row_off(int64_t j) {
-  int64_t Q = j >> 3, r = j & 7;
-  return 32 * Q * (Q + 1) + 8 * r * (Q + 1);
-}
-// The FP32 history pads rows to 16 elements (also 128 B):
-//   rowoff16(j) = 128 Q (Q+1) + 16 r (Q+1),  Q = j/16, r = j%16.
-__host__ __device__ __forceinline__ int64_t row_off16(int64_t j) {
-  int64_t Q = j >> 4, r = j & 15;
-  return 128 * Q * (Q + 1) + 16 * r * (Q + 1);
-}
-template <typename T>
-__host__ __device__ __forceinline__ int64_t row_off_t(int64_t j) {
-  if constexpr (sizeof(T) == 8) return row_off(j);
-  else return row_off16(j);
-}
+// Packed two-time history, strip-major. Columns t' are grouped in strips of 64; strip s
+// stores the rows j = 64 s .. N-1 (N = nt_max + 1) of its columns as consecutive 64-wide
+// segments, so that the history sums stream every strip of every (k, component) plane as
+// one contiguous run (the entries above the diagonal in a strip's first 64 rows are unused):
+//   elem(j, t') = base(s) + 64 (j - 64 s) + (t' - 64 s),   s = t' / 64,
+//   base(s) = sum_{s' < s} 64 (N - 64 s') = 64 s N - 2048 s (s - 1),
+//   plane length P = base(ceil(N / 64)).
+// The same layout holds complex128 (FP64 form) or complex64 (FP32 form) elements.
+__host__ __device__ __forceinline__ int64_t strip_base(int64_t s, int64_t N) { return 64 * s * N - 2048 * s * (s - 1); }
 
 struct Dims {
   int nkx, nky, nk, nb;
   int nbb, C;      // nb^2, 2 nb^2 complex components per two-time block
+  int N;           // rows of the history (nt_max + 1)
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
   int fp32;        // 1: the packed history is stored in FP32 (complex64)
-  int64_t P;       // padded length of one (k, component) plane of the history (elements)
+  int64_t P;       // length of one (k, component) plane of the history (elements)
 };
 
-// Element index helpers (complex units).
-__host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
-  return ((int64_t)k * d.C + c) * d.P + row_off(j) + tp;
+__host__ __device__ __forceinline__ int64_t tri_off(const Dims& d, int j, int tp) {
+  int s = tp >> 6;
+  return strip_base(s, d.N) + 64 * (int64_t)(j - 64 * s) + (tp & 63);
 }
-__host__ __device__ __forceinline__ int64_t hist32_idx(const Dims& d, int k, int c, int j, int tp) {
-  return ((int64_t)k * d.C + c) * d.P + row_off16(j) + tp;
+// Element index (complex units of the storage type).
+__host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
+  return ((int64_t)k * d.C + c) * d.P + tri_off(d, j, tp);
 }
 // FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
 __host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {

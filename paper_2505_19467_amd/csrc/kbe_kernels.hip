@@ -51,13 +51,13 @@ __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
 // Write one element of the packed history in its storage precision.
 __device__ __forceinline__ void commit_store(const Dims& d, void* hist, int k, int c, int j, int tp, cplx v) {
   if (d.fp32)
-    reinterpret_cast<float2*>(hist)[hist32_idx(d, k, c, j, tp)] = make_float2((float)v.x, (float)v.y);
+    reinterpret_cast<float2*>(hist)[hist_idx(d, k, c, j, tp)] = make_float2((float)v.x, (float)v.y);
   else
     reinterpret_cast<cplx*>(hist)[hist_idx(d, k, c, j, tp)] = v;
 }
 __device__ __forceinline__ cplx history_load(const Dims& d, const void* hist, int k, int c, int j, int tp) {
   if (d.fp32) {
-    float2 v = reinterpret_cast<const float2*>(hist)[hist32_idx(d, k, c, j, tp)];
+    float2 v = reinterpret_cast<const float2*>(hist)[hist_idx(d, k, c, j, tp)];
     return make_double2((double)v.x, (double)v.y);
   }
   return reinterpret_cast<const cplx*>(hist)[hist_idx(d, k, c, j, tp)];
@@ -278,6 +278,45 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
 }
 
 // ------------------------------------------------------------------ self-energy
+// 1D DFTs of the lines of two n x n' arrays held in LDS, in place into `out`:
+//   out[line][q] = scale * sum_p in[line][p] w^{p q},  w = e^{sgn 2 pi i / n},
+// line element p at base(line) + p * stride. A work item is (array, line, group of 8
+// outputs); its 8 outputs are evaluated as 8 Horner chains in z_q = w^q, so that every
+// LDS read of an input feeds 8 outputs and no twiddle table is read.
+__device__ __forceinline__ void dft_lines(const cplx* __restrict__ in0, const cplx* __restrict__ in1,
+                                          cplx* __restrict__ out0, cplx* __restrict__ out1, int n, int nlines,
+                                          int line_mul, int stride, int sgn, double scale) {
+  constexpr int Q = 8;
+  int groups = (n + Q - 1) / Q;
+  int items = 2 * nlines * groups;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    int arr = it / (nlines * groups);
+    int rem = it - arr * nlines * groups;
+    int line = rem / groups, g = rem - (rem / groups) * groups;
+    const cplx* x = (arr ? in1 : in0) + line * line_mul;
+    cplx* y = (arr ? out1 : out0) + line * line_mul;
+    cplx z[Q], acc[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      int q = g * Q + r;
+      double sn, cs;
+      sincospi(2.0 * (double)(q < n ? q : 0) / (double)n, &sn, &cs);
+      z[r] = cmk(cs, sgn * sn);
+      acc[r] = czero();
+    }
+    for (int p = n - 1; p >= 0; --p) {
+      cplx v = x[p * stride];
+#pragma unroll
+      for (int r = 0; r < Q; ++r) acc[r] = cadd(cmul(acc[r], z[r]), v);
+    }
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      int q = g * Q + r;
+      if (q < n) y[q * stride] = cscal(acc[r], scale);
+    }
+  }
+}
+
 // One block per (t_j, orbital pair ab) of row m. With plain index transforms
 //   g(R) = N_k^{-1} sum_j e^{+2 pi i j.R / n} G(k_j),   S(k_j) = sum_R e^{-2 pi i j.R / n} S(R),
 // the -pi offset of eq. (kj) cancels in the product of two forward lines and one backward
@@ -294,8 +333,6 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
   cplx* gg = lds + d.nk;
   cplx* tl = lds + 2 * d.nk;
   cplx* tg = lds + 3 * d.nk;
-  cplx* twx = lds + 4 * d.nk;          // e^{2 pi i p / nkx}
-  cplx* twy = twx + d.nkx;             // e^{2 pi i p / nky}
   int total = (m + 1) * NBB;
   int per = (total + 7) >> 3;
   int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -303,46 +340,18 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
   int j = item / NBB, ab = item - (item / NBB) * NBB;
   int t = threadIdx.x;
   int nx = d.nkx, ny = d.nky, nk = d.nk;
-  for (int p = t; p < nx; p += 256) {
-    double sn, cs;
-    sincospi(2.0 * p / nx, &sn, &cs);
-    twx[p] = cmk(cs, sn);
-  }
-  for (int p = t; p < ny; p += 256) {
-    double sn, cs;
-    sincospi(2.0 * p / ny, &sn, &cs);
-    twy[p] = cmk(cs, sn);
-  }
   for (int k = t; k < nk; k += 256) {
     gl[k] = row64[row64_idx(d, m, k, ab, j)];
     gg[k] = row64[row64_idx(d, m, k, NBB + ab, j)];
   }
   __syncthreads();
-  // k -> R along y: t[ix][ry] = sum_iy e^{+2 pi i iy ry / ny} g[ix][iy]
-  for (int o = t; o < nk; o += 256) {
-    int ix = o / ny, ry = o - (o / ny) * ny;
-    cplx al = czero(), ag = czero();
-    for (int iy = 0; iy < ny; ++iy) {
-      cplx w = twy[(iy * ry) % ny];
-      cmac(al, gl[ix * ny + iy], w);
-      cmac(ag, gg[ix * ny + iy], w);
-    }
-    tl[o] = al;
-    tg[o] = ag;
-  }
+  // k -> R: along y (lines ix, contiguous), then along x (lines ry, stride ny), 1/N_k
+  dft_lines(gl, gg, tl, tg, ny, nx, ny, 1, +1, 1.0);
   __syncthreads();
-  // along x, normalise, pointwise second-Born products
-  double inv = 1.0 / nk;
+  dft_lines(tl, tg, gl, gg, nx, ny, 1, ny, +1, 1.0 / nk);
+  __syncthreads();
   for (int o = t; o < nk; o += 256) {
-    int rx = o / ny, ry = o - (o / ny) * ny;
-    cplx al = czero(), ag = czero();
-    for (int ix = 0; ix < nx; ++ix) {
-      cplx w = twx[(ix * rx) % nx];
-      cmac(al, tl[ix * ny + ry], w);
-      cmac(ag, tg[ix * ny + ry], w);
-    }
-    al = cscal(al, inv);
-    ag = cscal(ag, inv);
+    cplx al = gl[o], ag = gg[o];
     cplx sl = czero(), sg = czero();
     if (corr) {
       sl = cscal(cmul(cmul(al, al), cconj(ag)), -UU);
@@ -352,27 +361,13 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
     gg[o] = sg;
   }
   __syncthreads();
-  // R -> k along y: t[rx][iy] = sum_ry e^{-2 pi i iy ry / ny} S[rx][ry]
-  for (int o = t; o < nk; o += 256) {
-    int rx = o / ny, iy = o - (o / ny) * ny;
-    cplx al = czero(), ag = czero();
-    for (int ry = 0; ry < ny; ++ry) {
-      cplx w = cconj(twy[(iy * ry) % ny]);
-      cmac(al, gl[rx * ny + ry], w);
-      cmac(ag, gg[rx * ny + ry], w);
-    }
-    tl[o] = al;
-    tg[o] = ag;
-  }
+  // R -> k: along y, then along x
+  dft_lines(gl, gg, tl, tg, ny, nx, ny, 1, -1, 1.0);
+  __syncthreads();
+  dft_lines(tl, tg, gl, gg, nx, ny, 1, ny, -1, 1.0);
   __syncthreads();
   for (int o = t; o < nk; o += 256) {
-    int ix = o / ny, iy = o - (o / ny) * ny;
-    cplx al = czero(), ag = czero();
-    for (int rx = 0; rx < nx; ++rx) {
-      cplx w = cconj(twx[(ix * rx) % nx]);
-      cmac(al, tl[rx * ny + iy], w);
-      cmac(ag, tg[rx * ny + iy], w);
-    }
+    cplx al = gl[o], ag = gg[o];
     sig[sig_idx(d, o, 0, ab, j)] = al;
     sig[sig_idx(d, o, 1, ab, j)] = ag;
     sig[sig_idx(d, o, 2, ab, j)] = csub(ag, al);
@@ -481,13 +476,14 @@ __device__ __forceinline__ double row16_sum(double x) {
 
 // History blocks are read once per pass: stream them past the caches.
 typedef double kbe_d2v __attribute__((ext_vector_type(2)));
+typedef float kbe_f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ cplx load_stream(const cplx* p) {
-#if KBE_BULK_NT
   kbe_d2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_d2v*>(p));
   return make_double2(v.x, v.y);
-#else
-  return *p;
-#endif
+}
+__device__ __forceinline__ float2 load_stream32(const float2* p) {
+  kbe_f2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_f2v*>(p));
+  return make_float2(v.x, v.y);
 }
 
 // Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
@@ -510,23 +506,37 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int CH = (C < 8) ? C : 8;  // components per LDS combine round
   constexpr int R = NB == 1 ? 4 : (NB == 2 ? 2 : 1);  // rows per wavefront iteration
+  // nb >= 3: the per-column Sigma of the row term lives in LDS instead of registers
+  constexpr bool SLDS = NB >= 3;
+  constexpr int NS = SLDS ? NBB : 1;
   __shared__ cplx red[3][CH][64];
+  __shared__ cplx sS[2][NS][64];
   int s = blockIdx.x / d.nk;  // strips with the most rows first
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int tp = 64 * s + lane;
   bool colv = tp < m;
   const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
-  cplx Sl[NBB], Sg[NBB];
+  cplx Sl[SLDS ? 1 : NBB], Sg[SLDS ? 1 : NBB];
+  if constexpr (SLDS) {
+    for (int i = threadIdx.x; i < 2 * NBB * 64; i += 256) {
+      int x = i / (NBB * 64), e = (i / 64) % NBB, l = i % 64;
+      int t = 64 * s + l;
+      sS[x][e][l] = t < m ? sk[(x * NBB + e) * d.Tp + t] : czero();
+    }
+    __syncthreads();
+  } else {
 #pragma unroll
-  for (int e = 0; e < NBB; ++e) {
-    Sl[e] = colv ? sk[(0 * NBB + e) * d.Tp + tp] : czero();
-    Sg[e] = colv ? sk[(1 * NBB + e) * d.Tp + tp] : czero();
+    for (int e = 0; e < NBB; ++e) {
+      Sl[e] = colv ? sk[(0 * NBB + e) * d.Tp + tp] : czero();
+      Sg[e] = colv ? sk[(1 * NBB + e) * d.Tp + tp] : czero();
+    }
   }
   cplx acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
-  const cplx* hk = hist + (int64_t)k * C * d.P + tp;
+  // strip s of every component plane of k: rows j >= 64 s as consecutive 64-wide segments
+  const cplx* hk = hist + (int64_t)k * C * d.P + strip_base(s, d.N) + lane - 64 * 64 * (int64_t)s;
   cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
     cplx G[R][C];
@@ -534,7 +544,7 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
     for (int r = 0; r < R; ++r) {
       int j = jb + r;
       bool v = colv && tp <= j && j < m;
-      int64_t off = row_off(j);
+      int64_t off = 64 * (int64_t)j;
 #pragma unroll
       for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream(hk + (int64_t)c * d.P + off) : czero();
     }
@@ -548,16 +558,33 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
       for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
       mm_acc<NB>(acc, SR, G[r]);
       mm_acc<NB>(acc + NBB, SR, G[r] + NBB);
-      cplx a[NBB], u[NBB];
-      mat_zero<NB>(a);
-      mat_zero<NB>(u);
-      mm_acc_bdag<NB>(a, Sl, G[r] + NBB);
-      mm_acc_bdag<NB>(u, Sg, G[r]);
       bool rv = tp < j;
+      if constexpr (SLDS) {
 #pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        rt[r][2 * e] = rv ? a[e].x - u[e].x : 0.0;
-        rt[r][2 * e + 1] = rv ? a[e].y - u[e].y : 0.0;
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            cplx a = czero(), u = czero();
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+              cmacc(a, sS[0][i * NB + l][lane], G[r][NBB + jj * NB + l]);
+              cmacc(u, sS[1][i * NB + l][lane], G[r][jj * NB + l]);
+            }
+            int e = i * NB + jj;
+            rt[r][2 * e] = rv ? a.x - u.x : 0.0;
+            rt[r][2 * e + 1] = rv ? a.y - u.y : 0.0;
+          }
+      } else {
+        cplx a[NBB], u[NBB];
+        mat_zero<NB>(a);
+        mat_zero<NB>(u);
+        mm_acc_bdag<NB>(a, Sl, G[r] + NBB);
+        mm_acc_bdag<NB>(u, Sg, G[r]);
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) {
+          rt[r][2 * e] = rv ? a[e].x - u[e].x : 0.0;
+          rt[r][2 * e + 1] = rv ? a[e].y - u[e].y : 0.0;
+        }
       }
     }
     // reduce-scatter over the 64 lanes; afterwards lane groups hold whole-row sums:
@@ -682,7 +709,7 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
     acc[c] = czero();
     acc32[c] = make_float2(0.f, 0.f);
   }
-  const cplx32* hk = hist + (int64_t)k * C * d.P + tp;
+  const cplx32* hk = hist + (int64_t)k * C * d.P + strip_base(s, d.N) + lane - 64 * 64 * (int64_t)s;
   cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
   int it = 0;
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
@@ -691,9 +718,9 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
     for (int r = 0; r < R; ++r) {
       int j = jb + r;
       bool v = colv && tp <= j && j < m;
-      int64_t off = row_off16(j);
+      int64_t off = 64 * (int64_t)j;
 #pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = v ? hk[(int64_t)c * d.P + off] : make_float2(0.f, 0.f);
+      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream32(hk + (int64_t)c * d.P + off) : make_float2(0.f, 0.f);
     }
     float rt[R][2 * NBB];
 #pragma unroll
@@ -1115,7 +1142,7 @@ struct Launch {
   static hipError_t sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     int total = (m + 1) * NB * NB;
     int per = (total + 7) / 8;
-    size_t shm = (size_t)(4 * d.nk + d.nkx + d.nky) * sizeof(cplx);
+    size_t shm = (size_t)(4 * d.nk) * sizeof(cplx);
     hipLaunchKernelGGL(k_sigma<NB>, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.row64, a.sig, m, a.UU,
                        a.corr);
     return hipGetLastError();

@@ -95,14 +95,24 @@ def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
     return h.value, w.value, o.value
 
 
-def row_off(j: int, fp32: bool = False) -> int:
-    """Start of row j inside a (k, component) plane of the packed history (include/kbe.h):
-    rows padded to 8 complex128 (FP64 form) or 16 complex64 (FP32 form) elements."""
-    if fp32:
-        Q, r = j >> 4, j & 15
-        return 128 * Q * (Q + 1) + 16 * r * (Q + 1)
-    Q, r = j >> 3, j & 7
-    return 32 * Q * (Q + 1) + 8 * r * (Q + 1)
+def strip_base(s: int, N: int) -> int:
+    return 64 * s * N - 2048 * s * (s - 1)
+
+
+def plane_length(nt_max: int) -> int:
+    """Length P of one (k, component) plane of the packed history (include/kbe.h)."""
+    N = nt_max + 1
+    return strip_base((N + 63) // 64, N)
+
+
+def tri_off(j, tp, nt_max: int):
+    """Position of element (t_j, t'_tp), tp <= j, inside a plane (strip-major layout);
+    works elementwise on numpy integer arrays."""
+    N = nt_max + 1
+    j = np.asarray(j, dtype=np.int64)
+    tp = np.asarray(tp, dtype=np.int64)
+    s = tp >> 6
+    return 64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s) + (tp & 63)
 
 
 class System:
@@ -122,7 +132,7 @@ class System:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.nk, self.nb = cfg.nk, cfg.nb
         self.C = 2 * cfg.nb * cfg.nb
-        self.P = row_off(self.nt_max + 1, self.fp32)
+        self.P = plane_length(self.nt_max)
         self.Tp = ((self.nt_max + 1 + 7) // 8) * 8
         self._ctx = None
         self._create()
@@ -215,18 +225,20 @@ class System:
         complex64 (FP32 form)."""
         return self.history.view(self.nk, self.C, self.P)
 
+    def _row_index(self, j: int) -> torch.Tensor:
+        idx = tri_off(j, np.arange(j + 1), self.nt_max)
+        return torch.from_numpy(idx).to(self.history.device)
+
     def history_row(self, j: int) -> torch.Tensor:
         """Row j as a [t'][k][</>][a][b] tensor (copy, in the storage precision)."""
         nb = self.nb
-        o = row_off(j, self.fp32)
-        h = self.history_planes()[:, :, o:o + j + 1]   # [k][c][t']
+        h = self.history_planes().index_select(2, self._row_index(j))   # [k][c][t']
         return h.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
 
     def set_history_row(self, j: int, row: torch.Tensor):
         """Write row j from a [t'][k][</>][a][b] tensor (cast to the storage precision)."""
-        o = row_off(j, self.fp32)
-        src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0)
-        self.history_planes()[:, :, o:o + j + 1].copy_(src)
+        src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0).to(self.history.dtype)
+        self.history_planes().index_copy_(2, self._row_index(j), src.contiguous())
 
     def row64(self, j: int) -> torch.Tensor:
         """FP64 working copy of history row j (j = m-1 or m of the current step), as a

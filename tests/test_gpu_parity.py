@@ -256,8 +256,7 @@ def test_collision_full_size_sampled(K):
         assert planes.dtype == np.complex128
         rows = []
         for j in range(m + 1):
-            o = K.row_off(j)
-            blk = planes[:, o:o + j + 1]                      # [C][t']
+            blk = planes[:, K.tri_off(j, np.arange(j + 1), m)]  # [C][t']
             rows.append(blk.T.reshape(j + 1, 1, 2, nb, nb))
         ref = O.collision_row(one, m, rows, sig_all[:, k:k + 1])
         err = relerr(got_all[:, k:k + 1], ref)
@@ -273,8 +272,10 @@ def test_sigma_full_size_sampled(K):
     m = cfg.nt
     _say(f"full-size sigma m={m}")
     S = K.System(cfg)
-    row = S.history_planes()[:, :, K.row_off(m):K.row_off(m) + m + 1]
+    import torch
+    row = torch.empty((S.nk, S.C, m + 1), dtype=torch.complex128, device="cuda")
     inputs.fill_normal_(row, seed=77, scale=0.4)
+    S.set_history_row(m, row.permute(2, 0, 1))
     S.rebuild_aux(m)
     S.stage_sigma(m)
     sig = S.sigma_row(m).cpu().numpy()

@@ -279,3 +279,39 @@ def test_corrector_count_changes_at_higher_order():
     d12 = np.abs(r1["obs"][-1] - r2["obs"][-1]).max()
     dfine = np.abs(r1["obs"][-1] - r_fine["obs"][-1]).max()
     assert d12 < dfine
+
+
+# ---------------------------------------------------------------- tangent-linear reference
+def test_tlm_values_equal_plain_run():
+    """The dual-number run's value part is the plain FP64 oracle, bit for bit."""
+    cfg = inputs.c1().replace(nkx=4)
+    obs, _ = O.tlm_run(cfg, 30)
+    ref = O.run(cfg, 30)["obs"]
+    assert np.array_equal(obs, ref)
+
+
+@pytest.mark.parametrize("cfg_name", ["c1", "c4"])
+def test_tlm_matches_central_differences(cfg_name):
+    """d n_upper(T) / d(A0, omega, U) from the tangent-linear run against central finite
+    differences (h = 1e-5, error O(h^2) ~ 1e-10 relative)."""
+    base = inputs.WORKLOADS[cfg_name]()
+    base = base.replace(nkx=4, nky=1 if base.nky == 1 else 3, dt=0.05)
+    n = 60
+    obs, dobs = O.tlm_run(base, n)
+    i = O.OBS["n_band1"]
+    h = 1e-5
+    fd = []
+    for q, name in enumerate(("amp", "omega", "U")):
+        def val(x):
+            if name == "U":
+                c = base.replace(U=x)
+            else:
+                pu = base.pulse
+                c = base.replace(pulse=inputs.Pulse(**{**pu.__dict__, name: x}))
+            return O.run(c, n)["obs"][-1, i]
+        x0 = base.U if name == "U" else getattr(base.pulse, name)
+        fd.append((val(x0 + h) - val(x0 - h)) / (2 * h))
+    fd = np.array(fd)
+    tlm = dobs[-1, i]
+    assert np.all(np.abs(tlm - fd) <= 1e-6 * np.abs(fd).max() + 1e-12), (tlm, fd)
+    assert np.abs(tlm).min() > 0  # every parameter moves the observable

@@ -82,6 +82,7 @@ typedef struct {
   int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes */
   int32_t nt_max;       /* largest step index the buffers hold */
   int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
+  int32_t adjoint;      /* 1: keep the per-step record (rho_m, D_m) the adjoint needs */
   double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
 } kbe_config;
 

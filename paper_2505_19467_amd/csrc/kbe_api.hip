@@ -20,7 +20,7 @@ namespace {
 
 enum {
   B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
-  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_COUNT
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_RHOALL, B_DALL, B_COUNT
 };
 
 struct Layout {
@@ -79,6 +79,10 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_EIGU] = nk * d.nbb * cz;
   sz[B_MU] = sizeof(double);
   sz[B_ROW64] = 2 * nk * d.C * d.Tp * cz;
+  // per-step record of rho_m and D_m, kept only when the adjoint will be run
+  size_t rec = c->adjoint ? (size_t)(c->nt_max + 1) * nk * d.nbb * cz : 0;
+  sz[B_RHOALL] = rec;
+  sz[B_DALL] = rec;
   size_t off = 0;
   for (int i = 0; i < B_COUNT; ++i) {
     L->off[i] = off;
@@ -142,6 +146,9 @@ struct kbe_ctx {
     a.eig_U = buf<cplx>(B_EIGU);
     a.mu = buf<double>(B_MU);
     a.obs = obs;
+    a.rho_save = nullptr;
+    a.D_save = nullptr;
+    a.commit = 1;
     a.Ax = a.Ay = 0.0;
     a.dt = cfg.dt;
     a.U = cfg.U;
@@ -205,10 +212,14 @@ struct kbe_ctx {
     set_A(a, t);
     return check(kbe::launch_obs(L.d, a, m, t, pulse_A(pulse, t), st), "observables launch");
   }
+  cplx* rec_rho(int m) const { return cfg.adjoint ? buf<cplx>(B_RHOALL) + (size_t)m * L.d.nk * L.d.nbb : nullptr; }
+  cplx* rec_D(int m) const { return cfg.adjoint ? buf<cplx>(B_DALL) + (size_t)m * L.d.nk * L.d.nbb : nullptr; }
   int one_step() {
     int m = step + 1;
     if (m > cfg.nt_max) return fail(KBE_ERR_STATE, "step index would pass nt_max");
     LaunchArgs a = args();
+    a.rho_save = rec_rho(m);
+    a.D_save = rec_D(m);
     int rc = props(a, m, 0);
     if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_PREDICT, st), "predictor launch");
     for (int it = 0; it < cfg.n_corr && !rc; ++it) {
@@ -281,6 +292,12 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
     rc = c->check(kbe::launch_init(d, a, c->st), "initial-state launch");
   }
   if (!rc) rc = c->observe(0);
+  if (!rc && cfg->adjoint) {
+    // record of t_0: rho_0 and D_0 = 0
+    rc = c->check(hipMemcpyAsync(c->rec_rho(0), c->buf<cplx>(B_RHOA), c->L.bytes[B_RHOA], hipMemcpyDeviceToDevice, c->st),
+                  "rho_0 record");
+    if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->rec_D(0), 2 * (size_t)d.nk * d.nbb, c->st), "zero");
+  }
   if (!rc) rc = c->check(hipStreamSynchronize(c->st), "initial state");
   if (rc) {
     delete c;

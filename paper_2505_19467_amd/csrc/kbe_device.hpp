@@ -233,4 +233,116 @@ __device__ void jacobi_eigh(cplx* A, double* w, cplx* V) {
     }
 }
 
+// ------------------------------------------------------------------ block reductions
+template <int N>
+__device__ __forceinline__ void block_sum_cplx(cplx* v, cplx* lds /* [N][256] */) {
+  int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) lds[i * 256 + t] = v[i];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) lds[i * 256 + t] = cadd(lds[i * 256 + t], lds[i * 256 + t + s]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = lds[i * 256];
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+
+// Cross-lane helpers on doubles (two 32-bit halves). gfx950's permlane swaps exchange
+// half-waves / 16-lane rows between two registers on the VALU, DPP moves within rows.
+__device__ __forceinline__ void dsplit(double x, unsigned& lo, unsigned& hi) {
+  unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  lo = (unsigned)u;
+  hi = (unsigned)(u >> 32);
+}
+__device__ __forceinline__ double djoin(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// a <- [a_lo + a_hi | b_lo + b_hi] over the two half-waves (lanes l and l+32)
+__device__ __forceinline__ double rs_half(double a, double b) {
+  unsigned al, ah, bl, bh;
+  dsplit(a, al, ah);
+  dsplit(b, bl, bh);
+  auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+  auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
+}
+// rows of 16 lanes: a = [a0 a1 a2 a3], b = [b0 b1 b2 b3] -> [a0+a1, b0+b1, a2+a3, b2+b3]
+__device__ __forceinline__ double rs_row(double a, double b) {
+  unsigned al, ah, bl, bh;
+  dsplit(a, al, ah);
+  dsplit(b, bl, bh);
+  auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+  auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  unsigned lo, hi;
+  dsplit(x, lo, hi);
+  lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xF, 0xF, false);
+  hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xF, 0xF, false);
+  return djoin(lo, hi);
+}
+// sum over the 16 lanes of each row, result in every lane of the row
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_d<0x141>(x);  // row_half_mirror
+  x += dpp_d<0x140>(x);  // row_mirror
+  return x;
+}
+
+
+// 1D DFTs of the lines of two n x n' arrays held in LDS, in place into `out`:
+//   out[line][q] = scale * sum_p in[line][p] w^{p q},  w = e^{sgn 2 pi i / n},
+// line element p at base(line) + p * stride. A work item is (array, line, group of 8
+// outputs); its 8 outputs are evaluated as 8 Horner chains in z_q = w^q, so that every
+// LDS read of an input feeds 8 outputs and no twiddle table is read.
+__device__ __forceinline__ void dft_lines(const cplx* __restrict__ in0, const cplx* __restrict__ in1,
+                                          cplx* __restrict__ out0, cplx* __restrict__ out1, int n, int nlines,
+                                          int line_mul, int stride, int sgn, double scale) {
+  constexpr int Q = 8;
+  int groups = (n + Q - 1) / Q;
+  int items = 2 * nlines * groups;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    int arr = it / (nlines * groups);
+    int rem = it - arr * nlines * groups;
+    int line = rem / groups, g = rem - (rem / groups) * groups;
+    const cplx* x = (arr ? in1 : in0) + line * line_mul;
+    cplx* y = (arr ? out1 : out0) + line * line_mul;
+    cplx z[Q], acc[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      int q = g * Q + r;
+      double sn, cs;
+      sincospi(2.0 * (double)(q < n ? q : 0) / (double)n, &sn, &cs);
+      z[r] = cmk(cs, sgn * sn);
+      acc[r] = czero();
+    }
+    for (int p = n - 1; p >= 0; --p) {
+      cplx v = x[p * stride];
+#pragma unroll
+      for (int r = 0; r < Q; ++r) acc[r] = cadd(cmul(acc[r], z[r]), v);
+    }
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      int q = g * Q + r;
+      if (q < n) y[q * stride] = cscal(acc[r], scale);
+    }
+  }
+}
+
+
 }  // namespace kbe

@@ -16,31 +16,6 @@
 
 namespace kbe {
 
-// ------------------------------------------------------------------ block reductions
-template <int N>
-__device__ __forceinline__ void block_sum_cplx(cplx* v, cplx* lds /* [N][256] */) {
-  int t = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < N; ++i) lds[i * 256 + t] = v[i];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) lds[i * 256 + t] = cadd(lds[i * 256 + t], lds[i * 256 + t + s]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = lds[i * 256];
-  __syncthreads();
-}
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
 // ------------------------------------------------------------------ utility
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,45 +253,6 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
 }
 
 // ------------------------------------------------------------------ self-energy
-// 1D DFTs of the lines of two n x n' arrays held in LDS, in place into `out`:
-//   out[line][q] = scale * sum_p in[line][p] w^{p q},  w = e^{sgn 2 pi i / n},
-// line element p at base(line) + p * stride. A work item is (array, line, group of 8
-// outputs); its 8 outputs are evaluated as 8 Horner chains in z_q = w^q, so that every
-// LDS read of an input feeds 8 outputs and no twiddle table is read.
-__device__ __forceinline__ void dft_lines(const cplx* __restrict__ in0, const cplx* __restrict__ in1,
-                                          cplx* __restrict__ out0, cplx* __restrict__ out1, int n, int nlines,
-                                          int line_mul, int stride, int sgn, double scale) {
-  constexpr int Q = 8;
-  int groups = (n + Q - 1) / Q;
-  int items = 2 * nlines * groups;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    int arr = it / (nlines * groups);
-    int rem = it - arr * nlines * groups;
-    int line = rem / groups, g = rem - (rem / groups) * groups;
-    const cplx* x = (arr ? in1 : in0) + line * line_mul;
-    cplx* y = (arr ? out1 : out0) + line * line_mul;
-    cplx z[Q], acc[Q];
-#pragma unroll
-    for (int r = 0; r < Q; ++r) {
-      int q = g * Q + r;
-      double sn, cs;
-      sincospi(2.0 * (double)(q < n ? q : 0) / (double)n, &sn, &cs);
-      z[r] = cmk(cs, sgn * sn);
-      acc[r] = czero();
-    }
-    for (int p = n - 1; p >= 0; --p) {
-      cplx v = x[p * stride];
-#pragma unroll
-      for (int r = 0; r < Q; ++r) acc[r] = cadd(cmul(acc[r], z[r]), v);
-    }
-#pragma unroll
-    for (int r = 0; r < Q; ++r) {
-      int q = g * Q + r;
-      if (q < n) y[q * stride] = cscal(acc[r], scale);
-    }
-  }
-}
-
 // One block per (t_j, orbital pair ab) of row m. With plain index transforms
 //   g(R) = N_k^{-1} sum_j e^{+2 pi i j.R / n} G(k_j),   S(k_j) = sum_R e^{-2 pi i j.R / n} S(R),
 // the -pi offset of eq. (kj) cancels in the product of two forward lines and one backward
@@ -381,7 +317,8 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
 template <int NB>
 __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ row64,
                                                 const cplx* __restrict__ sig, cplx* __restrict__ Icur,
-                                                cplx* __restrict__ Dcur, int m, double dt) {
+                                                cplx* __restrict__ Dcur, int m, double dt,
+                                                cplx* __restrict__ D_save) {
   constexpr int NBB = NB * NB;
   __shared__ cplx lds[NBB * 256];
   int k = blockIdx.x;
@@ -423,57 +360,14 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
         cplx I = cscal(acc[a * NB + b], dt);
         Icur[rowbuf_idx(d, k, a * NB + b, m)] = I;
         Icur[rowbuf_idx(d, k, NBB + a * NB + b, m)] = I;
-        Dcur[(int64_t)k * NBB + a * NB + b] = cadd(cscal(acc[a * NB + b], dt), cconj(cscal(acc[b * NB + a], dt)));
+        cplx Dv = cadd(cscal(acc[a * NB + b], dt), cconj(cscal(acc[b * NB + a], dt)));
+        Dcur[(int64_t)k * NBB + a * NB + b] = Dv;
+        if (D_save) D_save[(int64_t)k * NBB + a * NB + b] = Dv;
       }
   }
 }
 
 // ------------------------------------------------------------------ history sums (hot loop)
-// Cross-lane helpers on doubles (two 32-bit halves). gfx950's permlane swaps exchange
-// half-waves / 16-lane rows between two registers on the VALU, DPP moves within rows.
-__device__ __forceinline__ void dsplit(double x, unsigned& lo, unsigned& hi) {
-  unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-  lo = (unsigned)u;
-  hi = (unsigned)(u >> 32);
-}
-__device__ __forceinline__ double djoin(unsigned lo, unsigned hi) {
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-// a <- [a_lo + a_hi | b_lo + b_hi] over the two half-waves (lanes l and l+32)
-__device__ __forceinline__ double rs_half(double a, double b) {
-  unsigned al, ah, bl, bh;
-  dsplit(a, al, ah);
-  dsplit(b, bl, bh);
-  auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
-  auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
-  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
-}
-// rows of 16 lanes: a = [a0 a1 a2 a3], b = [b0 b1 b2 b3] -> [a0+a1, b0+b1, a2+a3, b2+b3]
-__device__ __forceinline__ double rs_row(double a, double b) {
-  unsigned al, ah, bl, bh;
-  dsplit(a, al, ah);
-  dsplit(b, bl, bh);
-  auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
-  auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
-  return djoin(l[0], h[0]) + djoin(l[1], h[1]);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double x) {
-  unsigned lo, hi;
-  dsplit(x, lo, hi);
-  lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xF, 0xF, false);
-  hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xF, 0xF, false);
-  return djoin(lo, hi);
-}
-// sum over the 16 lanes of each row, result in every lane of the row
-__device__ __forceinline__ double row16_sum(double x) {
-  x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp_d<0x141>(x);  // row_half_mirror
-  x += dpp_d<0x140>(x);  // row_mirror
-  return x;
-}
-
 // History blocks are read once per pass: stream them past the caches.
 typedef double kbe_d2v __attribute__((ext_vector_type(2)));
 typedef float kbe_f2v __attribute__((ext_vector_type(2)));
@@ -830,7 +724,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              cplx* __restrict__ Icur, const cplx* __restrict__ props,
                                              const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
                                              const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
-                                             double dt) {
+                                             double dt, int commit, cplx* __restrict__ rho_save) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   int k = blockIdx.y;
   int tp = blockIdx.x * 256 + threadIdx.x;
@@ -942,8 +836,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         for (int e = 0; e < NBB; ++e) {
           int c = sc * NBB + e;
           row64[row64_idx(d, m, k, c, tp)] = g[e];
-          commit_store(d, hist, k, c, m, tp, g[e]);
-          if (tp == 0) col0[rowbuf_idx(d, k, c, m)] = g[e];
+          if (commit) {
+            commit_store(d, hist, k, c, m, tp, g[e]);
+            if (tp == 0) col0[rowbuf_idx(d, k, c, m)] = g[e];
+          }
         }
       }
     }
@@ -973,6 +869,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         int e = a * NB + b;
         cplx rv = csub(rho[e], cscal(t2[e], dt));
         rho_cur[(int64_t)k * NBB + e] = rv;
+        if (rho_save) rho_save[(int64_t)k * NBB + e] = rv;
         cplx g[2];
         g[0] = cmuli(rv);
         g[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
@@ -980,8 +877,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         for (int sc = 0; sc < 2; ++sc) {
           int c = sc * NBB + e;
           row64[row64_idx(d, m, k, c, m)] = g[sc];
-          commit_store(d, hist, k, c, m, m, g[sc]);
-          diag[rowbuf_idx(d, k, c, m)] = g[sc];
+          if (commit) {
+            commit_store(d, hist, k, c, m, m, g[sc]);
+            diag[rowbuf_idx(d, k, c, m)] = g[sc];
+          }
         }
       }
   }
@@ -1149,7 +1048,7 @@ struct Launch {
   }
   static hipError_t diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.row64, (const cplx*)a.sig,
-                       a.I_cur, a.D_cur, m, a.dt);
+                       a.I_cur, a.D_cur, m, a.dt, a.D_save);
     return hipGetLastError();
   }
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
@@ -1168,7 +1067,7 @@ struct Launch {
 #define KBE_ROW_ARGS                                                                                      \
   d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
-      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt
+      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit, a.rho_save
     if (mode == KBE_ROW_PREDICT)
       hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
     else if (mode == KBE_ROW_CORRECT)

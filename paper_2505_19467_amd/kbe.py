@@ -37,7 +37,8 @@ BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_C
 
 class KbeConfig(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision")] + \
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision",
+                 "adjoint")] + \
                [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling")]
 
 
@@ -79,11 +80,11 @@ class KbeError(RuntimeError):
     pass
 
 
-def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
+def _c_config(cfg: _inputs.Config, nt_max: int | None = None, adjoint: bool = False) -> KbeConfig:
     return KbeConfig(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg, interaction=cfg.interaction,
                      hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
                      nt_max=cfg.nt if nt_max is None else nt_max, precision=cfg.precision,
-                     dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
+                     adjoint=1 if adjoint else 0, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
 
 
 def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):

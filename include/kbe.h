@@ -206,6 +206,36 @@ int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m);
 int kbe_timing(kbe_ctx* ctx, int32_t enable);
 int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* algo_bytes);
 
+/* ---------------------------------------------------------------------------------------
+ * a-8: adjoint (reverse mode) of the propagation. The paper defines the forward map only
+ * (Algorithm "prop" with eqs. (Green), (CI), (2BSE)); the adjoint is the exact discrete
+ * transpose of that map as the forward kernels evaluate it, so the gradient it returns is
+ * the derivative of the computed observable, not of the continuous equations.
+ *
+ * Loss: one final-time observable O(t_T), T = kbe_current_step at the first adjoint call:
+ *   KBE_OBS_NORB + a  (orbital occupation N_k^-1 sum_k rho_aa(T)), or
+ *   KBE_OBS_NBAND + b (band occupation in the eigenbasis of h0(k - A(T))).
+ * Parameters theta = (pulse amp, pulse omega, U); the initial state does not depend on them.
+ *
+ * Requirements: cfg->adjoint = 1 at kbe_create (the per-step rho_m and D_m record),
+ * precision KBE_FP64, n_corr = 1, nb <= 2, and T >= 1. The reverse sweep reads the forward
+ * history (unchanged) and recomputes I(t_{m-1}, .), the predictor row and the corrector's
+ * collision row of each step from it; it overwrites the context's working buffers, so the
+ * context cannot be stepped forward afterwards (KBE_ERR_STATE).
+ *
+ * kbe_adjoint_query: bytes of the caller-owned adjoint workspace for cfg (an FP64 adjoint
+ *   history of the same packed shape as the FP64 history, plus per-step rows).
+ * kbe_adjoint_attach: hand the workspace (device, >= the queried size) to the context.
+ * kbe_adjoint_step: the first call seeds dO/drho(T) (and dO/dA(T)), and every call reverses
+ *   one step (t_m -> t_{m-1}), asynchronously. If grad_out is not NULL the call
+ *   synchronises and writes the gradient accumulated so far, (dO/damp, dO/domega, dO/dU),
+ *   which is final when *steps_remaining == 0. KBE_ERR_STATE once no step remains or the
+ *   observable differs from the first call's.
+ * ------------------------------------------------------------------------------------- */
+int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes);
+int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes);
+int kbe_adjoint_step(kbe_ctx* ctx, int32_t observable_id, double* grad_out, int32_t* steps_remaining);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkbe.so")
-SOURCES = ["kbe_kernels.hip", "kbe_api.hip"]
+SOURCES = ["kbe_kernels.hip", "kbe_adjoint.hip", "kbe_api.hip"]
 ARCH = os.environ.get("KBE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

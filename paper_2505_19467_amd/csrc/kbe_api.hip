@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "kbe.h"
+#include "kbe_adjoint.hpp"
 #include "kbe_kernels.hpp"
 
 using kbe::cplx;
@@ -100,6 +101,45 @@ double pulse_A(const kbe_pulse& p, double t) {
   double x = (t - p.t0) / p.width;
   return p.amp * std::sin(p.omega * t) * std::exp(-x * x);
 }
+// dA/d(amp) and dA/d(omega) at t
+void pulse_dA(const kbe_pulse& p, double t, double* damp, double* domega) {
+  *damp = *domega = 0.0;
+  if (p.width <= 0.0) return;
+  double x = (t - p.t0) / p.width;
+  double g = std::exp(-x * x);
+  *damp = std::sin(p.omega * t) * g;
+  *domega = p.amp * t * std::cos(p.omega * t) * g;
+}
+
+// Adjoint workspace: adjoint history + per-step rows of the reverse sweep.
+enum {
+  A_LAM = 0, A_IBAR0, A_IBAR1, A_IBARC, A_RBAR, A_SBAR, A_SBARCOL, A_IREPREV, A_IREC, A_SBARRP,
+  A_DBAR0, A_DBAR1, A_DBARC, A_RHOBAR0, A_RHOBAR1, A_RHOBARP, A_RHOP, A_DC, A_DSCR,
+  A_PROPSP, A_PROPSC, A_PBAR, A_HFP, A_HFC, A_KPART, A_UBAR, A_THETA, A_COUNT
+};
+
+size_t adj_layout(const Layout& L, size_t* off) {
+  const Dims& d = L.d;
+  const size_t cz = sizeof(cplx), nk = d.nk;
+  size_t sz[A_COUNT];
+  sz[A_LAM] = nk * d.C * (size_t)d.P * cz;
+  size_t row = nk * d.C * d.Tp * cz;
+  for (int i = A_IBAR0; i <= A_IREC; ++i) sz[i] = row;
+  sz[A_SBARRP] = nk * (size_t)d.Smax * d.nbb * d.Tp * cz;
+  size_t mat = nk * d.nbb * cz;
+  for (int i = A_DBAR0; i <= A_DSCR; ++i) sz[i] = mat;
+  sz[A_PROPSP] = sz[A_PROPSC] = sz[A_PBAR] = 3 * mat;
+  sz[A_HFP] = sz[A_HFC] = d.nbb * cz;
+  sz[A_KPART] = nk * (d.nb + 1) * sizeof(double);
+  sz[A_UBAR] = ((size_t)((d.N * d.nbb + 7) / 8) * 8) * sizeof(double);
+  sz[A_THETA] = 3 * sizeof(double);
+  size_t o = 0;
+  for (int i = 0; i < A_COUNT; ++i) {
+    if (off) off[i] = o;
+    o += (sz[i] + 255) / 256 * 256;
+  }
+  return o;
+}
 
 }  // namespace
 
@@ -120,6 +160,13 @@ struct kbe_ctx {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_m;
   size_t ev_used;
+  // reverse sweep
+  char* adj;
+  size_t adj_off[A_COUNT];
+  int adj_obs;   // observable of the sweep (-1: not started)
+  int adj_m;     // next step to reverse
+  int adj_cur;   // role of the double-buffered adjoint rows
+  bool frozen;   // working buffers overwritten by a reverse sweep
 
   template <class T>
   T* buf(int b) const { return reinterpret_cast<T*>(ws + L.off[b]); }
@@ -150,6 +197,8 @@ struct kbe_ctx {
     a.D_save = nullptr;
     a.commit = 1;
     a.Ax = a.Ay = 0.0;
+    a.polx = pulse.pol[0];
+    a.poly = pulse.pol[1];
     a.dt = cfg.dt;
     a.U = cfg.U;
     a.UU = cfg.U * cfg.U;
@@ -235,6 +284,143 @@ struct kbe_ctx {
     step = m;
     return KBE_OK;
   }
+
+  // ---------------------------------------------------------------- reverse sweep
+  template <class T>
+  T* abuf(int i) const { return reinterpret_cast<T*>(adj + adj_off[i]); }
+  kbe::AdjArgs adj_args() const {
+    kbe::AdjArgs b;
+    int c = adj_cur;
+    b.lam = abuf<cplx>(A_LAM);
+    b.Ibar = abuf<cplx>(c == 0 ? A_IBAR0 : A_IBAR1);
+    b.Ibar_prev = abuf<cplx>(c == 0 ? A_IBAR1 : A_IBAR0);
+    b.Ibar_c = abuf<cplx>(A_IBARC);
+    b.Rbar = abuf<cplx>(A_RBAR);
+    b.sbar = abuf<cplx>(A_SBAR);
+    b.sbar_col = abuf<cplx>(A_SBARCOL);
+    b.sbar_rowpart = abuf<cplx>(A_SBARRP);
+    b.Dbar = abuf<cplx>(c == 0 ? A_DBAR0 : A_DBAR1);
+    b.Dbar_prev = abuf<cplx>(c == 0 ? A_DBAR1 : A_DBAR0);
+    b.Dbar_c = abuf<cplx>(A_DBARC);
+    b.rhobar = abuf<cplx>(c == 0 ? A_RHOBAR0 : A_RHOBAR1);
+    b.rhobar_prev = abuf<cplx>(c == 0 ? A_RHOBAR1 : A_RHOBAR0);
+    b.rhobar_P = abuf<cplx>(A_RHOBARP);
+    b.props_p = abuf<cplx>(A_PROPSP);
+    b.props_c = abuf<cplx>(A_PROPSC);
+    b.pbar = abuf<cplx>(A_PBAR);
+    b.rhoP = abuf<cplx>(A_RHOP);
+    b.Ire_prev = abuf<cplx>(A_IREPREV);
+    b.Ire_c = abuf<cplx>(A_IREC);
+    b.Dc = abuf<cplx>(A_DC);
+    b.Dscratch = abuf<cplx>(A_DSCR);
+    b.hf_p = abuf<cplx>(A_HFP);
+    b.hf_c = abuf<cplx>(A_HFC);
+    b.kpart = abuf<double>(A_KPART);
+    b.ubar_part = abuf<double>(A_UBAR);
+    b.theta_bar = abuf<double>(A_THETA);
+    return b;
+  }
+  int zero_adj(int i, size_t bytes) {
+    return check(kbe::launch_fill_zero(abuf<double>(i), (int64_t)(bytes / sizeof(double)), st), "zero");
+  }
+  int adj_seed(int obs_id) {
+    const Dims& d = L.d;
+    size_t row = (size_t)d.nk * d.C * d.Tp * sizeof(cplx), mat = (size_t)d.nk * d.nbb * sizeof(cplx);
+    int rc = zero_adj(A_LAM, (size_t)d.nk * d.C * (size_t)d.P * sizeof(cplx));
+    for (int i = A_IBAR0; i <= A_IBAR1 && !rc; ++i) rc = zero_adj(i, row);
+    for (int i = A_DBAR0; i <= A_RHOBARP && !rc; ++i) rc = zero_adj(i, mat);
+    if (!rc) rc = zero_adj(A_THETA, 3 * sizeof(double));
+    if (rc) return rc;
+    LaunchArgs a = args();
+    double T = step * cfg.dt, damp, dom;
+    set_A(a, T);
+    pulse_dA(pulse, T, &damp, &dom);
+    kbe::AdjArgs b = adj_args();
+    return check(kbe::launch_adj_seed(d, a, b, rec_rho(step), obs_id, damp, dom, st), "adjoint seed launch");
+  }
+  int adj_sigma_pass(const LaunchArgs& a, const kbe::AdjArgs& b, const cplx* Ibar, const cplx* Dbar, int m) {
+    const Dims& d = L.d;
+    int nblk = 0;
+    int rc = check(kbe::launch_adj_bulk(d, a, b, Ibar, m, st), "adjoint history-sum launch");
+    if (!rc) rc = check(kbe::launch_adj_row(d, a, b, Ibar, Dbar, m, st), "adjoint end-point launch");
+    if (!rc) rc = check(kbe::launch_adj_sigma(d, a, b, m, &nblk, st), "adjoint self-energy launch");
+    if (!rc) rc = check(kbe::launch_adj_reduce_u(b, nblk, st), "adjoint reduction launch");
+    return rc;
+  }
+  // Reverse step m (t_m -> t_{m-1}) of the K = 1 scheme: evaluation pass, corrector
+  // update, corrector mean field/propagators, corrector collision pass, predictor update,
+  // predictor mean field/propagators.
+  int adj_reverse(int m) {
+    const Dims& d = L.d;
+    LaunchArgs a = args();
+    a.rho_save = nullptr;
+    a.D_save = nullptr;
+    double tm = (m - 0.5) * cfg.dt, damp, dom;
+    set_A(a, tm);
+    pulse_dA(pulse, tm, &damp, &dom);
+    kbe::AdjArgs b = adj_args();
+    cplx* rho0 = rec_rho(m - 1);
+    // committed rows m-1, m, column 0 and diagonal; Sigma of the committed row m
+    int rc = check(kbe::launch_aux(d, a, m, st), "aux launch");
+    if (!rc) rc = check(kbe::launch_sigma(d, a, m, st), "self-energy launch");
+    // evaluation pass of t_m
+    if (!rc) rc = adj_sigma_pass(a, b, b.Ibar, b.Dbar, m);
+    // recompute I(t_{m-1}, .)
+    LaunchArgs e = a;
+    e.I_cur = b.Ire_prev;
+    e.D_cur = b.Dscratch;
+    if (!rc) rc = check(kbe::launch_sigma(d, e, m - 1, st), "self-energy launch");
+    if (!rc) rc = check(kbe::launch_diag_I(d, e, m - 1, st), "equal-time collision launch");
+    if (!rc) rc = check(kbe::launch_bulk(d, e, m - 1, st), "history-sum launch");
+    if (!rc) rc = check(kbe::launch_row(d, e, m - 1, KBE_ROW_EVAL, st), "collision-row launch");
+    // recompute the predictor (row m of the working copy only)
+    LaunchArgs p = a;
+    p.I_prev = b.Ire_prev;
+    p.rho_prev = rho0;
+    p.rho_cur = b.rhoP;
+    p.D_prev = rec_D(m - 1);
+    p.props = b.props_p;
+    p.hfbuf = b.hf_p;
+    p.commit = 0;
+    if (!rc) rc = check(kbe::launch_hf(d, p, 0.0, st), "mean-field launch");
+    if (!rc) rc = check(kbe::launch_props(d, p, st), "propagator launch");
+    if (!rc) rc = check(kbe::launch_row(d, p, m, KBE_ROW_PREDICT, st), "predictor launch");
+    // recompute the corrector's collision row and propagators
+    LaunchArgs c = p;
+    c.I_cur = b.Ire_c;
+    c.D_cur = b.Dc;
+    c.props = b.props_c;
+    c.hfbuf = b.hf_c;
+    if (!rc) rc = check(kbe::launch_sigma(d, c, m, st), "self-energy launch");
+    if (!rc) rc = check(kbe::launch_diag_I(d, c, m, st), "equal-time collision launch");
+    if (!rc) rc = check(kbe::launch_bulk(d, c, m, st), "history-sum launch");
+    if (!rc) rc = check(kbe::launch_row(d, c, m, KBE_ROW_EVAL, st), "collision-row launch");
+    if (!rc) rc = check(kbe::launch_hf(d, c, 0.5, st), "mean-field launch");
+    if (!rc) rc = check(kbe::launch_props(d, c, st), "propagator launch");
+    // corrector update, its propagators and mean field
+    if (!rc) rc = check(kbe::launch_adj_update(d, p, b, m, 1, b.lam, b.Rbar, rho0, st), "adjoint update launch");
+    if (!rc) rc = check(kbe::launch_adj_props(d, a, b, b.hf_c, st), "adjoint propagator launch");
+    if (!rc)
+      rc = check(kbe::launch_adj_hf(d, a, b, rho0, b.rhoP, 0.5, b.rhobar_prev, b.rhobar_P, damp, dom, st),
+                 "adjoint mean-field launch");
+    // corrector collision pass (Sigma of the predictor row, still in place)
+    if (!rc) rc = adj_sigma_pass(a, b, b.Ibar_c, b.Dbar_c, m);
+    // predictor update, its propagators and mean field
+    if (!rc) rc = check(kbe::launch_adj_update(d, p, b, m, 0, nullptr, b.Rbar, rho0, st), "adjoint update launch");
+    if (!rc) rc = check(kbe::launch_adj_props(d, a, b, b.hf_p, st), "adjoint propagator launch");
+    if (!rc)
+      rc = check(kbe::launch_adj_hf(d, a, b, rho0, rho0, 0.0, b.rhobar_prev, nullptr, damp, dom, st),
+                 "adjoint mean-field launch");
+    if (rc) return rc;
+    // the accumulated adjoints of step m-1 become the inputs of the next reverse step
+    adj_cur ^= 1;
+    size_t row = (size_t)d.nk * d.C * d.Tp * sizeof(cplx), mat = (size_t)d.nk * d.nbb * sizeof(cplx);
+    rc = zero_adj(adj_cur == 0 ? A_IBAR1 : A_IBAR0, row);
+    if (!rc) rc = zero_adj(adj_cur == 0 ? A_DBAR1 : A_DBAR0, mat);
+    if (!rc) rc = zero_adj(adj_cur == 0 ? A_RHOBAR1 : A_RHOBAR0, mat);
+    if (!rc) rc = zero_adj(A_RHOBARP, mat);
+    return rc;
+  }
 };
 
 extern "C" {
@@ -274,6 +460,11 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   c->step = 0;
   c->timing = false;
   c->ev_used = 0;
+  c->adj = nullptr;
+  c->adj_obs = -1;
+  c->adj_m = 0;
+  c->adj_cur = 0;
+  c->frozen = false;
   const Dims& d = c->L.d;
   c->hop_host.resize(3 * d.nbb);
   for (int i = 0; i < 3 * d.nbb; ++i) c->hop_host[i] = make_double2(hop[2 * i], hop[2 * i + 1]);
@@ -309,6 +500,7 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
 
 int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0) return KBE_ERR_INVALID_ARG;
+  if (ctx->frozen) return ctx->fail(KBE_ERR_STATE, "the context's buffers were used by a reverse sweep");
   if (ctx->step + nsteps > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_STATE, "step index would pass nt_max");
   for (int i = 0; i < nsteps; ++i) {
     int rc = ctx->one_step();
@@ -367,6 +559,7 @@ int kbe_buffer(const kbe_ctx* ctx, int32_t which, void** ptr, size_t* bytes) {
 
 static int check_m(kbe_ctx* ctx, int32_t m, int lo) {
   if (!ctx) return KBE_ERR_INVALID_ARG;
+  if (ctx->frozen) return ctx->fail(KBE_ERR_STATE, "the context's buffers were used by a reverse sweep");
   if (m < lo || m > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_INVALID_ARG, "time-slice index out of range");
   return KBE_OK;
 }
@@ -451,6 +644,65 @@ int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* 
   if (launches) *launches = (int64_t)ctx->ev_m.size();
   if (total_ms) *total_ms = ms_sum;
   if (algo_bytes) *algo_bytes = bytes;
+  return KBE_OK;
+}
+
+int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
+  if (!adjoint_bytes) return KBE_ERR_INVALID_ARG;
+  Layout L;
+  std::string why;
+  int rc = make_layout(cfg, &L, &why);
+  if (rc) return rc;
+  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->nb > 2) return KBE_ERR_SHAPE;
+  *adjoint_bytes = adj_layout(L, nullptr);
+  return KBE_OK;
+}
+
+int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes) {
+  if (!ctx || !d_adjoint) return KBE_ERR_INVALID_ARG;
+  if (!ctx->cfg.adjoint) return ctx->fail(KBE_ERR_STATE, "the context was created without cfg.adjoint = 1");
+  if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->L.d.nb > 2)
+    return ctx->fail(KBE_ERR_SHAPE, "the adjoint needs precision KBE_FP64, n_corr = 1 and nb <= 2");
+  if (ctx->adj_obs >= 0) return ctx->fail(KBE_ERR_STATE, "a reverse sweep is in progress");
+  size_t need = adj_layout(ctx->L, ctx->adj_off);
+  if (bytes < need) return ctx->fail(KBE_ERR_INVALID_ARG, "adjoint workspace smaller than kbe_adjoint_query");
+  ctx->adj = (char*)d_adjoint;
+  return KBE_OK;
+}
+
+int kbe_adjoint_step(kbe_ctx* ctx, int32_t observable_id, double* grad_out, int32_t* steps_remaining) {
+  if (!ctx) return KBE_ERR_INVALID_ARG;
+  if (!ctx->adj) return ctx->fail(KBE_ERR_STATE, "no adjoint workspace attached");
+  int nb = ctx->L.d.nb;
+  bool norb = observable_id >= KBE_OBS_NORB && observable_id < KBE_OBS_NORB + nb;
+  bool nband = observable_id >= KBE_OBS_NBAND && observable_id < KBE_OBS_NBAND + nb;
+  if (!norb && !nband) return ctx->fail(KBE_ERR_INVALID_ARG, "observable must be an orbital or band occupation");
+  int rc;
+  if (ctx->adj_obs < 0) {
+    if (ctx->step < 1) return ctx->fail(KBE_ERR_STATE, "no step to reverse");
+    ctx->frozen = true;
+    ctx->adj_obs = observable_id;
+    ctx->adj_m = ctx->step;
+    ctx->adj_cur = 0;
+    rc = ctx->adj_seed(observable_id);
+    if (rc) return rc;
+  } else if (observable_id != ctx->adj_obs) {
+    return ctx->fail(KBE_ERR_STATE, "observable differs from the one the sweep was seeded with");
+  }
+  if (ctx->adj_m < 1) return ctx->fail(KBE_ERR_STATE, "no step left to reverse");
+  rc = ctx->adj_reverse(ctx->adj_m);
+  if (rc) return rc;
+  ctx->adj_m -= 1;
+  if (steps_remaining) *steps_remaining = ctx->adj_m;
+  if (grad_out) {
+    rc = ctx->check(hipMemcpyAsync(grad_out, ctx->abuf<double>(A_THETA), 3 * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->st),
+                    "gradient copy");
+    if (!rc) rc = ctx->check(hipStreamSynchronize(ctx->st), "stream synchronisation");
+    if (rc) return rc;
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(grad_out[i])) return ctx->fail(KBE_ERR_NONFINITE, "non-finite gradient");
+  }
   return KBE_OK;
 }
 

@@ -8,6 +8,8 @@
 #define KBE_DEV_INT_HUBBARD 0
 #define KBE_DEV_INT_INTERBAND 1
 #define KBE_DEV_NOBS 17
+#define KBE_DEV_OBS_NORB 9
+#define KBE_DEV_OBS_NBAND 13
 
 #define KBE_ROW_PREDICT 0
 #define KBE_ROW_CORRECT 1
@@ -42,6 +44,7 @@ struct LaunchArgs {
   cplx* D_save;    // if set: where the equal-time collision kernel also stores D_m
   int commit;      // 0: the row kernel writes only the FP64 working row (recomputation)
   double Ax, Ay;  // A(t) * pol for the launch at hand
+  double polx, poly;  // pulse polarisation
   double dt, U, UU, temp, target, spin;
   int interaction, hf, corr;
 };

@@ -7,6 +7,7 @@ library has not been built; nothing here falls back to a CPU implementation.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 
 import numpy as np
@@ -69,11 +70,15 @@ for _n in ("kbe_stage_sigma", "kbe_stage_collision", "kbe_stage_observables", "k
     getattr(_lib, _n).argtypes = [_vp, _i32]
 _lib.kbe_timing_query.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
+_lib.kbe_adjoint_query.argtypes = [ctypes.POINTER(KbeConfig), _szp]
+_lib.kbe_adjoint_attach.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.kbe_adjoint_step.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 
 EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_observables",
            "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma",
            "kbe_stage_collision", "kbe_stage_update", "kbe_stage_observables", "kbe_stage_commit",
-           "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query"]
+           "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query", "kbe_adjoint_query", "kbe_adjoint_attach",
+           "kbe_adjoint_step"]
 
 
 class KbeError(RuntimeError):
@@ -120,9 +125,11 @@ class System:
     """One propagation context: caller-owned (torch) device buffers + the library context."""
 
     def __init__(self, cfg: _inputs.Config, nt_max: int | None = None, device: str = "cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, adjoint: bool = False):
         self.cfg = cfg
         self.nt_max = cfg.nt if nt_max is None else nt_max
+        self.adjoint = adjoint
+        self.adj_workspace = None
         hb, wb, ob = workspace_query(cfg, self.nt_max)
         dev = torch.device(device)
         self.fp32 = cfg.precision == _inputs.PRECISION_FP32
@@ -140,7 +147,7 @@ class System:
 
     def _create(self):
         cfg = self.cfg
-        c = _c_config(cfg, self.nt_max)
+        c = _c_config(cfg, self.nt_max, self.adjoint)
         hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
         pu = cfg.pulse
         p = KbePulse(amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
@@ -157,6 +164,32 @@ class System:
         """Re-create the library context on the same device buffers (back to t = 0)."""
         self.close()
         self._create()
+        if self.adj_workspace is not None:
+            self._attach()
+
+    # ------------------------------------------------------------------ adjoint
+    def _attach(self):
+        self._check(_lib.kbe_adjoint_attach(self._ctx, _vp(self.adj_workspace.data_ptr()),
+                                            self.adj_workspace.numel()), "kbe_adjoint_attach")
+
+    def adjoint_gradient(self, observable) -> np.ndarray:
+        """Reverse sweep from the current step: d O(t_T) / d(amp, omega, U) for a final-time
+        orbital or band occupation O (name such as 'n_band1' or column index)."""
+        obs_id = OBS[observable] if isinstance(observable, str) else int(observable)
+        if self.adj_workspace is None:
+            nbytes = ctypes.c_size_t()
+            rc = _lib.kbe_adjoint_query(ctypes.byref(_c_config(self.cfg, self.nt_max, True)), ctypes.byref(nbytes))
+            if rc != KBE_OK:
+                raise KbeError(f"kbe_adjoint_query: {ERRORS.get(rc, rc)}")
+            self.adj_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.workspace.device)
+            self._attach()
+        grad = np.zeros(3)
+        left = _i32(self.current_step)
+        while left.value > 0:
+            last = left.value == 1
+            gp = grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if last else None
+            self._check(_lib.kbe_adjoint_step(self._ctx, obs_id, gp, ctypes.byref(left)), "kbe_adjoint_step")
+        return grad
 
     # ------------------------------------------------------------------ lifecycle
     def close(self):
@@ -279,3 +312,31 @@ class System:
         self._check(_lib.kbe_timing_query(self._ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
                     "kbe_timing_query")
         return n.value, ms.value, by.value
+
+
+class KBEFunction(torch.autograd.Function):
+    """O(t_T)(amp, omega, U): final-time orbital or band occupation of a propagation of
+    ``nsteps`` steps, with the library's reverse sweep as the backward pass.
+
+    ``KBEFunction.apply(theta, cfg, nsteps, observable)``; theta = (amp, omega, U) as a
+    float64 tensor of shape (3,). Returns a 0-d float64 tensor on theta's device."""
+
+    @staticmethod
+    def forward(ctx, theta, cfg, nsteps, observable):
+        amp, omega, U = (float(x) for x in theta.detach().cpu().tolist())
+        pulse = dataclasses.replace(cfg.pulse, amp=amp, omega=omega)
+        run_cfg = cfg.replace(U=U, pulse=pulse)
+        sys_ = System(run_cfg, nt_max=nsteps, adjoint=True)
+        sys_.step(nsteps)
+        obs_id = OBS[observable] if isinstance(observable, str) else int(observable)
+        val = sys_.observables(nsteps, 1)[0, obs_id]
+        ctx.system = sys_
+        ctx.obs_id = obs_id
+        return torch.tensor(val, dtype=torch.float64, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.system.adjoint_gradient(ctx.obs_id)
+        ctx.system.close()
+        gt = torch.as_tensor(g, dtype=torch.float64, device=grad_out.device)
+        return grad_out * gt, None, None, None

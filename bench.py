@@ -52,6 +52,58 @@ def cpu_baseline(cfg, sample_steps: int):
     return dt, threads
 
 
+def adjoint_leg(torch, inputs, kbe):
+    """Gradient workload: the 12x12-k, nb = 2, 400-step system; forward propagation with
+    the per-step record, then the reverse sweep for d n_band1(T) / d(amp, omega, U)."""
+    cfg = inputs.c4()
+    n = cfg.nt
+    S = kbe.System(cfg, adjoint=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(n)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = S.adjoint_gradient("n_band1")
+    torch.cuda.synchronize()
+    tr = time.perf_counter() - t0
+    S.close()
+    print(f"[bench] adjoint ({cfg.name}, {n} steps): forward {tf:.3f} s, reverse {tr:.3f} s, "
+          f"grad {g}", file=sys.stderr, flush=True)
+    return {"workload": f"{cfg.name}: 2D 12x12 k-grid, nb=2, nt={n}, dt={cfg.dt}, loss n_band1(T)",
+            "forward_s": tf, "reverse_s": tr, "reverse_over_forward": tr / tf,
+            "grad_amp_omega_U": [float(x) for x in g]}
+
+
+def hbm_ceiling(torch, gib: float = 4.0, reps: int = 5):
+    """Plain device-to-device copy (read + write) and a full-array sum (read) with torch's
+    own kernels, as a measured ceiling beside the 8 TB/s peak."""
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    a.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_gbs = n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    print(f"[bench] HBM probe: copy {copy_gbs:.0f} GB/s (read + write), sum {read_gbs:.0f} GB/s (read)",
+          file=sys.stderr, flush=True)
+    return {"copy_GBs": copy_gbs, "read_GBs": read_gbs, "bytes_each": n * 8}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +112,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=60, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the plain copy/read bandwidth probe")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run one device-to-device copy of GIB GiB (to scale HBM byte counters) and exit")
     args = ap.parse_args()
@@ -144,6 +198,18 @@ def main():
         torch.cuda.empty_cache()
         S = kbe.System(cfg)
 
+    adj = None
+    if not args.no_adjoint:
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        adj = adjoint_leg(torch, inputs, kbe)
+        S = kbe.System(cfg)
+
+    ceiling = None
+    if not args.no_ceiling:
+        ceiling = hbm_ceiling(torch)
+
     cpu = None
     if args.cpu_sample > 0:
         ns = min(args.cpu_sample, K)
@@ -184,6 +250,8 @@ def main():
                      "kernel": "k_hist_bulk", "launches": launches, "kernel_ms": kms},
         "cpu_baseline": cpu,
         "fp32_form": fp32,
+        "adjoint": adj,
+        "hbm_ceiling": ceiling,
         "checks": {"N_drift": n_drift, "energy_balance_max": e_bal, "finite": finite},
     }
     print(json.dumps(line), flush=True)

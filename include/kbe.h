@@ -122,10 +122,15 @@ int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* wo
  *   hop   : host, 3 complex nb x nb blocks T0, Tx, Ty (row-major, interleaved re/im);
  *           h0(k) = T0 + sum_d (T_d e^{i k_d} + T_d^dag e^{-i k_d}); Ty is ignored when nky = 1.
  *   pulse : host, may be NULL (no pulse).
+ *   d_history, d_workspace, d_obs : device buffers and their sizes in bytes; each size must
+ *           be at least what kbe_workspace_query returns for the same cfg (the adjoint flag
+ *           adds the per-step record to the workspace), else KBE_ERR_INVALID_ARG and nothing
+ *           is launched.
  *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
  */
 int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
-               void* d_workspace, void* d_obs, void* hip_stream, kbe_ctx** out);
+               size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
+               void* hip_stream, kbe_ctx** out);
 
 /* Advance nsteps time steps (Algorithm "prop" with K = cfg->n_corr fixed corrector passes),
  * asynchronously. KBE_ERR_STATE if the step index would pass nt_max. */

@@ -328,7 +328,8 @@ struct kbe_ctx {
     size_t row = (size_t)d.nk * d.C * d.Tp * sizeof(cplx), mat = (size_t)d.nk * d.nbb * sizeof(cplx);
     int rc = zero_adj(A_LAM, (size_t)d.nk * d.C * (size_t)d.P * sizeof(cplx));
     for (int i = A_IBAR0; i <= A_IBAR1 && !rc; ++i) rc = zero_adj(i, row);
-    for (int i = A_DBAR0; i <= A_RHOBARP && !rc; ++i) rc = zero_adj(i, mat);
+    // A_RHOP too: the recomputed predictor's mean field reads it with weight 0 before it is written
+    for (int i = A_DBAR0; i <= A_RHOP && !rc; ++i) rc = zero_adj(i, mat);
     if (!rc) rc = zero_adj(A_THETA, 3 * sizeof(double));
     if (rc) return rc;
     LaunchArgs a = args();
@@ -438,7 +439,8 @@ int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* wo
 }
 
 int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
-               void* d_workspace, void* d_obs, void* hip_stream, kbe_ctx** out) {
+               size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
+               void* hip_stream, kbe_ctx** out) {
   if (!out) return KBE_ERR_INVALID_ARG;
   *out = nullptr;
   if (!cfg || !hop || !d_history || !d_workspace || !d_obs) return KBE_ERR_INVALID_ARG;
@@ -451,6 +453,10 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   if (rc) {
     delete c;
     return rc;
+  }
+  if (history_bytes < c->L.hist_bytes || workspace_bytes < c->L.ws_bytes || obs_bytes < c->L.obs_bytes) {
+    delete c;
+    return KBE_ERR_INVALID_ARG;
   }
   c->st = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;

@@ -53,7 +53,8 @@ _i32 = ctypes.c_int32
 _szp = ctypes.POINTER(ctypes.c_size_t)
 _lib.kbe_workspace_query.argtypes = [ctypes.POINTER(KbeConfig), _szp, _szp, _szp]
 _lib.kbe_create.argtypes = [ctypes.POINTER(KbeConfig), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(KbePulse),
-                            _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+                            _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
+                            ctypes.POINTER(_vp)]
 _lib.kbe_step.argtypes = [_vp, _i32]
 _lib.kbe_current_step.argtypes = [_vp]
 _lib.kbe_current_step.restype = _i32
@@ -92,8 +93,14 @@ def _c_config(cfg: _inputs.Config, nt_max: int | None = None, adjoint: bool = Fa
                      adjoint=1 if adjoint else 0, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
 
 
-def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
-    c = _c_config(cfg, nt_max)
+def workspace_query(cfg: _inputs.Config, nt_max: int | None = None, adjoint: bool = False):
+    """Byte sizes (history, workspace, observables) for the context that kbe_create would
+    build from the same (cfg, nt_max, adjoint): the per-step record of an adjoint-enabled
+    context lives in the workspace, so the flag changes the workspace size."""
+    return _query(_c_config(cfg, nt_max, adjoint))
+
+
+def _query(c: KbeConfig):
     h, w, o = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     rc = _lib.kbe_workspace_query(ctypes.byref(c), ctypes.byref(h), ctypes.byref(w), ctypes.byref(o))
     if rc != KBE_OK:
@@ -130,7 +137,9 @@ class System:
         self.nt_max = cfg.nt if nt_max is None else nt_max
         self.adjoint = adjoint
         self.adj_workspace = None
-        hb, wb, ob = workspace_query(cfg, self.nt_max)
+        # one KbeConfig for both the sizing and the creation of the context
+        self._cconf = _c_config(cfg, self.nt_max, adjoint)
+        hb, wb, ob = _query(self._cconf)
         dev = torch.device(device)
         self.fp32 = cfg.precision == _inputs.PRECISION_FP32
         hdt = torch.complex64 if self.fp32 else torch.complex128
@@ -147,14 +156,17 @@ class System:
 
     def _create(self):
         cfg = self.cfg
-        c = _c_config(cfg, self.nt_max, self.adjoint)
+        c = self._cconf
         hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
         pu = cfg.pulse
         p = KbePulse(amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
                      pol=(ctypes.c_double * 2)(pu.pol[0], pu.pol[1]))
         ctx = _vp()
+        nbytes = lambda t: t.numel() * t.element_size()  # noqa: E731
         rc = _lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(p),
-                             _vp(self.history.data_ptr()), _vp(self.workspace.data_ptr()), _vp(self.obs.data_ptr()),
+                             _vp(self.history.data_ptr()), nbytes(self.history),
+                             _vp(self.workspace.data_ptr()), nbytes(self.workspace),
+                             _vp(self.obs.data_ptr()), nbytes(self.obs),
                              _vp(self.stream.cuda_stream), ctypes.byref(ctx))
         if rc != KBE_OK:
             raise KbeError(f"kbe_create: {ERRORS.get(rc, rc)}")
@@ -178,7 +190,7 @@ class System:
         obs_id = OBS[observable] if isinstance(observable, str) else int(observable)
         if self.adj_workspace is None:
             nbytes = ctypes.c_size_t()
-            rc = _lib.kbe_adjoint_query(ctypes.byref(_c_config(self.cfg, self.nt_max, True)), ctypes.byref(nbytes))
+            rc = _lib.kbe_adjoint_query(ctypes.byref(self._cconf), ctypes.byref(nbytes))
             if rc != KBE_OK:
                 raise KbeError(f"kbe_adjoint_query: {ERRORS.get(rc, rc)}")
             self.adj_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.workspace.device)

@@ -82,3 +82,45 @@ def test_strip_layout_is_a_bijection_onto_the_plane():
             rows = np.arange(64 * s, nt + 1)
             base = kbe.tri_off(rows, np.full_like(rows, 64 * s), nt)
             assert np.all(np.diff(base) == 64)
+
+
+def test_adjoint_record_enlarges_the_workspace():
+    """An adjoint-enabled context keeps (rho_m, D_m) for every step inside the workspace:
+    the queried size grows by at least 2 (nt+1) N_k nb^2 complex128."""
+    from paper_2505_19467_amd import kbe
+    for cfg in (inputs.c1(), inputs.c4()):
+        _, w0, _ = kbe.workspace_query(cfg)
+        _, w1, _ = kbe.workspace_query(cfg, adjoint=True)
+        assert w1 - w0 >= 2 * (cfg.nt + 1) * cfg.nk * cfg.nb * cfg.nb * 16
+
+
+def test_create_rejects_undersized_buffers():
+    """kbe_create checks every buffer size against the layout of its own config before it
+    launches anything (so this runs without a GPU): a workspace sized for the config without
+    the adjoint record is refused for the config with it."""
+    from paper_2505_19467_amd import kbe
+    import numpy as np
+    cfg = inputs.c1()
+    c_adj = kbe._c_config(cfg, 20, True)
+    hb, wb, ob = kbe._query(c_adj)
+    _, wb_plain, _ = kbe._query(kbe._c_config(cfg, 20, False))
+    hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: the size check comes first
+    ctx = ctypes.c_void_p()
+    dp = hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for sizes in ((hb, wb_plain, ob), (hb - 16, wb, ob), (hb, wb, ob - 8)):
+        rc = kbe._lib.kbe_create(ctypes.byref(c_adj), dp, None, fake, sizes[0], fake, sizes[1], fake, sizes[2],
+                                 None, ctypes.byref(ctx))
+        assert rc == -1 and not ctx.value
+
+
+def test_adjoint_query():
+    from paper_2505_19467_amd import kbe
+    n = ctypes.c_size_t()
+    cfg = inputs.c4()
+    hb, _, _ = kbe.workspace_query(cfg)
+    assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(cfg, None, True)), ctypes.byref(n)) == 0
+    assert n.value > hb  # the adjoint history alone has the FP64 history's size
+    # K = 2, the FP32 form and nb > 2 are outside the reverse sweep
+    for bad in (cfg.replace(n_corr=2), cfg.replace(precision=inputs.PRECISION_FP32), inputs.c5()):
+        assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(bad, None, True)), ctypes.byref(n)) == -2

@@ -28,6 +28,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
+# HBM traffic of the FP64 history-sum kernel per launch, averaged over the 2000 launches of
+# this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by what the same counters
+# read for a plain 1 GiB device copy (x2.000 and x1.000); summary and commands in
+# profiles/k_hist_bulk_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
+# (SHA-1 of kbe_kernels.hip + kbe_device.hpp); reported as null once that source changes.
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2727e10, "fetch_over_algorithmic": 1.021,
+                    "write_over_algorithmic": 0.0116,
+                    "source_sha1": "bc4eb7eec3ef013389f98c3e3f11e9c517377ee3"}
+
+
+def _kernel_source_sha1():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2505_19467_amd", "csrc")
+    data = b"".join(open(os.path.join(d, f), "rb").read() for f in ("kbe_kernels.hip", "kbe_device.hpp"))
+    return hashlib.sha1(data).hexdigest()
+
 
 def _energy_balance(obs, cfg):
     pu = cfg.pulse
@@ -230,6 +246,9 @@ def main():
                          f"{tcpu:.2f} s; the GPU path takes {tgpu:.3f} s on the same steps",
                "gpu_same_sample_steps_per_s": ns / tgpu}
 
+    traffic = None
+    if args.workload == "c2" and K == cfg.nt and _kernel_source_sha1() == MEASURED_TRAFFIC["source_sha1"]:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     line = {
         "metric": "KBE steps/s (history sums: achieved HBM GB/s)",
         "value": steps_per_s,
@@ -248,7 +267,8 @@ def main():
                    "nk": cfg.nk, "nb": cfg.nb, "nt": cfg.nt, "steps_timed_from_t0": K,
                    "history_passes_per_step": cfg.n_corr + 1, "history_GB": round(hist_gb, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM fetch + write)",
                      "kernel": "k_hist_bulk", "launches": launches, "kernel_ms": kms},
         "cpu_baseline": cpu,
         "fp32_form": fp32,

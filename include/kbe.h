@@ -96,12 +96,12 @@ typedef struct kbe_ctx kbe_ctx;
 /*
  * Device layout:
  *   history : G^{<,>}_{ab}(k; t_j, t') for 0 <= t' <= j <= nt_max, packed lower triangle per
- *             k and per component, strip-major: the columns t' are grouped in strips of 64, and
- *             strip s holds rows j = 64 s .. N-1 (N = nt_max + 1) as consecutive 64-wide
- *             segments, contiguous in t':
- *               elem(k, c, j, t') = (k * C + c) * P + base(s) + 64 (j - 64 s) + (t' - 64 s),
+ *             k, strip-major and component-interleaved: the columns t' are grouped in strips
+ *             of 64; strip s holds rows j = 64 s .. N-1 (N = nt_max + 1), and each row segment
+ *             holds the C = 2 nb^2 components one after the other, 64 elements each:
+ *               elem(k, c, j, t') = k C P + C (base(s) + 64 (j - 64 s)) + 64 c + (t' - 64 s),
  *               s = t' / 64,  base(s) = 64 s N - 2048 s (s - 1),  P = base(ceil(N / 64)),
- *             C = 2 nb^2, c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). Entries above the
+ *             c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). Entries above the
  *             diagonal in a strip's first 64 rows are unused. Elements are complex128 (KBE_FP64)
  *             or complex64 (KBE_FP32). In the FP32 form the history sums read the FP32 history
  *             and compute in FP32 (FP32 accumulation over tiles of 16 rows, FP64 across tiles

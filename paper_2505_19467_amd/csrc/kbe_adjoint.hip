@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   cplx acc[C];  // [0, NBB): Sbar^<_{t'}, [NBB, C): Sbar^>_{t'}
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
-  int64_t base = (int64_t)k * C * d.P + strip_base(s, d.N) + lane - 64 * 64 * (int64_t)s;
+  int64_t base = strip_lane_base(d, k, s, lane);
   const cplx* hk = hist + base;
   cplx* lk = lam + base;
   cplx* rp = sbar_rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
@@ -80,11 +80,11 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
     for (int r = 0; r < R; ++r) {
       int j = jb + r;
       bool v = colv && tp <= j && j < m;
-      int64_t off = 64 * (int64_t)j;
+      int64_t off = 64 * (int64_t)C * j;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        G[r][c] = v ? hk[(int64_t)c * d.P + off] : czero();
-        L[r][c] = v ? lk[(int64_t)c * d.P + off] : czero();
+        G[r][c] = v ? hk[off + 64 * c] : czero();
+        L[r][c] = v ? lk[off + 64 * c] : czero();
       }
     }
     double rt[R][2 * NBB];
@@ -130,9 +130,9 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
         }
       }
       if (v) {
-        int64_t off = 64 * (int64_t)j;
+        int64_t off = 64 * (int64_t)C * j;
 #pragma unroll
-        for (int c = 0; c < C; ++c) lk[(int64_t)c * d.P + off] = cadd(L[r][c], cscal(dl[c], dt));
+        for (int c = 0; c < C; ++c) lk[off + 64 * c] = cadd(L[r][c], cscal(dl[c], dt));
       }
       // SRbar_j partial: sum_s Ibar^s G^s^dag (lanes with a stored block)
       cplx q[NBB];

@@ -65,14 +65,14 @@ __device__ __forceinline__ void mm_acc_bdag(cplx* acc, const cplx* A, const cplx
 }
 
 // ------------------------------------------------------------------ layout
-// Packed two-time history, strip-major. Columns t' are grouped in strips of 64; strip s
-// stores the rows j = 64 s .. N-1 (N = nt_max + 1) of its columns as consecutive 64-wide
-// segments, so that the history sums stream every strip of every (k, component) plane as
-// one contiguous run (the entries above the diagonal in a strip's first 64 rows are unused):
-//   elem(j, t') = base(s) + 64 (j - 64 s) + (t' - 64 s),   s = t' / 64,
-//   base(s) = sum_{s' < s} 64 (N - 64 s') = 64 s N - 2048 s (s - 1),
-//   plane length P = base(ceil(N / 64)).
-// The same layout holds complex128 (FP64 form) or complex64 (FP32 form) elements.
+// Packed two-time history, strip-major and component-interleaved. Columns t' are grouped in
+// strips of 64; strip s stores the rows j = 64 s .. N-1 (N = nt_max + 1) of its columns, and
+// each row segment holds the C = 2 nb^2 components one after the other, 64 elements each:
+//   elem(k, c, j, t') = k C P + C (base(s) + 64 (j - 64 s)) + 64 c + (t' - 64 s),  s = t' / 64,
+//   base(s) = sum_{s' < s} 64 (N - 64 s') = 64 s N - 2048 s (s - 1),  P = base(ceil(N / 64)).
+// A strip of one k is a single contiguous run of rows of C x 64 elements, which the history
+// sums stream front to back (the entries above the diagonal in a strip's first 64 rows are
+// unused). The same layout holds complex128 (FP64 form) or complex64 (FP32 form) elements.
 __host__ __device__ __forceinline__ int64_t strip_base(int64_t s, int64_t N) { return 64 * s * N - 2048 * s * (s - 1); }
 
 struct Dims {
@@ -82,16 +82,21 @@ struct Dims {
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
   int fp32;        // 1: the packed history is stored in FP32 (complex64)
-  int64_t P;       // length of one (k, component) plane of the history (elements)
+  int64_t P;       // history elements per (k, component): one k occupies C * P elements
 };
 
-__host__ __device__ __forceinline__ int64_t tri_off(const Dims& d, int j, int tp) {
+// Row segment (j, strip of t') of a k, in units of C-component rows of 64 elements.
+__host__ __device__ __forceinline__ int64_t seg_off(const Dims& d, int j, int tp) {
   int s = tp >> 6;
-  return strip_base(s, d.N) + 64 * (int64_t)(j - 64 * s) + (tp & 63);
+  return strip_base(s, d.N) + 64 * (int64_t)(j - 64 * s);
 }
 // Element index (complex units of the storage type).
 __host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
-  return ((int64_t)k * d.C + c) * d.P + tri_off(d, j, tp);
+  return (int64_t)k * d.C * d.P + (int64_t)d.C * seg_off(d, j, tp) + 64 * c + (tp & 63);
+}
+// Strip s of k seen from lane `lane`: element (c, j) of the strip is at this + 64 C j + 64 c.
+__host__ __device__ __forceinline__ int64_t strip_lane_base(const Dims& d, int k, int s, int lane) {
+  return (int64_t)k * d.C * d.P + (int64_t)d.C * (strip_base(s, d.N) - 64 * 64 * (int64_t)s) + lane;
 }
 // FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
 __host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {

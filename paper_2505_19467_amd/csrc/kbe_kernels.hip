@@ -388,7 +388,7 @@ __device__ __forceinline__ float2 load_stream32(const float2* p) {
 // Block = (64-column strip s, k); strips with the most rows are launched first. Lane l owns
 // column t' = 64 s + l and keeps its column sums in registers; each wavefront takes R
 // consecutive rows per iteration (R x 2nb^2 loads of 1 KB-contiguous data in flight, one per
-// row and component plane; R = 4, 2, 1 for nb = 1, 2, >= 3 to stay within the register
+// row and component; R = 4, 2, 1 for nb = 1, 2, >= 3 to stay within the register
 // file), so every stored block is read from HBM exactly once. The R rows' row terms are
 // reduced over the 64 lanes with a reduce-scatter (half-wave and 16-lane-row permlane swaps,
 // then DPP within rows) and stored per strip (rowpart); the 4 wavefronts' column sums are
@@ -429,8 +429,8 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
   cplx acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
-  // strip s of every component plane of k: rows j >= 64 s as consecutive 64-wide segments
-  const cplx* hk = hist + (int64_t)k * C * d.P + strip_base(s, d.N) + lane - 64 * 64 * (int64_t)s;
+  // strip s of k: rows j >= 64 s, each a run of C component segments of 64 elements
+  const cplx* hk = hist + strip_lane_base(d, k, s, lane);
   cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
     cplx G[R][C];
@@ -438,9 +438,9 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
     for (int r = 0; r < R; ++r) {
       int j = jb + r;
       bool v = colv && tp <= j && j < m;
-      int64_t off = 64 * (int64_t)j;
+      const cplx* row = hk + 64 * (int64_t)C * j;
 #pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream(hk + (int64_t)c * d.P + off) : czero();
+      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream(row + 64 * c) : czero();
     }
     double rt[R][2 * NBB];
 #pragma unroll
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
     acc[c] = czero();
     acc32[c] = make_float2(0.f, 0.f);
   }
-  const cplx32* hk = hist + (int64_t)k * C * d.P + strip_base(s, d.N) + lane - 64 * 64 * (int64_t)s;
+  const cplx32* hk = hist + strip_lane_base(d, k, s, lane);
   cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
   int it = 0;
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
@@ -612,9 +612,9 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
     for (int r = 0; r < R; ++r) {
       int j = jb + r;
       bool v = colv && tp <= j && j < m;
-      int64_t off = 64 * (int64_t)j;
+      const cplx32* row = hk + 64 * (int64_t)C * j;
 #pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream32(hk + (int64_t)c * d.P + off) : make_float2(0.f, 0.f);
+      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream32(row + 64 * c) : make_float2(0.f, 0.f);
     }
     float rt[R][2 * NBB];
 #pragma unroll

@@ -113,19 +113,20 @@ def strip_base(s: int, N: int) -> int:
 
 
 def plane_length(nt_max: int) -> int:
-    """Length P of one (k, component) plane of the packed history (include/kbe.h)."""
+    """P of the history layout (include/kbe.h): one k occupies C * P elements."""
     N = nt_max + 1
     return strip_base((N + 63) // 64, N)
 
 
-def tri_off(j, tp, nt_max: int):
-    """Position of element (t_j, t'_tp), tp <= j, inside a plane (strip-major layout);
-    works elementwise on numpy integer arrays."""
+def hist_offset(c, j, tp, nt_max: int, C: int):
+    """Element offset of component c of (t_j, t'_tp), tp <= j, inside the C * P elements of one
+    k (strip-major, component-interleaved layout); elementwise on numpy integer arrays."""
     N = nt_max + 1
+    c = np.asarray(c, dtype=np.int64)
     j = np.asarray(j, dtype=np.int64)
     tp = np.asarray(tp, dtype=np.int64)
     s = tp >> 6
-    return 64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s) + (tp & 63)
+    return C * (64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s)) + 64 * c + (tp & 63)
 
 
 class System:
@@ -266,25 +267,26 @@ class System:
         off = ptr.value - self.workspace.data_ptr()
         return self.workspace[off:off + nbytes.value].view(torch.complex128)
 
-    def history_planes(self) -> torch.Tensor:
-        """History as [k][component][P] (component c = s*nb^2 + a*nb + b), complex128 or
-        complex64 (FP32 form)."""
-        return self.history.view(self.nk, self.C, self.P)
+    def history_blocks(self) -> torch.Tensor:
+        """History as [k][C * P] (complex128, or complex64 in the FP32 form); element offsets
+        inside a k from hist_offset."""
+        return self.history.view(self.nk, self.C * self.P)
 
     def _row_index(self, j: int) -> torch.Tensor:
-        idx = tri_off(j, np.arange(j + 1), self.nt_max)
+        c, tp = np.meshgrid(np.arange(self.C), np.arange(j + 1), indexing="ij")
+        idx = hist_offset(c.ravel(), j, tp.ravel(), self.nt_max, self.C)   # [c][t'] flattened
         return torch.from_numpy(idx).to(self.history.device)
 
     def history_row(self, j: int) -> torch.Tensor:
         """Row j as a [t'][k][</>][a][b] tensor (copy, in the storage precision)."""
         nb = self.nb
-        h = self.history_planes().index_select(2, self._row_index(j))   # [k][c][t']
+        h = self.history_blocks().index_select(1, self._row_index(j)).view(self.nk, self.C, j + 1)
         return h.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
 
     def set_history_row(self, j: int, row: torch.Tensor):
         """Write row j from a [t'][k][</>][a][b] tensor (cast to the storage precision)."""
-        src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0).to(self.history.dtype)
-        self.history_planes().index_copy_(2, self._row_index(j), src.contiguous())
+        src = row.reshape(j + 1, self.nk, self.C).permute(1, 2, 0).to(self.history.dtype)   # [k][c][t']
+        self.history_blocks().index_copy_(1, self._row_index(j), src.reshape(self.nk, -1).contiguous())
 
     def row64(self, j: int) -> torch.Tensor:
         """FP64 working copy of history row j (j = m-1 or m of the current step), as a

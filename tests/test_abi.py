@@ -65,23 +65,27 @@ def test_workspace_query_rejects_bad_shapes():
         kbe.workspace_query(inputs.c1().replace(dt=-0.1))
 
 
-def test_strip_layout_is_a_bijection_onto_the_plane():
-    """Every stored (t_j, t') maps to a distinct position inside the plane; consecutive rows
-    of a strip are consecutive 64-element segments (what the history sums stream)."""
+def test_history_layout_is_a_bijection():
+    """Every stored (c, t_j, t') of one k maps to a distinct offset inside its C * P elements;
+    each row segment of a strip holds the C components' 64-element segments back to back, and
+    consecutive rows of a strip follow each other (one contiguous stream per strip)."""
     import numpy as np
     from paper_2505_19467_amd import kbe
-    for nt in (1, 63, 64, 65, 200, 1000):
+    for nt, C in ((1, 2), (63, 8), (64, 8), (65, 2), (200, 8), (1000, 8), (130, 32)):
         P = kbe.plane_length(nt)
         j, tp = np.tril_indices(nt + 1)
-        off = kbe.tri_off(j, tp, nt)
-        assert off.min() >= 0 and off.max() < P
+        c = np.repeat(np.arange(C), len(j))
+        off = kbe.hist_offset(c, np.tile(j, C), np.tile(tp, C), nt, C)
+        assert off.min() >= 0 and off.max() < C * P
         assert len(np.unique(off)) == len(off)
-        # fill factor: the unused part is at most one 64x64 triangle per strip
-        assert P - len(off) <= ((nt + 64) // 64) * 64 * 63 // 2
+        # fill factor: the unused part is at most one 64x64 triangle per strip and component
+        assert C * P - len(off) <= C * ((nt + 64) // 64) * 64 * 63 // 2
         for s in range(0, (nt + 1 + 63) // 64):
             rows = np.arange(64 * s, nt + 1)
-            base = kbe.tri_off(rows, np.full_like(rows, 64 * s), nt)
-            assert np.all(np.diff(base) == 64)
+            first = kbe.hist_offset(0, rows, np.full_like(rows, 64 * s), nt, C)
+            assert np.all(np.diff(first) == 64 * C)
+            last = kbe.hist_offset(C - 1, rows, np.full_like(rows, 64 * s + 63), nt, C)
+            assert np.all(last - first == 64 * C - 1)
 
 
 def test_adjoint_record_enlarges_the_workspace():

@@ -251,12 +251,14 @@ def test_collision_full_size_sampled(K):
     sig_all = S.sigma_row(m).cpu().numpy()
     one = cfg.replace(nkx=1, nky=1)
     nb = cfg.nb
+    C = 2 * nb * nb
     for k in (0, 313, cfg.nk - 1):
-        planes = S.history_planes()[k].cpu().numpy()  # [C][P]
-        assert planes.dtype == np.complex128
+        hk = S.history_blocks()[k].cpu().numpy()  # [C * P]
+        assert hk.dtype == np.complex128
         rows = []
         for j in range(m + 1):
-            blk = planes[:, K.tri_off(j, np.arange(j + 1), m)]  # [C][t']
+            c, tp = np.meshgrid(np.arange(C), np.arange(j + 1), indexing="ij")
+            blk = hk[K.hist_offset(c, j, tp, m, C)]  # [C][t']
             rows.append(blk.T.reshape(j + 1, 1, 2, nb, nb))
         ref = O.collision_row(one, m, rows, sig_all[:, k:k + 1])
         err = relerr(got_all[:, k:k + 1], ref)

@@ -101,7 +101,10 @@ typedef struct kbe_ctx kbe_ctx;
  *             holds the C = 2 nb^2 components one after the other, 64 elements each:
  *               elem(k, c, j, t') = k C P + C (base(s) + 64 (j - 64 s)) + 64 c + (t' - 64 s),
  *               s = t' / 64,  base(s) = 64 s N - 2048 s (s - 1),  P = base(ceil(N / 64)),
- *             c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). Entries above the
+ *             c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). In the FP32 form the
+ *             components of a row segment are stored in pairs interleaved per column:
+ *               elem = k C P + C (base(s) + 64 (j - 64 s)) + 128 (c / 2) + 2 (t' - 64 s) + c % 2.
+ *             Entries above the
  *             diagonal in a strip's first 64 rows are unused. Elements are complex128 (KBE_FP64)
  *             or complex64 (KBE_FP32). In the FP32 form the history sums read the FP32 history
  *             and compute in FP32 (FP32 accumulation over tiles of 16 rows, FP64 across tiles

@@ -72,7 +72,9 @@ __device__ __forceinline__ void mm_acc_bdag(cplx* acc, const cplx* A, const cplx
 //   base(s) = sum_{s' < s} 64 (N - 64 s') = 64 s N - 2048 s (s - 1),  P = base(ceil(N / 64)).
 // A strip of one k is a single contiguous run of rows of C x 64 elements, which the history
 // sums stream front to back (the entries above the diagonal in a strip's first 64 rows are
-// unused). The same layout holds complex128 (FP64 form) or complex64 (FP32 form) elements.
+// unused). In the FP32 form (complex64 elements) the components of a row segment are stored
+// in pairs, interleaved per column, so that one 16-byte load brings a lane two components:
+//   elem = k C P + C (base(s) + 64 (j - 64 s)) + 128 (c / 2) + 2 (t' - 64 s) + (c % 2).
 __host__ __device__ __forceinline__ int64_t strip_base(int64_t s, int64_t N) { return 64 * s * N - 2048 * s * (s - 1); }
 
 struct Dims {
@@ -92,11 +94,14 @@ __host__ __device__ __forceinline__ int64_t seg_off(const Dims& d, int j, int tp
 }
 // Element index (complex units of the storage type).
 __host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
-  return (int64_t)k * d.C * d.P + (int64_t)d.C * seg_off(d, j, tp) + 64 * c + (tp & 63);
+  int64_t in_seg = d.fp32 ? 128 * (c >> 1) + 2 * (tp & 63) + (c & 1) : 64 * c + (tp & 63);
+  return (int64_t)k * d.C * d.P + (int64_t)d.C * seg_off(d, j, tp) + in_seg;
 }
-// Strip s of k seen from lane `lane`: element (c, j) of the strip is at this + 64 C j + 64 c.
+// Strip s of k seen from lane `lane`: element (c, j) of the strip is at this + 64 C j + 64 c
+// (FP64), or component pair c2 at this + 64 C j + 128 c2 (FP32 form).
 __host__ __device__ __forceinline__ int64_t strip_lane_base(const Dims& d, int k, int s, int lane) {
-  return (int64_t)k * d.C * d.P + (int64_t)d.C * (strip_base(s, d.N) - 64 * 64 * (int64_t)s) + lane;
+  return (int64_t)k * d.C * d.P + (int64_t)d.C * (strip_base(s, d.N) - 64 * 64 * (int64_t)s) +
+         (d.fp32 ? 2 * lane : lane);
 }
 // FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
 __host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {

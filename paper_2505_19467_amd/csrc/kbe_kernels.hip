@@ -370,14 +370,16 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
 // ------------------------------------------------------------------ history sums (hot loop)
 // History blocks are read once per pass: stream them past the caches.
 typedef double kbe_d2v __attribute__((ext_vector_type(2)));
-typedef float kbe_f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ cplx load_stream(const cplx* p) {
   kbe_d2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_d2v*>(p));
   return make_double2(v.x, v.y);
 }
-__device__ __forceinline__ float2 load_stream32(const float2* p) {
-  kbe_f2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_f2v*>(p));
-  return make_float2(v.x, v.y);
+typedef float kbe_f4v __attribute__((ext_vector_type(4)));
+// two complex64 values (a component pair of one column) in one 16-byte load
+__device__ __forceinline__ void load_stream32x2(const float2* p, float2& a, float2& b) {
+  kbe_f4v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_f4v*>(p));
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
 }
 
 // Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
@@ -614,7 +616,14 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
       bool v = colv && tp <= j && j < m;
       const cplx32* row = hk + 64 * (int64_t)C * j;
 #pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream32(row + 64 * c) : make_float2(0.f, 0.f);
+      for (int c2 = 0; c2 < C / 2; ++c2) {
+        if (v) {
+          load_stream32x2(row + 128 * c2, G[r][2 * c2], G[r][2 * c2 + 1]);
+        } else {
+          G[r][2 * c2] = make_float2(0.f, 0.f);
+          G[r][2 * c2 + 1] = make_float2(0.f, 0.f);
+        }
+      }
     }
     float rt[R][2 * NBB];
 #pragma unroll

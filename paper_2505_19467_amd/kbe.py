@@ -118,15 +118,17 @@ def plane_length(nt_max: int) -> int:
     return strip_base((N + 63) // 64, N)
 
 
-def hist_offset(c, j, tp, nt_max: int, C: int):
+def hist_offset(c, j, tp, nt_max: int, C: int, fp32: bool = False):
     """Element offset of component c of (t_j, t'_tp), tp <= j, inside the C * P elements of one
-    k (strip-major, component-interleaved layout); elementwise on numpy integer arrays."""
+    k (strip-major, component-interleaved layout; component pairs interleaved per column in
+    the FP32 form); elementwise on numpy integer arrays."""
     N = nt_max + 1
     c = np.asarray(c, dtype=np.int64)
     j = np.asarray(j, dtype=np.int64)
     tp = np.asarray(tp, dtype=np.int64)
     s = tp >> 6
-    return C * (64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s)) + 64 * c + (tp & 63)
+    in_seg = 128 * (c >> 1) + 2 * (tp & 63) + (c & 1) if fp32 else 64 * c + (tp & 63)
+    return C * (64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s)) + in_seg
 
 
 class System:
@@ -274,7 +276,7 @@ class System:
 
     def _row_index(self, j: int) -> torch.Tensor:
         c, tp = np.meshgrid(np.arange(self.C), np.arange(j + 1), indexing="ij")
-        idx = hist_offset(c.ravel(), j, tp.ravel(), self.nt_max, self.C)   # [c][t'] flattened
+        idx = hist_offset(c.ravel(), j, tp.ravel(), self.nt_max, self.C, self.fp32)   # [c][t'] flattened
         return torch.from_numpy(idx).to(self.history.device)
 
     def history_row(self, j: int) -> torch.Tensor:

@@ -71,21 +71,25 @@ def test_history_layout_is_a_bijection():
     consecutive rows of a strip follow each other (one contiguous stream per strip)."""
     import numpy as np
     from paper_2505_19467_amd import kbe
-    for nt, C in ((1, 2), (63, 8), (64, 8), (65, 2), (200, 8), (1000, 8), (130, 32)):
-        P = kbe.plane_length(nt)
-        j, tp = np.tril_indices(nt + 1)
-        c = np.repeat(np.arange(C), len(j))
-        off = kbe.hist_offset(c, np.tile(j, C), np.tile(tp, C), nt, C)
-        assert off.min() >= 0 and off.max() < C * P
-        assert len(np.unique(off)) == len(off)
-        # fill factor: the unused part is at most one 64x64 triangle per strip and component
-        assert C * P - len(off) <= C * ((nt + 64) // 64) * 64 * 63 // 2
-        for s in range(0, (nt + 1 + 63) // 64):
-            rows = np.arange(64 * s, nt + 1)
-            first = kbe.hist_offset(0, rows, np.full_like(rows, 64 * s), nt, C)
-            assert np.all(np.diff(first) == 64 * C)
-            last = kbe.hist_offset(C - 1, rows, np.full_like(rows, 64 * s + 63), nt, C)
-            assert np.all(last - first == 64 * C - 1)
+    for fp32 in (False, True):
+        for nt, C in ((1, 2), (63, 8), (64, 8), (65, 2), (200, 8), (1000, 8), (130, 32), (70, 18)):
+            P = kbe.plane_length(nt)
+            j, tp = np.tril_indices(nt + 1)
+            c = np.repeat(np.arange(C), len(j))
+            off = kbe.hist_offset(c, np.tile(j, C), np.tile(tp, C), nt, C, fp32)
+            assert off.min() >= 0 and off.max() < C * P
+            assert len(np.unique(off)) == len(off)
+            # fill factor: the unused part is at most one 64x64 triangle per strip and component
+            assert C * P - len(off) <= C * ((nt + 64) // 64) * 64 * 63 // 2
+            for s in range(0, (nt + 1 + 63) // 64):
+                rows = np.arange(64 * s, nt + 1)
+                first = kbe.hist_offset(0, rows, np.full_like(rows, 64 * s), nt, C, fp32)
+                assert np.all(np.diff(first) == 64 * C)
+                last = kbe.hist_offset(C - 1, rows, np.full_like(rows, 64 * s + 63), nt, C, fp32)
+                assert np.all(last - first == 64 * C - 1)
+            if fp32:  # a column's component pair is adjacent: one 16-byte load
+                pair = kbe.hist_offset(np.array([0, 1]), 64, 5, nt if nt >= 64 else 64, C, True)
+                assert pair[1] - pair[0] == 1
 
 
 def test_adjoint_record_enlarges_the_workspace():

@@ -513,6 +513,7 @@ __global__ __launch_bounds__(256) void k_adj_sigma(Dims d, const cplx* __restric
   constexpr int PT = 4;  // k points per thread (N_k <= 1024)
   extern __shared__ cplx lds[];
   __shared__ double ured[256];
+  __shared__ cplx twx[64], twy[64];
   cplx* xl = lds;
   cplx* xg = lds + d.nk;
   cplx* tl = lds + 2 * d.nk;
@@ -525,15 +526,14 @@ __global__ __launch_bounds__(256) void k_adj_sigma(Dims d, const cplx* __restric
     int j = item / NBB, ab = item - (item / NBB) * NBB;
     int t = threadIdx.x;
     int nx = d.nkx, ny = d.nky, nk = d.nk;
+    fill_roots(twx, nx);
+    fill_roots(twy, ny);
     for (int k = t; k < nk; k += 256) {
       xl[k] = row64[row64_idx(d, m, k, ab, j)];
       xg[k] = row64[row64_idx(d, m, k, NBB + ab, j)];
     }
     __syncthreads();
-    dft_lines(xl, xg, tl, tg, ny, nx, ny, 1, +1, 1.0);
-    __syncthreads();
-    dft_lines(tl, tg, xl, xg, nx, ny, 1, ny, +1, 1.0 / nk);  // g(R)
-    __syncthreads();
+    grid_dft(xl, xg, tl, tg, nx, ny, twx, twy, +1, 1.0 / nk);  // g(R)
     cplx ra[PT], rb[PT];
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -547,10 +547,7 @@ __global__ __launch_bounds__(256) void k_adj_sigma(Dims d, const cplx* __restric
       xg[k] = sbar[(((int64_t)k * 2 + 1) * NBB + ab) * d.Tp + j];
     }
     __syncthreads();
-    dft_lines(xl, xg, tl, tg, ny, nx, ny, 1, +1, 1.0);
-    __syncthreads();
-    dft_lines(tl, tg, xl, xg, nx, ny, 1, ny, +1, 1.0);  // sbar(R)
-    __syncthreads();
+    grid_dft(xl, xg, tl, tg, nx, ny, twx, twy, +1, 1.0);  // sbar(R)
     double cc = -U * U;
 #pragma unroll
     for (int i = 0; i < PT; ++i) {
@@ -571,10 +568,7 @@ __global__ __launch_bounds__(256) void k_adj_sigma(Dims d, const cplx* __restric
       xg[o] = gb;
     }
     __syncthreads();
-    dft_lines(xl, xg, tl, tg, ny, nx, ny, 1, -1, 1.0);
-    __syncthreads();
-    dft_lines(tl, tg, xl, xg, nx, ny, 1, ny, -1, 1.0 / nk);
-    __syncthreads();
+    grid_dft(xl, xg, tl, tg, nx, ny, twx, twy, -1, 1.0 / nk);
     for (int k = t; k < nk; k += 256) {
       int64_t il = rowbuf_idx(d, k, ab, j), ig = rowbuf_idx(d, k, NBB + ab, j);
       Rbar[il] = cadd(Rbar[il], xl[k]);

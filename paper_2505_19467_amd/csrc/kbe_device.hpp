@@ -315,44 +315,121 @@ __device__ __forceinline__ double row16_sum(double x) {
 }
 
 
-// 1D DFTs of the lines of two n x n' arrays held in LDS, in place into `out`:
-//   out[line][q] = scale * sum_p in[line][p] w^{p q},  w = e^{sgn 2 pi i / n},
-// line element p at base(line) + p * stride. A work item is (array, line, group of 8
-// outputs); its 8 outputs are evaluated as 8 Horner chains in z_q = w^q, so that every
-// LDS read of an input feeds 8 outputs and no twiddle table is read.
-__device__ __forceinline__ void dft_lines(const cplx* __restrict__ in0, const cplx* __restrict__ in1,
-                                          cplx* __restrict__ out0, cplx* __restrict__ out1, int n, int nlines,
-                                          int line_mul, int stride, int sgn, double scale) {
+// ------------------------------------------------------------------ factorised line transforms
+// Roots of unity tw[u] = e^{+2 pi i u / n}, u < n (n <= 64), for one block (one per thread).
+__device__ __forceinline__ void fill_roots(cplx* tw, int n) {
+  for (int u = threadIdx.x; u < n; u += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)u / (double)n, &sn, &cs);
+    tw[u] = cmk(cs, sn);
+  }
+}
+__device__ __forceinline__ cplx root(const cplx* tw, int u, int sgn) {
+  cplx w = tw[u];
+  return sgn > 0 ? w : cconj(w);
+}
+// largest divisor n1 of n with n1 * n1 <= n (1 when n is prime)
+__host__ __device__ __forceinline__ int fft_split(int n) {
+  int best = 1;
+  for (int f = 2; f * f <= n; ++f)
+    if (n % f == 0) best = f;
+  return best;
+}
+
+// In-place DFT of the lines of two arrays held in LDS:
+//   x[line][q] <- scale * sum_p x[line][p] w^{sgn p q},  w = e^{2 pi i / n},
+// element p of a line at line * line_mul + p * stride; (t0, t1) are scratch of the same shape.
+// For n = n1 n2 (n1 = fft_split(n) > 1) in two Cooley-Tukey stages with p = n2 p1 + p2,
+// q = q1 + n1 q2: first the n1-point transforms over p1 with the twiddle w^{p2 q1} into the
+// scratch, then the n2-point transforms over p2 back into x; each output costs n1 + n2
+// multiply-adds instead of n. Horner chains in registers, roots from the LDS table tw.
+// Every stage ends with a block barrier; the caller synchronises before the first.
+__device__ __forceinline__ void axis_dft(cplx* __restrict__ x0, cplx* __restrict__ x1, cplx* __restrict__ t0,
+                                         cplx* __restrict__ t1, int n, int nlines, int line_mul, int stride,
+                                         const cplx* __restrict__ tw, int sgn, double scale) {
+  const int n1 = fft_split(n);
+  if (n1 == 1) {
+    int items = 2 * nlines * n;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      int arr = it / (nlines * n);
+      int rem = it - arr * nlines * n;
+      int line = rem / n, q = rem - (rem / n) * n;
+      const cplx* x = (arr ? x1 : x0) + line * line_mul;
+      cplx z = root(tw, q, sgn), acc = czero();
+      for (int p = n - 1; p >= 0; --p) acc = cadd(cmul(acc, z), x[p * stride]);
+      (arr ? t1 : t0)[line * line_mul + q * stride] = cscal(acc, scale);
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      int arr = it / (nlines * n);
+      int rem = it - arr * nlines * n;
+      int line = rem / n, q = rem - (rem / n) * n;
+      int o = line * line_mul + q * stride;
+      (arr ? x1 : x0)[o] = (arr ? t1 : t0)[o];
+    }
+    __syncthreads();
+    return;
+  }
+  const int n2 = n / n1;
+  // stage A: item = (array, line, p2), n1 outputs q1
+  int itemsA = 2 * nlines * n2;
+  for (int it = threadIdx.x; it < itemsA; it += blockDim.x) {
+    int arr = it / (nlines * n2);
+    int rem = it - arr * nlines * n2;
+    int line = rem / n2, p2 = rem - (rem / n2) * n2;
+    const cplx* x = (arr ? x1 : x0) + line * line_mul;
+    cplx* t = (arr ? t1 : t0) + line * line_mul;
+    cplx v[8];
+#pragma unroll
+    for (int p1 = 0; p1 < 8; ++p1) v[p1] = p1 < n1 ? x[(p1 * n2 + p2) * stride] : czero();
+    for (int q1 = 0; q1 < n1; ++q1) {
+      cplx r = root(tw, (n2 * q1) % n, sgn), acc = czero();
+#pragma unroll
+      for (int p1 = 7; p1 >= 0; --p1)
+        if (p1 < n1) acc = cadd(cmul(acc, r), v[p1]);
+      t[(q1 * n2 + p2) * stride] = cmul(acc, root(tw, (p2 * q1) % n, sgn));
+    }
+  }
+  __syncthreads();
+  // stage B: item = (array, line, q1, group of 8 q2)
   constexpr int Q = 8;
-  int groups = (n + Q - 1) / Q;
-  int items = 2 * nlines * groups;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    int arr = it / (nlines * groups);
-    int rem = it - arr * nlines * groups;
-    int line = rem / groups, g = rem - (rem / groups) * groups;
-    const cplx* x = (arr ? in1 : in0) + line * line_mul;
-    cplx* y = (arr ? out1 : out0) + line * line_mul;
+  const int groups = (n2 + Q - 1) / Q;
+  int itemsB = 2 * nlines * n1 * groups;
+  for (int it = threadIdx.x; it < itemsB; it += blockDim.x) {
+    int arr = it / (nlines * n1 * groups);
+    int rem = it - arr * nlines * n1 * groups;
+    int line = rem / (n1 * groups);
+    rem -= line * n1 * groups;
+    int q1 = rem / groups, g = rem - (rem / groups) * groups;
+    const cplx* t = (arr ? t1 : t0) + line * line_mul + q1 * n2 * stride;
+    cplx* x = (arr ? x1 : x0) + line * line_mul;
     cplx z[Q], acc[Q];
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
-      int q = g * Q + r;
-      double sn, cs;
-      sincospi(2.0 * (double)(q < n ? q : 0) / (double)n, &sn, &cs);
-      z[r] = cmk(cs, sgn * sn);
+      int q2 = g * Q + r;
+      z[r] = root(tw, ((q2 < n2 ? q2 : 0) * n1) % n, sgn);
       acc[r] = czero();
     }
-    for (int p = n - 1; p >= 0; --p) {
-      cplx v = x[p * stride];
+    for (int p2 = n2 - 1; p2 >= 0; --p2) {
+      cplx v = t[p2 * stride];
 #pragma unroll
       for (int r = 0; r < Q; ++r) acc[r] = cadd(cmul(acc[r], z[r]), v);
     }
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
-      int q = g * Q + r;
-      if (q < n) y[q * stride] = cscal(acc[r], scale);
+      int q2 = g * Q + r;
+      if (q2 < n2) x[(q1 + n1 * q2) * stride] = cscal(acc[r], scale);
     }
   }
+  __syncthreads();
 }
 
+// Index transform of an nx x ny grid (k = ix * ny + iy) for two arrays in place:
+//   x(R) <- scale * sum_k e^{sgn 2 pi i (ix Rx / nx + iy Ry / ny)} x(k); y lines, then x lines.
+__device__ __forceinline__ void grid_dft(cplx* x0, cplx* x1, cplx* t0, cplx* t1, int nx, int ny, const cplx* twx,
+                                         const cplx* twy, int sgn, double scale) {
+  axis_dft(x0, x1, t0, t1, ny, nx, ny, 1, twy, sgn, 1.0);
+  axis_dft(x0, x1, t0, t1, nx, ny, 1, ny, twx, sgn, scale);
+}
 
 }  // namespace kbe

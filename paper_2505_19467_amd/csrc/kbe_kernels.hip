@@ -265,6 +265,7 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
                                                int m, double UU, int corr) {
   constexpr int NBB = NB * NB;
   extern __shared__ cplx lds[];
+  __shared__ cplx twx[64], twy[64];
   cplx* gl = lds;
   cplx* gg = lds + d.nk;
   cplx* tl = lds + 2 * d.nk;
@@ -276,16 +277,15 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
   int j = item / NBB, ab = item - (item / NBB) * NBB;
   int t = threadIdx.x;
   int nx = d.nkx, ny = d.nky, nk = d.nk;
+  fill_roots(twx, nx);
+  fill_roots(twy, ny);
   for (int k = t; k < nk; k += 256) {
     gl[k] = row64[row64_idx(d, m, k, ab, j)];
     gg[k] = row64[row64_idx(d, m, k, NBB + ab, j)];
   }
   __syncthreads();
-  // k -> R: along y (lines ix, contiguous), then along x (lines ry, stride ny), 1/N_k
-  dft_lines(gl, gg, tl, tg, ny, nx, ny, 1, +1, 1.0);
-  __syncthreads();
-  dft_lines(tl, tg, gl, gg, nx, ny, 1, ny, +1, 1.0 / nk);
-  __syncthreads();
+  // k -> R (1/N_k)
+  grid_dft(gl, gg, tl, tg, nx, ny, twx, twy, +1, 1.0 / nk);
   for (int o = t; o < nk; o += 256) {
     cplx al = gl[o], ag = gg[o];
     cplx sl = czero(), sg = czero();
@@ -297,11 +297,8 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
     gg[o] = sg;
   }
   __syncthreads();
-  // R -> k: along y, then along x
-  dft_lines(gl, gg, tl, tg, ny, nx, ny, 1, -1, 1.0);
-  __syncthreads();
-  dft_lines(tl, tg, gl, gg, nx, ny, 1, ny, -1, 1.0);
-  __syncthreads();
+  // R -> k
+  grid_dft(gl, gg, tl, tg, nx, ny, twx, twy, -1, 1.0);
   for (int o = t; o < nk; o += 256) {
     cplx al = gl[o], ag = gg[o];
     sig[sig_idx(d, o, 0, ab, j)] = al;

@@ -63,6 +63,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
   d.Smax = (c->nt_max + 63) / 64;
   d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
+  d.rps = c->nb == 4 ? 2 : 1;
   d.N = c->nt_max + 1;
   d.P = kbe::strip_base((d.N + 63) / 64, d.N);
   const size_t cz = sizeof(cplx);
@@ -73,7 +74,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_RHOA] = sz[B_RHOB] = sz[B_DA] = sz[B_DB] = nk * d.nbb * cz;
   sz[B_PROP] = nk * 3 * d.nbb * cz;
   sz[B_COL0] = sz[B_DIAG] = sz[B_COLSUM] = nk * d.C * d.Tp * cz;
-  sz[B_ROWPART] = nk * (size_t)d.Smax * d.nbb * d.Tp * cz;
+  sz[B_ROWPART] = nk * (size_t)d.Smax * d.rps * d.nbb * d.Tp * cz;
   sz[B_HF] = d.nbb * cz;
   sz[B_HOP] = 3 * d.nbb * cz;
   sz[B_EIGW] = nk * d.nb * sizeof(double);

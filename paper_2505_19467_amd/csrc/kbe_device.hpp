@@ -84,6 +84,8 @@ struct Dims {
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
   int fp32;        // 1: the packed history is stored in FP32 (complex64)
+  int rps;         // row-partial slots per strip: 2 when the history sums split a block's components
+                   // between two wavefronts (nb = 4), else 1
   int64_t P;       // history elements per (k, component): one k occupies C * P elements
 };
 
@@ -106,6 +108,10 @@ __host__ __device__ __forceinline__ int64_t strip_lane_base(const Dims& d, int k
 // FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
 __host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {
   return (((int64_t)(row & 1) * d.nk + k) * d.C + c) * d.Tp + t;
+}
+// Row-partial sums of the history sums: [k][slot][nb^2][Tp], slot = strip * rps + half.
+__host__ __device__ __forceinline__ const cplx* rowpart_slot(const Dims& d, const cplx* rowpart, int k, int slot) {
+  return rowpart + ((int64_t)k * d.Smax * d.rps + slot) * d.nbb * d.Tp;
 }
 __host__ __device__ __forceinline__ int64_t rowbuf_idx(const Dims& d, int k, int c, int t) {
   return ((int64_t)k * d.C + c) * d.Tp + t;

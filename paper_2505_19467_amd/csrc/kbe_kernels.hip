@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restric
   for (int c = 0; c < C; ++c) acc[c] = czero();
   // strip s of k: rows j >= 64 s, each a run of C component segments of 64 elements
   const cplx* hk = hist + strip_lane_base(d, k, s, lane);
-  cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
     cplx G[R][C];
 #pragma unroll
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
     acc32[c] = make_float2(0.f, 0.f);
   }
   const cplx32* hk = hist + strip_lane_base(d, k, s, lane);
-  cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
   int it = 0;
   for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
     cplx32 G[R][C];
@@ -712,6 +712,201 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
   }
 }
 
+// ------------------------------------------------------------------ history sums, nb = 4
+// With nb = 4 a stored block has 2 nb^2 = 32 components, too many for one wavefront's
+// registers next to its column sums. The block's components are split by half: waves 0 and 2
+// stream G^< (components 0..15), waves 1 and 3 stream G^> (16..31), each over every second row
+// of the strip (R = 1 row per iteration: 16 contiguous 1 KB segments in flight per wavefront).
+// Half 0 contributes -Sigma^>_{t'} (G^<_{j t'})^dag to the row term, half 1 +Sigma^<_{t'}
+// (G^>_{j t'})^dag; each half's row partials go to their own slot (strip * 2 + half), summed by
+// k_row. The per-column Sigma of the row term is read from LDS. FP64 storage.
+template <int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hist_bulk_split(
+    Dims d, const cplx* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+    cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  __shared__ cplx sS[2][NBB][64];  // [half][e][lane]: half 0 needs Sigma^>, half 1 Sigma^<;
+                                   // reused for the column-sum combine after the row loop
+  int s = blockIdx.x / d.nk;
+  int k = blockIdx.x - s * d.nk;
+  int lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform: rows and Sigma^R in SGPRs
+  int h = wv & 1, rg = wv >> 1;
+  int tp = 64 * s + lane;
+  bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  for (int i = threadIdx.x; i < 2 * NBB * 64; i += 256) {
+    int x = i / (NBB * 64), e = (i / 64) % NBB, l = i % 64;
+    int t = 64 * s + l;
+    sS[x][e][l] = t < m ? sk[((1 - x) * NBB + e) * d.Tp + t] : czero();
+  }
+  __syncthreads();
+  cplx acc[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) acc[e] = czero();
+  const cplx* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
+  const double sgn = h ? 1.0 : -1.0;
+  for (int j = 64 * s + rg; j < m; j += 2) {
+    bool v = colv && tp <= j;
+    const cplx* row = hk + 64 * (int64_t)C * j;
+    cplx G[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) G[e] = v ? load_stream(row + 64 * e) : czero();
+    bool rv = tp < j;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      cplx SRi[NB];
+#pragma unroll
+      for (int l = 0; l < NB; ++l) SRi[l] = sk[(2 * NBB + i * NB + l) * d.Tp + j];
+      // column term, row i:  acc[i][jj] += sum_l SR[i][l] G[l][jj]
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) cmac(acc[i * NB + jj], SRi[l], G[l * NB + jj]);
+      // row term, row i:  sgn * sum_l S[i][l] conj(G[jj][l]), reduced over the 64 lanes
+      double x[2 * NB];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        cplx a = czero();
+#pragma unroll
+        for (int l = 0; l < NB; ++l) cmacc(a, sS[h][i * NB + l][lane], G[jj * NB + l]);
+        x[2 * jj] = rv ? sgn * a.x : 0.0;
+        x[2 * jj + 1] = rv ? sgn * a.y : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NB; ++q) {
+        double y = rs_half(x[q], x[q]);
+        x[q] = row16_sum(rs_row(y, y));
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) rp[(int64_t)(i * NB + jj) * d.Tp + j] = cmk(x[2 * jj], x[2 * jj + 1]);
+      }
+      asm volatile("" ::: "memory");  // keep the next row i's loads after this one (register pressure)
+    }
+  }
+  __syncthreads();  // every wavefront is done with sS
+  cplx (*red)[NBB][64] = sS;
+  if (rg == 1) {
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) red[h][e][lane] = acc[e];
+  }
+  __syncthreads();
+  if (rg == 0 && colv) {
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) colsum[rowbuf_idx(d, k, h * NBB + e, tp)] = cadd(acc[e], red[h][e][lane]);
+  }
+}
+
+// FP32 form of k_hist_bulk_split: each half's 16 components are 8 column-interleaved pairs,
+// one 16-byte load each; FP32 products and row reductions, column sums in FP32 over tiles of
+// 16 rows per wavefront, then FP64.
+template <int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hist_bulk32_split(Dims d, const cplx32* __restrict__ hist,
+                                                           const cplx* __restrict__ sig,
+                                                           cplx* __restrict__ colsum, cplx* __restrict__ rowpart,
+                                                           int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  static_assert(NBB % 2 == 0, "component pairs must not straddle the halves");
+  constexpr int FLUSH = 16;
+  __shared__ cplx32 sS[2][NBB][64];
+  __shared__ cplx red[2][NBB][64];
+  int s = blockIdx.x / d.nk;
+  int k = blockIdx.x - s * d.nk;
+  int lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform: rows and Sigma^R in SGPRs
+  int h = wv & 1, rg = wv >> 1;
+  int tp = 64 * s + lane;
+  bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  for (int i = threadIdx.x; i < 2 * NBB * 64; i += 256) {
+    int x = i / (NBB * 64), e = (i / 64) % NBB, l = i % 64;
+    int t = 64 * s + l;
+    sS[x][e][l] = to32(t < m ? sk[((1 - x) * NBB + e) * d.Tp + t] : czero());
+  }
+  __syncthreads();
+  cplx acc[NBB];
+  cplx32 acc32[NBB];
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) {
+    acc[e] = czero();
+    acc32[e] = make_float2(0.f, 0.f);
+  }
+  const cplx32* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
+  const float sgn = h ? 1.f : -1.f;
+  int it = 0;
+  for (int j = 64 * s + rg; j < m; j += 2) {
+    bool v = colv && tp <= j;
+    const cplx32* row = hk + 64 * (int64_t)C * j;
+    cplx32 G[NBB];
+#pragma unroll
+    for (int p = 0; p < NBB / 2; ++p) {
+      if (v) {
+        load_stream32x2(row + 128 * p, G[2 * p], G[2 * p + 1]);
+      } else {
+        G[2 * p] = make_float2(0.f, 0.f);
+        G[2 * p + 1] = make_float2(0.f, 0.f);
+      }
+    }
+    bool rv = tp < j;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      cplx32 SRi[NB];
+#pragma unroll
+      for (int l = 0; l < NB; ++l) SRi[l] = to32(sk[(2 * NBB + i * NB + l) * d.Tp + j]);
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) cmac32(acc32[i * NB + jj], SRi[l], G[l * NB + jj]);
+      float x[2 * NB];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        cplx32 a = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) cmacc32(a, sS[h][i * NB + l][lane], G[jj * NB + l]);
+        x[2 * jj] = rv ? sgn * a.x : 0.f;
+        x[2 * jj + 1] = rv ? sgn * a.y : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < 2 * NB; ++q) {
+        float y = rs_half32(x[q], x[q]);
+        x[q] = row16_sum32(rs_row32(y, y));
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj)
+          rp[(int64_t)(i * NB + jj) * d.Tp + j] = cmk((double)x[2 * jj], (double)x[2 * jj + 1]);
+      }
+      asm volatile("" ::: "memory");
+    }
+    if (++it == FLUSH) {
+      it = 0;
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) {
+        acc[e].x += (double)acc32[e].x;
+        acc[e].y += (double)acc32[e].y;
+        acc32[e] = make_float2(0.f, 0.f);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < NBB; ++e) {
+    acc[e].x += (double)acc32[e].x;
+    acc[e].y += (double)acc32[e].y;
+  }
+  if (rg == 1) {
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) red[h][e][lane] = acc[e];
+  }
+  __syncthreads();
+  if (rg == 0 && colv) {
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) colsum[rowbuf_idx(d, k, h * NBB + e, tp)] = cadd(acc[e], red[h][e][lane]);
+  }
+}
+
 // ------------------------------------------------------------------ row assembly and update
 // Thread per (k, t'), t' <= m.
 //  EVAL/CORRECT, t' < m: I^{<,>}(t_m, t') = dt [bulk + end-point terms], where the
@@ -744,9 +939,9 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
       for (int c = 0; c < C; ++c) In[c] = colsum[rowbuf_idx(d, k, c, tp)];
       cplx rs[NBB];
       mat_zero<NB>(rs);
-      int ns = (tp >> 6) + 1;
-      for (int s = 0; s < ns; ++s) {
-        const cplx* rp = rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
+      int nslot = ((tp >> 6) + 1) * d.rps;
+      for (int q = 0; q < nslot; ++q) {
+        const cplx* rp = rowpart_slot(d, rowpart, k, q);
 #pragma unroll
         for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], rp[(int64_t)e * d.Tp + tp]);
       }
@@ -1060,12 +1255,21 @@ struct Launch {
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     if (m < 1) return hipSuccess;
     int ns = (m + 63) / 64;
-    if (d.fp32)
-      hipLaunchKernelGGL(k_hist_bulk32<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
-                         (const cplx*)a.sig, a.colsum, a.rowpart, m);
-    else
-      hipLaunchKernelGGL(k_hist_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
-                         (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    if constexpr (NB == 4) {
+      if (d.fp32)
+        hipLaunchKernelGGL(k_hist_bulk32_split<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+      else
+        hipLaunchKernelGGL(k_hist_bulk_split<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    } else {
+      if (d.fp32)
+        hipLaunchKernelGGL(k_hist_bulk32<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+      else
+        hipLaunchKernelGGL(k_hist_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    }
     return hipGetLastError();
   }
   static hipError_t row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {

@@ -69,7 +69,7 @@ def test_fp32_collision_row(K, nkx, nky, nb, m):
 SERIES = ["N", "Ekin", "EHF", "Ecorr", "Etot", "Jx", "n_orb0", "n_orb1", "n_band0", "n_band1"]
 
 
-@pytest.mark.parametrize("name,nsteps", [("c1", 200), ("c4", 60), ("c2", 40)])
+@pytest.mark.parametrize("name,nsteps", [("c1", 200), ("c4", 60), ("c2", 40), ("c5", 70)])
 def test_fp32_run_accuracy(K, name, nsteps):
     _say(f"fp32 run {name} steps={nsteps}")
     cfg = inputs.WORKLOADS[name]().replace(precision=inputs.PRECISION_FP32)

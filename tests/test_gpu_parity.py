@@ -182,6 +182,7 @@ def _compare_run(K, cfg, nsteps):
     ("c1", dict(hf=0, pulse=inputs.Pulse(amp=0.0)), 60),
     ("c4", {}, 70),
     ("c2", {}, 40),
+    ("c5", {}, 70),  # the nb = 4 workload, truncated (its history at n_t = 1600 is 175 GB)
 ])
 def test_run_parity_workloads(K, name, mods, nsteps):
     _say(f"run parity {name} {mods} steps={nsteps}")

@@ -40,7 +40,9 @@
 //   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
 //   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
 //                     dt-convergence ratio 4, TDHF limit vs RK4
-
+//   symmetry ........ full-square mode: the upper triangle propagated on its own with the
+//                     t'-equation and right-form collision integrals equals -G^dag of the
+//                     lower one to rounding (Hubbard and interband presets); rho Hermitian
 //   tangent-linear .. R = double run reproduced bit-for-bit by the value part; derivatives
 //                     against central finite differences of the double oracle
 
@@ -461,19 +463,19 @@ struct Dft {
   }
 };
 
-// Second-Born self-energy on row m, eq. (2BSE), for every t_j, j = 0..m:
-//   Sigma^<(k; t_m, t_j) and Sigma^>(k; t_m, t_j) from G(k; t_m, t_j) (row m) and
-//   G(k; t_j, t_m) = -[G(k; t_m, t_j)]^dag.
-// In real space the double k-sum of eq. (2BSE) becomes a product at each lattice
-// vector R (momentum conservation): for the Hubbard preset (opposite-spin bubble)
+// Second-Born self-energy, eq. (2BSE), for pairs of times: out[j] = Sigma(k; t_x, t_j) from the
+// forward line fwd[j] = G(k; t_x, t_j) and the backward line bwd[j] = G(k; t_j, t_x), j = 0..m.
+// In real space the double k-sum of eq. (2BSE) becomes a product at each lattice vector R
+// (momentum conservation): for the Hubbard preset (opposite-spin bubble)
 //   Sigma^<_ab(R; t,t') = U^2 G^<_ab(R; t,t') G^<_ab(R; t,t') G^>_ba(-R; t',t)
 // and for the paper's interband preset (jbar = other band)
 //   Sigma^<_jm(R) = U^2 G^>_{mbar jbar}(-R; t',t) [G^<_{jbar mbar}(R) G^<_jm(R)
 //                                                - G^<_{j mbar}(R) G^<_{jbar m}(R)],
 // with lesser and greater swapped for Sigma^>. U(t) is constant here.
-// row: [j][k][comp][a][b]; out: same layout.
+// fwd, bwd, out: [j][k][comp][a][b].
 template <class R>
-void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const Cx<R>* row, Cx<R>* out) {
+void sigma_pairs(const Params& p, const Theta<R>& th, const Grid& g, int m, const Cx<R>* fwd, const Cx<R>* bwd,
+                 Cx<R>* out) {
   typedef Cx<R> C;
   int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
   Dft<R> dft(g);
@@ -484,17 +486,14 @@ void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const 
   }
 #pragma omp parallel for schedule(dynamic)
   for (int j = 0; j <= m; ++j) {
-    // gf[comp][a][b][R] = G^comp_ab(R; t_m, t_j); gb[comp][a][b][R] = G^comp_ab(-R; t_j, t_m)
+    // gf[comp][a][b][R] = G^comp_ab(R; t_x, t_j); gb[comp][a][b][R] = G^comp_ab(-R; t_j, t_x)
     std::vector<C> gf(blk * nk), gb(blk * nk), in(nk), o(nk), sr(blk * nk);
     for (int comp = 0; comp < 2; ++comp)
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b) {
-          for (int k = 0; k < nk; ++k)
-            in[k] = row[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b];
+          for (int k = 0; k < nk; ++k) in[k] = fwd[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b];
           dft.to_real(in.data(), &gf[((comp * nb + a) * nb + b) * nk]);
-          // G(k; t_j, t_m)_{ab} = -conj(G(k; t_m, t_j)_{ba})
-          for (int k = 0; k < nk; ++k)
-            in[k] = -conj(row[((size_t)j * nk + k) * blk + comp * nbb + b * nb + a]);
+          for (int k = 0; k < nk; ++k) in[k] = bwd[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b];
           dft.to_real(in.data(), &gb[((comp * nb + a) * nb + b) * nk], -1);
         }
     auto G = [&](const std::vector<C>& v, int comp, int a, int b, int Rv) -> C {
@@ -521,10 +520,24 @@ void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const 
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b) {
           dft.to_k(&sr[((comp * nb + a) * nb + b) * nk], o.data());
-          for (int k = 0; k < nk; ++k)
-            out[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b] = o[k];
+          for (int k = 0; k < nk; ++k) out[((size_t)j * nk + k) * blk + comp * nbb + a * nb + b] = o[k];
         }
   }
+}
+
+// Self-energy on row m: Sigma(k; t_m, t_j), j = 0..m, from row m alone, the backward line
+// being G(k; t_j, t_m) = -[G(k; t_m, t_j)]^dag. row, out: [j][k][comp][a][b].
+template <class R>
+void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const Cx<R>* row, Cx<R>* out) {
+  typedef Cx<R> C;
+  int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
+  std::vector<C> bwd((size_t)(m + 1) * nk * blk);
+  for (size_t jk = 0; jk < (size_t)(m + 1) * nk; ++jk)
+    for (int comp = 0; comp < 2; ++comp)
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+          bwd[jk * blk + comp * nbb + a * nb + b] = -conj(row[jk * blk + comp * nbb + b * nb + a]);
+  sigma_pairs(p, th, g, m, row, bwd.data(), out);
 }
 
 // ---------------------------------------------------------------- collision integral
@@ -542,9 +555,10 @@ double trap(int j, int pend) {
 //   Sigma^R = Sigma^> - Sigma^< (tb < t_m),  G^A(tb,t') = -(G^> - G^<)(tb, t') (tb < t'),
 // on the grid with trapezoid weights, for t' = t_0 .. t_m.
 // hist(j, t', k) returns the stored block (j >= t'); blocks above the diagonal come from
-// G(j, t') = -[G(t', j)]^dag.
+// G(j, t') = -[G(t', j)]^dag, unless full_square, when hist returns G(t_j, t') for any pair.
 template <class R, class Hist>
-void collision_row(const Params& p, const Grid& g, int m, Hist hist, const Cx<R>* sig, Cx<R>* Iout) {
+void collision_row(const Params& p, const Grid& g, int m, Hist hist, const Cx<R>* sig, Cx<R>* Iout,
+                   bool full_square = false) {
   typedef Cx<R> C;
   int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
   double dt = p.dt;
@@ -555,7 +569,7 @@ void collision_row(const Params& p, const Grid& g, int m, Hist hist, const Cx<R>
       std::fill(acc.begin(), acc.end(), C());
       for (int j = 0; j <= m; ++j) {
         // G(t_j, t')
-        if (j >= tp) {
+        if (j >= tp || full_square) {  // full_square: hist holds G(t_j, t') for every pair
           const C* src = hist(j, tp, k);
           std::copy(src, src + blk, Gb.begin());
         } else {
@@ -790,6 +804,178 @@ void init(State<R>& st) {
 
 typedef Cx<double> C;
 
+// ---------------------------------------------------------------- full-square propagation
+// Test-only mode that pins the symmetry G^{<,>}(t,t')^dag = -G^{<,>}(t',t): the upper triangle
+// G(t_j, t_m), j < m, is NOT taken from the lower one but propagated on its own with the
+// adjoint (t'-derivative) equation of motion,
+//   -i d/dt' G(t,t') = G(t,t') h(t') + I_R(t,t'),
+//   I_R^{<,>}(t,t') = int_0^t dtb G^R(t,tb) Sigma^{<,>}(tb,t') + int_0^t' dtb G^{<,>}(t,tb) Sigma^A(tb,t'),
+// in the same exponential midpoint form, G(t_j, t_m) = G(t_j, t_{m-1}) V^dag + Ibar_R Phi^dag, with
+// its own self-energy column Sigma(t_j, t_m) (forward line from the upper triangle, backward
+// line from the lower). Both triangles feed each other's collision integrals and self-energies;
+// the diagonal follows the density matrix as in the plain scheme.
+
+// Right-form collision integrals of column m: IR[j] = I_R(t_j, t_m), j = 0..m, with trapezoid
+// weights; Gat(i, j, k) gives G(t_i, t_j) for any pair; sigcol[l] = Sigma(t_l, t_m).
+template <class GA>
+void collision_col(const Params& p, const Grid& g, int m, GA Gat, const C* sigcol, C* IR) {
+  int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
+  double dt = p.dt;
+#pragma omp parallel for schedule(dynamic)
+  for (int k = 0; k < nk; ++k) {
+    std::vector<C> GR(nbb), SR(nbb), tmp(nbb), acc(blk);
+    for (int j = 0; j <= m; ++j) {
+      std::fill(acc.begin(), acc.end(), C());
+      // int_0^{t_j} G^R(t_j, t_l) Sigma^{<,>}(t_l, t_m),  G^R = G^> - G^< (t_l < t_j)
+      for (int l = 0; l <= j; ++l) {
+        double w = trap(l, j) * dt;
+        if (w == 0.0) continue;
+        const C* G = Gat(j, l, k);
+        for (int i = 0; i < nbb; ++i) GR[i] = G[nbb + i] - G[i];
+        const C* S = sigcol + ((size_t)l * nk + k) * blk;
+        for (int c = 0; c < 2; ++c) {
+          mm(nb, GR.data(), S + c * nbb, tmp.data());
+          for (int i = 0; i < nbb; ++i) acc[c * nbb + i] += tmp[i] * w;
+        }
+      }
+      // int_0^{t_m} G^{<,>}(t_j, t_l) Sigma^A(t_l, t_m),  Sigma^A = -(Sigma^> - Sigma^<) (t_l < t_m)
+      for (int l = 0; l <= m; ++l) {
+        double w = trap(l, m) * dt;
+        if (w == 0.0) continue;
+        const C* G = Gat(j, l, k);
+        const C* S = sigcol + ((size_t)l * nk + k) * blk;
+        for (int i = 0; i < nbb; ++i) SR[i] = S[nbb + i] - S[i];
+        for (int c = 0; c < 2; ++c) {
+          mm(nb, G + c * nbb, SR.data(), tmp.data());
+          for (int i = 0; i < nbb; ++i) acc[c * nbb + i] -= tmp[i] * w;
+        }
+      }
+      std::copy(acc.begin(), acc.end(), IR + ((size_t)j * nk + k) * blk);
+    }
+  }
+}
+
+struct FullSquare {
+  Params p;
+  Grid g;
+  Theta<double> th;
+  std::vector<C> hop;
+  int n, nk, nb, nbb, blk;
+  std::vector<C> G;  // [(i * (n + 1) + j) * nk + k][blk] = G(k; t_i, t_j)
+  std::vector<C> rho_prev, rho_cur, D_prev, D_cur;
+  std::vector<C> I_prev, I_cur;    // rows:    [t'][k][blk] = I(t_m, t')
+  std::vector<C> IR_prev, IR_cur;  // columns: [j][k][blk]  = I_R(t_j, t_m)
+  FullSquare(const Params& p_, const double* hopd, int nsteps)
+      : p(p_), g(p_), th{p_.amp, p_.omega, p_.U}, n(nsteps) {
+    nk = g.nk;
+    nb = g.nb;
+    nbb = nb * nb;
+    blk = 2 * nbb;
+    hop.resize(3 * nbb);
+    for (int i = 0; i < 3 * nbb; ++i) hop[i] = C(hopd[2 * i], hopd[2 * i + 1]);
+    G.assign((size_t)(n + 1) * (n + 1) * nk * blk, C());
+  }
+  C* at(int i, int j, int k) { return &G[(((size_t)i * (n + 1) + j) * nk + k) * blk]; }
+  void eval(int m) {
+    size_t sz = (size_t)(m + 1) * nk * blk;
+    std::vector<C> fwd(sz), bwd(sz), sr(sz), sc(sz);
+    for (int j = 0; j <= m; ++j)
+      for (int k = 0; k < nk; ++k) {
+        std::copy(at(m, j, k), at(m, j, k) + blk, &fwd[((size_t)j * nk + k) * blk]);
+        std::copy(at(j, m, k), at(j, m, k) + blk, &bwd[((size_t)j * nk + k) * blk]);
+      }
+    sigma_pairs(p, th, g, m, fwd.data(), bwd.data(), sr.data());  // Sigma(t_m, t_j)
+    sigma_pairs(p, th, g, m, bwd.data(), fwd.data(), sc.data());  // Sigma(t_j, t_m)
+    I_cur.assign(sz, C());
+    collision_row<double>(p, g, m, [&](int j, int tp, int k) { return (const C*)at(j, tp, k); }, sr.data(),
+                          I_cur.data(), true);
+    IR_cur.assign(sz, C());
+    collision_col(p, g, m, [&](int i, int j, int k) { return (const C*)at(i, j, k); }, sc.data(), IR_cur.data());
+    D_cur.assign(nk * nbb, C());
+    for (int k = 0; k < nk; ++k) {
+      const C* Ik = &I_cur[((size_t)m * nk + k) * blk];
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) D_cur[k * nbb + a * nb + b] = Ik[a * nb + b] + conj(Ik[b * nb + a]);
+    }
+  }
+  void update(int m, bool corrector) {
+    std::vector<C> rho_h(nk * nbb);
+    for (int i = 0; i < nk * nbb; ++i) rho_h[i] = corrector ? (rho_prev[i] + rho_cur[i]) * 0.5 : rho_prev[i];
+    std::vector<C> hf(nbb), ob(nbb);
+    hf_field(p, th, g, rho_h, hf.data());
+    onebody_extra(p, th, nb, ob.data());
+    for (int i = 0; i < nbb; ++i) hf[i] += ob[i];
+    double Amid = pulse_A(p, th, (m - 0.5) * p.dt);
+    std::vector<C> new_rho(nk * nbb);
+    for (int k = 0; k < nk; ++k) {
+      std::vector<C> h(nbb), V(nbb), Vh(nbb), Phi(nbb), Vd(nbb), Phid(nbb), Ib(blk), t1(nbb), t2(nbb), t3(nbb),
+          adj(nbb);
+      h0(p, g, hop.data(), k, Amid, h.data());
+      for (int i = 0; i < nbb; ++i) h[i] += hf[i];
+      propagators(nb, p.dt, h.data(), V.data(), Vh.data(), Phi.data());
+      adjoint(nb, V.data(), Vd.data());
+      adjoint(nb, Phi.data(), Phid.data());
+      for (int t = 0; t < m; ++t) {
+        // row: G(t_m, t) = V G(t_{m-1}, t) + Phi Ibar(t)
+        for (int i = 0; i < blk; ++i) {
+          C a = I_prev[((size_t)t * nk + k) * blk + i];
+          Ib[i] = corrector ? (a + I_cur[((size_t)t * nk + k) * blk + i]) * 0.5 : a;
+        }
+        for (int c = 0; c < 2; ++c) {
+          mm(nb, V.data(), at(m - 1, t, k) + c * nbb, t1.data());
+          mm(nb, Phi.data(), &Ib[c * nbb], t2.data());
+          for (int i = 0; i < nbb; ++i) at(m, t, k)[c * nbb + i] = t1[i] + t2[i];
+        }
+        // column: G(t, t_m) = G(t, t_{m-1}) V^dag + IbarR(t) Phi^dag
+        for (int i = 0; i < blk; ++i) {
+          C a = IR_prev[((size_t)t * nk + k) * blk + i];
+          Ib[i] = corrector ? (a + IR_cur[((size_t)t * nk + k) * blk + i]) * 0.5 : a;
+        }
+        for (int c = 0; c < 2; ++c) {
+          mm(nb, at(t, m - 1, k) + c * nbb, Vd.data(), t1.data());
+          mm(nb, &Ib[c * nbb], Phid.data(), t2.data());
+          for (int i = 0; i < nbb; ++i) at(t, m, k)[c * nbb + i] = t1[i] + t2[i];
+        }
+      }
+      std::vector<C> Db(nbb);
+      for (int i = 0; i < nbb; ++i) Db[i] = corrector ? (D_prev[k * nbb + i] + D_cur[k * nbb + i]) * 0.5 : D_prev[k * nbb + i];
+      mm(nb, V.data(), &rho_prev[k * nbb], t1.data());
+      mm(nb, t1.data(), Vd.data(), t2.data());
+      mm(nb, Vh.data(), Db.data(), t1.data());
+      adjoint(nb, Vh.data(), adj.data());
+      mm(nb, t1.data(), adj.data(), t3.data());
+      for (int i = 0; i < nbb; ++i) new_rho[k * nbb + i] = t2[i] - t3[i] * p.dt;
+    }
+    rho_cur = new_rho;
+    for (int k = 0; k < nk; ++k) set_diag_block(nb, &rho_cur[k * nbb], at(m, m, k));
+  }
+  void run() {
+    std::vector<C> rho0;
+    initial_state(p, g, hop.data(), rho0);
+    rho_cur = rho0;
+    for (int k = 0; k < nk; ++k) set_diag_block(nb, &rho_cur[k * nbb], at(0, 0, k));
+    rho_prev = rho_cur;
+    eval(0);
+    I_prev = I_cur;
+    IR_prev = IR_cur;
+    D_prev = D_cur;
+    for (int m = 1; m <= n; ++m) {
+      update(m, false);
+      for (int it = 0; it < p.n_corr; ++it) {
+        eval(m);
+        update(m, true);
+      }
+      eval(m);
+      I_prev = I_cur;
+      IR_prev = IR_cur;
+      D_prev = D_cur;
+      rho_prev = rho_cur;
+    }
+  }
+};
+
+typedef Cx<double> C;
+
 void to_doubles(const C* src, size_t n, double* dst) {
   for (size_t i = 0; i < n; ++i) { dst[2 * i] = src[i].re; dst[2 * i + 1] = src[i].im; }
 }
@@ -941,6 +1127,55 @@ int oracle_h0(const Params* p, const double* hop, double A, double* out) {
     h0(*p, g, H.data(), k, A, h.data());
     to_doubles(h.data(), nbb, out + 2 * (size_t)k * nbb);
   }
+  return 0;
+}
+
+// Full-square propagation (test only): out[0] = max |G(t_i,t_j) + G(t_j,t_i)^dag| / max |G| over
+// i < j, out[1] = max |rho - rho^dag| over all steps' final rho, out[2] = max relative difference
+// of the lower triangle from the plain run's rows (which take the upper triangle as -G^dag).
+int oracle_full_square_check(const Params* p, const double* hop, int32_t nsteps, double* out) {
+  if (p->nt < nsteps) return -1;
+  FullSquare fsq(*p, hop, nsteps);
+  fsq.run();
+  int nk = fsq.nk, nb = fsq.nb, nbb = fsq.nbb, blk = fsq.blk, n = nsteps;
+  double gmax = 0.0, asym = 0.0;
+  for (int i = 0; i <= n; ++i)
+    for (int j = 0; j <= n; ++j)
+      for (int k = 0; k < nk; ++k) {
+        const C* a = fsq.at(i, j, k);
+        for (int e = 0; e < blk; ++e) gmax = std::max(gmax, std::sqrt(abs2(a[e])));
+        if (i >= j) continue;
+        const C* b = fsq.at(j, i, k);
+        for (int c = 0; c < 2; ++c)
+          for (int x = 0; x < nb; ++x)
+            for (int y = 0; y < nb; ++y) {
+              C d = a[c * nbb + x * nb + y] + conj(b[c * nbb + y * nb + x]);
+              asym = std::max(asym, std::sqrt(abs2(d)));
+            }
+      }
+  double herm = 0.0;
+  for (int k = 0; k < nk; ++k)
+    for (int x = 0; x < nb; ++x)
+      for (int y = 0; y < nb; ++y) {
+        C d = fsq.rho_cur[k * nbb + x * nb + y] - conj(fsq.rho_cur[k * nbb + y * nb + x]);
+        herm = std::max(herm, std::sqrt(abs2(d)));
+      }
+  // plain run on the same parameters
+  Theta<double> th{p->amp, p->omega, p->U};
+  State<double> st(*p, th, hop);
+  init(st);
+  for (int m = 1; m <= n; ++m) step(st, m);
+  double diff = 0.0;
+  for (int i = 0; i <= n; ++i)
+    for (int j = 0; j <= i; ++j)
+      for (int k = 0; k < nk; ++k) {
+        const C* a = fsq.at(i, j, k);
+        const C* b = st.at(i, j, k);
+        for (int e = 0; e < blk; ++e) diff = std::max(diff, std::sqrt(abs2(a[e] - b[e])));
+      }
+  out[0] = asym / gmax;
+  out[1] = herm;
+  out[2] = diff / gmax;
   return 0;
 }
 

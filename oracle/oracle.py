@@ -62,6 +62,7 @@ def lib():
         _lib.oracle_initial_state.argtypes = [P, dp, dp, dp]
         _lib.oracle_h0.argtypes = [P, dp, ctypes.c_double, dp]
         _lib.oracle_tlm_run.argtypes = [P, dp, ctypes.c_int32, dp, dp]
+        _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
     return _lib
 
 
@@ -124,6 +125,18 @@ def tlm_run(cfg, nsteps: int | None = None):
     if rc != 0:
         raise ValueError(f"oracle_tlm_run rejected the configuration (rc={rc})")
     return obs, dobs
+
+
+def full_square_check(cfg, nsteps: int):
+    """Full-square propagation (upper triangle from the t'-equation with right-form collision
+    integrals). Returns (asymmetry max|G(t,t') + G(t',t)^dag| / max|G|, max|rho - rho^dag|,
+    max relative difference of the lower triangle from the plain run)."""
+    out = np.zeros(3)
+    p = params(cfg)
+    rc = lib().oracle_full_square_check(ctypes.byref(p), _ptr(_hop(cfg)), nsteps, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_full_square_check rejected the configuration (rc={rc})")
+    return tuple(out)
 
 
 def sigma_row(cfg, m: int, row: np.ndarray) -> np.ndarray:

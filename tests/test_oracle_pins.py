@@ -315,3 +315,25 @@ def test_tlm_matches_central_differences(cfg_name):
     tlm = dobs[-1, i]
     assert np.all(np.abs(tlm - fd) <= 1e-6 * np.abs(fd).max() + 1e-12), (tlm, fd)
     assert np.abs(tlm).min() > 0  # every parameter moves the observable
+
+
+# ---------------------------------------------------------------- two-time symmetry
+@pytest.mark.parametrize("name,mods,n", [
+    ("c1", dict(nkx=4), 30),
+    ("c4", dict(nkx=3, nky=4, dt=0.05), 25),
+    ("c1", dict(nkx=4, hf=0, n_corr=2), 20),
+    ("c1", dict(nkx=5, interaction=inputs.INTERACTION_INTERBAND, hf=0), 20),
+])
+def test_two_time_symmetry_full_square(name, mods, n):
+    """G^{<,>}(t,t')^dag = -G^{<,>}(t',t): a full-square run propagates the upper triangle on
+    its own with the t'-equation of motion and right-form collision integrals (G^R Sigma and
+    G Sigma^A, with its own self-energy column), both triangles feeding each other. The scheme's
+    left form (Sigma^R G + Sigma G^A on rows, upper blocks taken as -G^dag) must give the mirror
+    image to rounding; a planted mistake in the left form (a weight on the wrong interval, the
+    operand order, the sign of G^A, Sigma^R without Sigma^<) breaks the symmetry at 1e-4..1e-2.
+    The density matrix stays Hermitian, and the full-square lower triangle equals the plain run."""
+    cfg = inputs.WORKLOADS[name]().replace(**mods)
+    asym, herm, lower = O.full_square_check(cfg, n)
+    assert asym < 1e-13, asym
+    assert herm < 1e-14, herm
+    assert lower < 1e-13, lower

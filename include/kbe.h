@@ -82,7 +82,6 @@ typedef struct {
   int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes */
   int32_t nt_max;       /* largest step index the buffers hold */
   int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
-  int32_t adjoint;      /* 1: keep the per-step record (rho_m, D_m) the adjoint needs */
   double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
 } kbe_config;
 
@@ -126,9 +125,8 @@ int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* wo
  *           h0(k) = T0 + sum_d (T_d e^{i k_d} + T_d^dag e^{-i k_d}); Ty is ignored when nky = 1.
  *   pulse : host, may be NULL (no pulse).
  *   d_history, d_workspace, d_obs : device buffers and their sizes in bytes; each size must
- *           be at least what kbe_workspace_query returns for the same cfg (the adjoint flag
- *           adds the per-step record to the workspace), else KBE_ERR_INVALID_ARG and nothing
- *           is launched.
+ *           be at least what kbe_workspace_query returns for the same cfg, else
+ *           KBE_ERR_INVALID_ARG and nothing is launched.
  *   hip_stream : hipStream_t to enqueue on (NULL = default stream).
  */
 int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
@@ -177,26 +175,26 @@ enum {
  * _PREV/_CUR roles swap at every completed step). */
 int kbe_buffer(const kbe_ctx* ctx, int32_t which, void** ptr, size_t* bytes);
 
-/* a-1: hbar = h0(k - A(t_{m-1/2})) + Sigma^HF[rho], rho = rho_{m-1} (mode 0) or
+/* Propagators: hbar = h0(k - A(t_{m-1/2})) + Sigma^HF[rho], rho = rho_{m-1} (mode 0) or
  * (rho_{m-1} + rho_m)/2 (mode 1), and V, Vh, Phi per k into KBE_BUF_PROP. */
 int kbe_stage_propagators(kbe_ctx* ctx, int32_t m, int32_t mode);
 
-/* a-2: second-Born Sigma^{<,>}(k; t_m, t_j), j = 0..m, from history row m (eq. (2BSE)), by
+/* Self-energy: second-Born Sigma^{<,>}(k; t_m, t_j), j = 0..m, from history row m (eq. (2BSE)), by
  * batched k <-> R transforms and pointwise products, into KBE_BUF_SIGMA. */
 int kbe_stage_sigma(kbe_ctx* ctx, int32_t m);
 
-/* a-3 + a-4: collision integrals I^{<,>}(t_m, t'), t' = 0..m (eq. (CI), Langreth left form,
+/* Collision integrals: I^{<,>}(t_m, t'), t' = 0..m (eq. (CI), Langreth left form,
  * trapezoid weights) from history rows 0..m, KBE_BUF_SIGMA, COL0 and DIAG, into
  * KBE_BUF_I_CUR; D_m into KBE_BUF_D_CUR. */
 int kbe_stage_collision(kbe_ctx* ctx, int32_t m);
 
-/* a-5: row m of the history and rho_m from row m-1:
+/* Update: row m of the history and rho_m from row m-1:
  * mode 0 (predictor): G(t_m, t') = V G(t_{m-1}, t') + Phi I(t_{m-1}, t'),
  * mode 1 (corrector): same with (I(t_{m-1}, .) + I(t_m, .))/2 (recomputes I(t_m, .) first);
  * rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag, and the equal-time block. */
 int kbe_stage_update(kbe_ctx* ctx, int32_t m, int32_t mode);
 
-/* a-6: observables of t_m from rho_m and I^<(t_m, t_m) into row m of d_obs. */
+/* Observables of t_m from rho_m and I^<(t_m, t_m) into row m of d_obs. */
 int kbe_stage_observables(kbe_ctx* ctx, int32_t m);
 
 /* Make step m the current step and swap the _PREV/_CUR roles as kbe_step does after
@@ -215,7 +213,7 @@ int kbe_timing(kbe_ctx* ctx, int32_t enable);
 int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* algo_bytes);
 
 /* ---------------------------------------------------------------------------------------
- * a-8: adjoint (reverse mode) of the propagation. The paper defines the forward map only
+ * Adjoint (reverse mode) of the propagation. The paper defines the forward map only
  * (Algorithm "prop" with eqs. (Green), (CI), (2BSE)); the adjoint is the exact discrete
  * transpose of that map as the forward kernels evaluate it, so the gradient it returns is
  * the derivative of the computed observable, not of the continuous equations.
@@ -225,11 +223,12 @@ int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* 
  *   KBE_OBS_NBAND + b (band occupation in the eigenbasis of h0(k - A(T))).
  * Parameters theta = (pulse amp, pulse omega, U); the initial state does not depend on them.
  *
- * Requirements: cfg->adjoint = 1 at kbe_create (the per-step rho_m and D_m record),
- * precision KBE_FP64, n_corr = 1, nb <= 2, and T >= 1. The reverse sweep reads the forward
- * history (unchanged) and recomputes I(t_{m-1}, .), the predictor row and the corrector's
- * collision row of each step from it; it overwrites the context's working buffers, so the
- * context cannot be stepped forward afterwards (KBE_ERR_STATE).
+ * Requirements: precision KBE_FP64, n_corr = 1, nb <= 2, and T >= 1. The forward run keeps
+ * nothing for the adjoint beyond its own history: every committed time slice is a checkpoint.
+ * Reversing step m reads rho_{m-1} back from the history diagonal (G^< = i rho exactly) and
+ * recomputes I(t_{m-1}, .) with D_{m-1}, the predictor row and the corrector's collision row
+ * from the history (unchanged); it overwrites the context's working buffers, so the context
+ * cannot be stepped forward afterwards (KBE_ERR_STATE).
  *
  * kbe_adjoint_query: bytes of the caller-owned adjoint workspace for cfg (an FP64 adjoint
  *   history of the same packed shape as the FP64 history, plus per-step rows).

@@ -17,6 +17,7 @@
 //   k_adj_props   adjoint of V, Vh, Phi: Frechet derivative of the augmented exponential
 //   k_adj_hf      adjoint of the mean field and of the pulse; parameter gradients
 //   k_adj_seed    adjoint of the final-time observable
+//   k_adj_rho     rho_m = -i G^<(t_m, t_m) read back from the stored history diagonal
 #include "kbe_adjoint.hpp"
 #include "kbe_device.hpp"
 #include "kbe_kernels.hpp"
@@ -986,6 +987,18 @@ __global__ __launch_bounds__(256) void k_adj_seed(Dims d, const cplx* __restrict
   }
 }
 
+// The row kernel stores the equal-time block as G^<(t_m, t_m) = i rho_m; multiplying by -i
+// swaps the parts and flips one sign, so rho_m comes back bit for bit from the history.
+template <int NB>
+__global__ void k_adj_rho(Dims d, const void* __restrict__ hist, int m, cplx* __restrict__ rho) {
+  constexpr int NBB = NB * NB;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.nk * NBB) return;
+  int k = i / NBB, e = i - (i / NBB) * NBB;
+  cplx g = static_cast<const cplx*>(hist)[hist_idx(d, k, e, m, m)];  // FP64 history
+  rho[i] = cmk(g.y, -g.x);
+}
+
 // ------------------------------------------------------------------ launchers
 template <int NB>
 struct AdjLaunch {
@@ -1032,6 +1045,11 @@ struct AdjLaunch {
                        double wb, cplx* rbA, cplx* rbB, double dAdamp, double dAdomega, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_hf<NB>, dim3(1), dim3(256), 0, st, d, (const double*)b.kpart, rA, rB, wb, a.hf, a.U,
                        rbA, rbB, dAdamp, dAdomega, b.theta_bar);
+    return hipGetLastError();
+  }
+  static hipError_t rho(const Dims& d, const void* hist, int m, cplx* out, hipStream_t st) {
+    int n = d.nk * NB * NB;
+    hipLaunchKernelGGL(k_adj_rho<NB>, dim3((n + 255) / 256), dim3(256), 0, st, d, hist, m, out);
     return hipGetLastError();
   }
   static hipError_t seed(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* rho_T, int obs_id,
@@ -1081,6 +1099,10 @@ hipError_t launch_adj_reduce_u(const AdjArgs& b, int n, hipStream_t st) {
 hipError_t launch_adj_seed(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* rho_T, int obs_id,
                            double dAdamp, double dAdomega, hipStream_t st) {
   KBE_ADJ_DISPATCH(d.nb, seed(d, a, b, rho_T, obs_id, dAdamp, dAdomega, st));
+}
+
+hipError_t launch_adj_rho(const Dims& d, const void* hist, int m, cplx* rho, hipStream_t st) {
+  KBE_ADJ_DISPATCH(d.nb, rho(d, hist, m, rho, st));
 }
 
 }  // namespace kbe

@@ -29,7 +29,8 @@ struct AdjArgs {
   cplx* Ire_prev;     // recomputed I(t_{m-1}, .)
   cplx* Ire_c;        // recomputed corrector I(t_m, .)
   cplx* Dc;           // recomputed corrector D
-  cplx* Dscratch;     // D of the recomputed evaluation pass of t_{m-1} (unused values)
+  cplx* Dscratch;     // D_{m-1} from the recomputed evaluation pass of t_{m-1}
+  cplx* rho0;         // rho_{m-1} (rho_T at the seed) read back from the history diagonal
   cplx* hf_p;         // recomputed predictor mean field [nb^2]
   cplx* hf_c;         // recomputed corrector mean field
   double* kpart;      // [k][NB + 1] per-k partials: dL/dhf_aa, dL/dA
@@ -52,6 +53,8 @@ hipError_t launch_adj_hf(const Dims& d, const LaunchArgs& a, const AdjArgs& b, c
                          const cplx* rho_cur, double wb, cplx* rbar_prev, cplx* rbar_cur, double dAdamp,
                          double dAdomega, hipStream_t st);
 hipError_t launch_adj_reduce_u(const AdjArgs& b, int n, hipStream_t st);
+// rho[k][nb^2] = rho_m of the committed FP64 history (its diagonal block G^< = i rho_m)
+hipError_t launch_adj_rho(const Dims& d, const void* hist, int m, cplx* rho, hipStream_t st);
 hipError_t launch_adj_seed(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* rho_T, int obs_id,
                            double dAdamp, double dAdomega, hipStream_t st);
 

@@ -21,7 +21,7 @@ namespace {
 
 enum {
   B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
-  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_RHOALL, B_DALL, B_COUNT
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_COUNT
 };
 
 struct Layout {
@@ -81,10 +81,6 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_EIGU] = nk * d.nbb * cz;
   sz[B_MU] = sizeof(double);
   sz[B_ROW64] = 2 * nk * d.C * d.Tp * cz;
-  // per-step record of rho_m and D_m, kept only when the adjoint will be run
-  size_t rec = c->adjoint ? (size_t)(c->nt_max + 1) * nk * d.nbb * cz : 0;
-  sz[B_RHOALL] = rec;
-  sz[B_DALL] = rec;
   size_t off = 0;
   for (int i = 0; i < B_COUNT; ++i) {
     L->off[i] = off;
@@ -115,7 +111,7 @@ void pulse_dA(const kbe_pulse& p, double t, double* damp, double* domega) {
 // Adjoint workspace: adjoint history + per-step rows of the reverse sweep.
 enum {
   A_LAM = 0, A_IBAR0, A_IBAR1, A_IBARC, A_RBAR, A_SBAR, A_SBARCOL, A_IREPREV, A_IREC, A_SBARRP,
-  A_DBAR0, A_DBAR1, A_DBARC, A_RHOBAR0, A_RHOBAR1, A_RHOBARP, A_RHOP, A_DC, A_DSCR,
+  A_DBAR0, A_DBAR1, A_DBARC, A_RHOBAR0, A_RHOBAR1, A_RHOBARP, A_RHOP, A_DC, A_DSCR, A_RHO0,
   A_PROPSP, A_PROPSC, A_PBAR, A_HFP, A_HFC, A_KPART, A_UBAR, A_THETA, A_COUNT
 };
 
@@ -128,7 +124,7 @@ size_t adj_layout(const Layout& L, size_t* off) {
   for (int i = A_IBAR0; i <= A_IREC; ++i) sz[i] = row;
   sz[A_SBARRP] = nk * (size_t)d.Smax * d.nbb * d.Tp * cz;
   size_t mat = nk * d.nbb * cz;
-  for (int i = A_DBAR0; i <= A_DSCR; ++i) sz[i] = mat;
+  for (int i = A_DBAR0; i <= A_RHO0; ++i) sz[i] = mat;
   sz[A_PROPSP] = sz[A_PROPSC] = sz[A_PBAR] = 3 * mat;
   sz[A_HFP] = sz[A_HFC] = d.nbb * cz;
   sz[A_KPART] = nk * (d.nb + 1) * sizeof(double);
@@ -194,8 +190,6 @@ struct kbe_ctx {
     a.eig_U = buf<cplx>(B_EIGU);
     a.mu = buf<double>(B_MU);
     a.obs = obs;
-    a.rho_save = nullptr;
-    a.D_save = nullptr;
     a.commit = 1;
     a.Ax = a.Ay = 0.0;
     a.polx = pulse.pol[0];
@@ -262,14 +256,10 @@ struct kbe_ctx {
     set_A(a, t);
     return check(kbe::launch_obs(L.d, a, m, t, pulse_A(pulse, t), st), "observables launch");
   }
-  cplx* rec_rho(int m) const { return cfg.adjoint ? buf<cplx>(B_RHOALL) + (size_t)m * L.d.nk * L.d.nbb : nullptr; }
-  cplx* rec_D(int m) const { return cfg.adjoint ? buf<cplx>(B_DALL) + (size_t)m * L.d.nk * L.d.nbb : nullptr; }
   int one_step() {
     int m = step + 1;
     if (m > cfg.nt_max) return fail(KBE_ERR_STATE, "step index would pass nt_max");
     LaunchArgs a = args();
-    a.rho_save = rec_rho(m);
-    a.D_save = rec_D(m);
     int rc = props(a, m, 0);
     if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_PREDICT, st), "predictor launch");
     for (int it = 0; it < cfg.n_corr && !rc; ++it) {
@@ -314,6 +304,7 @@ struct kbe_ctx {
     b.Ire_c = abuf<cplx>(A_IREC);
     b.Dc = abuf<cplx>(A_DC);
     b.Dscratch = abuf<cplx>(A_DSCR);
+    b.rho0 = abuf<cplx>(A_RHO0);
     b.hf_p = abuf<cplx>(A_HFP);
     b.hf_c = abuf<cplx>(A_HFC);
     b.kpart = abuf<double>(A_KPART);
@@ -338,7 +329,9 @@ struct kbe_ctx {
     set_A(a, T);
     pulse_dA(pulse, T, &damp, &dom);
     kbe::AdjArgs b = adj_args();
-    return check(kbe::launch_adj_seed(d, a, b, rec_rho(step), obs_id, damp, dom, st), "adjoint seed launch");
+    rc = check(kbe::launch_adj_rho(d, hist, step, b.rho0, st), "density read-back launch");
+    if (!rc) rc = check(kbe::launch_adj_seed(d, a, b, b.rho0, obs_id, damp, dom, st), "adjoint seed launch");
+    return rc;
   }
   int adj_sigma_pass(const LaunchArgs& a, const kbe::AdjArgs& b, const cplx* Ibar, const cplx* Dbar, int m) {
     const Dims& d = L.d;
@@ -355,15 +348,16 @@ struct kbe_ctx {
   int adj_reverse(int m) {
     const Dims& d = L.d;
     LaunchArgs a = args();
-    a.rho_save = nullptr;
-    a.D_save = nullptr;
     double tm = (m - 0.5) * cfg.dt, damp, dom;
     set_A(a, tm);
     pulse_dA(pulse, tm, &damp, &dom);
     kbe::AdjArgs b = adj_args();
-    cplx* rho0 = rec_rho(m - 1);
+    // The committed history is every time slice's checkpoint: rho_{m-1} is its diagonal block,
+    // and D_{m-1} comes out of the recomputed evaluation pass of t_{m-1} below.
+    cplx* rho0 = b.rho0;
+    int rc = check(kbe::launch_adj_rho(d, hist, m - 1, rho0, st), "density read-back launch");
     // committed rows m-1, m, column 0 and diagonal; Sigma of the committed row m
-    int rc = check(kbe::launch_aux(d, a, m, st), "aux launch");
+    if (!rc) rc = check(kbe::launch_aux(d, a, m, st), "aux launch");
     if (!rc) rc = check(kbe::launch_sigma(d, a, m, st), "self-energy launch");
     // evaluation pass of t_m
     if (!rc) rc = adj_sigma_pass(a, b, b.Ibar, b.Dbar, m);
@@ -380,7 +374,7 @@ struct kbe_ctx {
     p.I_prev = b.Ire_prev;
     p.rho_prev = rho0;
     p.rho_cur = b.rhoP;
-    p.D_prev = rec_D(m - 1);
+    p.D_prev = b.Dscratch;
     p.props = b.props_p;
     p.hfbuf = b.hf_p;
     p.commit = 0;
@@ -490,12 +484,6 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
     rc = c->check(kbe::launch_init(d, a, c->st), "initial-state launch");
   }
   if (!rc) rc = c->observe(0);
-  if (!rc && cfg->adjoint) {
-    // record of t_0: rho_0 and D_0 = 0
-    rc = c->check(hipMemcpyAsync(c->rec_rho(0), c->buf<cplx>(B_RHOA), c->L.bytes[B_RHOA], hipMemcpyDeviceToDevice, c->st),
-                  "rho_0 record");
-    if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->rec_D(0), 2 * (size_t)d.nk * d.nbb, c->st), "zero");
-  }
   if (!rc) rc = c->check(hipStreamSynchronize(c->st), "initial state");
   if (rc) {
     delete c;
@@ -667,7 +655,6 @@ int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
 
 int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes) {
   if (!ctx || !d_adjoint) return KBE_ERR_INVALID_ARG;
-  if (!ctx->cfg.adjoint) return ctx->fail(KBE_ERR_STATE, "the context was created without cfg.adjoint = 1");
   if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->L.d.nb > 2)
     return ctx->fail(KBE_ERR_SHAPE, "the adjoint needs precision KBE_FP64, n_corr = 1 and nb <= 2");
   if (ctx->adj_obs >= 0) return ctx->fail(KBE_ERR_STATE, "a reverse sweep is in progress");

@@ -314,8 +314,7 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
 template <int NB>
 __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ row64,
                                                 const cplx* __restrict__ sig, cplx* __restrict__ Icur,
-                                                cplx* __restrict__ Dcur, int m, double dt,
-                                                cplx* __restrict__ D_save) {
+                                                cplx* __restrict__ Dcur, int m, double dt) {
   constexpr int NBB = NB * NB;
   __shared__ cplx lds[NBB * 256];
   int k = blockIdx.x;
@@ -359,7 +358,6 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
         Icur[rowbuf_idx(d, k, NBB + a * NB + b, m)] = I;
         cplx Dv = cadd(cscal(acc[a * NB + b], dt), cconj(cscal(acc[b * NB + a], dt)));
         Dcur[(int64_t)k * NBB + a * NB + b] = Dv;
-        if (D_save) D_save[(int64_t)k * NBB + a * NB + b] = Dv;
       }
   }
 }
@@ -925,7 +923,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              cplx* __restrict__ Icur, const cplx* __restrict__ props,
                                              const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
                                              const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
-                                             double dt, int commit, cplx* __restrict__ rho_save) {
+                                             double dt, int commit) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   int k = blockIdx.y;
   int tp = blockIdx.x * 256 + threadIdx.x;
@@ -1070,7 +1068,6 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         int e = a * NB + b;
         cplx rv = csub(rho[e], cscal(t2[e], dt));
         rho_cur[(int64_t)k * NBB + e] = rv;
-        if (rho_save) rho_save[(int64_t)k * NBB + e] = rv;
         cplx g[2];
         g[0] = cmuli(rv);
         g[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
@@ -1249,7 +1246,7 @@ struct Launch {
   }
   static hipError_t diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.row64, (const cplx*)a.sig,
-                       a.I_cur, a.D_cur, m, a.dt, a.D_save);
+                       a.I_cur, a.D_cur, m, a.dt);
     return hipGetLastError();
   }
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
@@ -1277,7 +1274,7 @@ struct Launch {
 #define KBE_ROW_ARGS                                                                                      \
   d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
-      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit, a.rho_save
+      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit
     if (mode == KBE_ROW_PREDICT)
       hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
     else if (mode == KBE_ROW_CORRECT)

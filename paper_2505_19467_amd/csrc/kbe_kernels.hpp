@@ -40,8 +40,6 @@ struct LaunchArgs {
   cplx* eig_U;
   double* mu;
   double* obs;
-  cplx* rho_save;  // if set: where the row kernel also stores rho_m (per-step record)
-  cplx* D_save;    // if set: where the equal-time collision kernel also stores D_m
   int commit;      // 0: the row kernel writes only the FP64 working row (recomputation)
   double Ax, Ay;  // A(t) * pol for the launch at hand
   double polx, poly;  // pulse polarisation

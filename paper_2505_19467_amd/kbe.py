@@ -38,8 +38,7 @@ BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_C
 
 class KbeConfig(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision",
-                 "adjoint")] + \
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision")] + \
                [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling")]
 
 
@@ -86,18 +85,17 @@ class KbeError(RuntimeError):
     pass
 
 
-def _c_config(cfg: _inputs.Config, nt_max: int | None = None, adjoint: bool = False) -> KbeConfig:
+def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
     return KbeConfig(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg, interaction=cfg.interaction,
                      hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
                      nt_max=cfg.nt if nt_max is None else nt_max, precision=cfg.precision,
-                     adjoint=1 if adjoint else 0, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
+                     dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
 
 
-def workspace_query(cfg: _inputs.Config, nt_max: int | None = None, adjoint: bool = False):
+def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
     """Byte sizes (history, workspace, observables) for the context that kbe_create would
-    build from the same (cfg, nt_max, adjoint): the per-step record of an adjoint-enabled
-    context lives in the workspace, so the flag changes the workspace size."""
-    return _query(_c_config(cfg, nt_max, adjoint))
+    build from the same (cfg, nt_max)."""
+    return _query(_c_config(cfg, nt_max))
 
 
 def _query(c: KbeConfig):
@@ -135,13 +133,12 @@ class System:
     """One propagation context: caller-owned (torch) device buffers + the library context."""
 
     def __init__(self, cfg: _inputs.Config, nt_max: int | None = None, device: str = "cuda",
-                 stream: torch.cuda.Stream | None = None, adjoint: bool = False):
+                 stream: torch.cuda.Stream | None = None):
         self.cfg = cfg
         self.nt_max = cfg.nt if nt_max is None else nt_max
-        self.adjoint = adjoint
         self.adj_workspace = None
         # one KbeConfig for both the sizing and the creation of the context
-        self._cconf = _c_config(cfg, self.nt_max, adjoint)
+        self._cconf = _c_config(cfg, self.nt_max)
         hb, wb, ob = _query(self._cconf)
         dev = torch.device(device)
         self.fp32 = cfg.precision == _inputs.PRECISION_FP32
@@ -342,7 +339,7 @@ class KBEFunction(torch.autograd.Function):
         amp, omega, U = (float(x) for x in theta.detach().cpu().tolist())
         pulse = dataclasses.replace(cfg.pulse, amp=amp, omega=omega)
         run_cfg = cfg.replace(U=U, pulse=pulse)
-        sys_ = System(run_cfg, nt_max=nsteps, adjoint=True)
+        sys_ = System(run_cfg, nt_max=nsteps)
         sys_.step(nsteps)
         obs_id = OBS[observable] if isinstance(observable, str) else int(observable)
         val = sys_.observables(nsteps, 1)[0, obs_id]

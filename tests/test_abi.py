@@ -92,32 +92,23 @@ def test_history_layout_is_a_bijection():
                 assert pair[1] - pair[0] == 1
 
 
-def test_adjoint_record_enlarges_the_workspace():
-    """An adjoint-enabled context keeps (rho_m, D_m) for every step inside the workspace:
-    the queried size grows by at least 2 (nt+1) N_k nb^2 complex128."""
-    from paper_2505_19467_amd import kbe
-    for cfg in (inputs.c1(), inputs.c4()):
-        _, w0, _ = kbe.workspace_query(cfg)
-        _, w1, _ = kbe.workspace_query(cfg, adjoint=True)
-        assert w1 - w0 >= 2 * (cfg.nt + 1) * cfg.nk * cfg.nb * cfg.nb * 16
-
-
 def test_create_rejects_undersized_buffers():
     """kbe_create checks every buffer size against the layout of its own config before it
-    launches anything (so this runs without a GPU): a workspace sized for the config without
-    the adjoint record is refused for the config with it."""
+    launches anything (so this runs without a GPU): one element short in any buffer, or a
+    workspace sized for a shorter run, is refused."""
     from paper_2505_19467_amd import kbe
     import numpy as np
     cfg = inputs.c1()
-    c_adj = kbe._c_config(cfg, 20, True)
-    hb, wb, ob = kbe._query(c_adj)
-    _, wb_plain, _ = kbe._query(kbe._c_config(cfg, 20, False))
+    c = kbe._c_config(cfg, 20)
+    hb, wb, ob = kbe._query(c)
+    _, wb_short, _ = kbe._query(kbe._c_config(cfg, 10))
+    assert wb_short < wb
     hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
     fake = ctypes.c_void_p(0x100000)  # never dereferenced: the size check comes first
     ctx = ctypes.c_void_p()
     dp = hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    for sizes in ((hb, wb_plain, ob), (hb - 16, wb, ob), (hb, wb, ob - 8)):
-        rc = kbe._lib.kbe_create(ctypes.byref(c_adj), dp, None, fake, sizes[0], fake, sizes[1], fake, sizes[2],
+    for sizes in ((hb, wb_short, ob), (hb - 16, wb, ob), (hb, wb - 256, ob), (hb, wb, ob - 8)):
+        rc = kbe._lib.kbe_create(ctypes.byref(c), dp, None, fake, sizes[0], fake, sizes[1], fake, sizes[2],
                                  None, ctypes.byref(ctx))
         assert rc == -1 and not ctx.value
 
@@ -127,8 +118,8 @@ def test_adjoint_query():
     n = ctypes.c_size_t()
     cfg = inputs.c4()
     hb, _, _ = kbe.workspace_query(cfg)
-    assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(cfg, None, True)), ctypes.byref(n)) == 0
+    assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(cfg, None)), ctypes.byref(n)) == 0
     assert n.value > hb  # the adjoint history alone has the FP64 history's size
     # K = 2, the FP32 form and nb > 2 are outside the reverse sweep
     for bad in (cfg.replace(n_corr=2), cfg.replace(precision=inputs.PRECISION_FP32), inputs.c5()):
-        assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(bad, None, True)), ctypes.byref(n)) == -2
+        assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(bad, None)), ctypes.byref(n)) == -2

@@ -6,6 +6,7 @@ Tolerances: 1e-9 relative to the largest gradient component against the tangent-
 oracle (both sides differentiate the same discrete scheme in FP64), 1e-5 against central
 differences (step h = 1e-4 times the parameter scale; O(h^2) truncation).
 """
+import ctypes
 import dataclasses
 
 import numpy as np
@@ -35,7 +36,7 @@ def O():
 
 
 def _gpu_grad(K, cfg, n, obs):
-    s = K.System(cfg, nt_max=n, adjoint=True)
+    s = K.System(cfg, nt_max=n)
     s.step(n)
     val = s.observables(n, 1)[0, K.OBS[obs]]
     g = s.adjoint_gradient(obs)
@@ -147,16 +148,20 @@ def test_adjoint_reverse_is_repeatable(K):
 
 def test_adjoint_errors(K):
     cfg = I.c1()
-    s = K.System(cfg, nt_max=10)          # no per-step record
-    s.step(3)
-    with pytest.raises(K.KbeError):
-        s.adjoint_gradient("n_band1")
+    s = K.System(cfg, nt_max=10)
+    # at t_0 nothing depends on theta (A(0) = 0, no U): the binding returns zeros, and the
+    # library itself refuses a reverse sweep with no step to reverse
+    assert np.array_equal(s.adjoint_gradient("n_band1"), np.zeros(3))
+    left = ctypes.c_int32()
+    assert K._lib.kbe_adjoint_step(s._ctx, K.OBS["n_band1"], None, ctypes.byref(left)) != 0
     s.close()
-    with pytest.raises(K.KbeError):       # K = 2 is not supported by the reverse sweep
-        s2 = K.System(cfg.replace(n_corr=2), nt_max=10, adjoint=True)
+    for bad in (cfg.replace(n_corr=2), cfg.replace(precision=I.PRECISION_FP32)):
+        s2 = K.System(bad, nt_max=10)     # K = 2 and the FP32 form are outside the reverse sweep
         s2.step(2)
-        s2.adjoint_gradient("n_band1")
-    s3 = K.System(cfg, nt_max=10, adjoint=True)
+        with pytest.raises(K.KbeError):
+            s2.adjoint_gradient("n_band1")
+        s2.close()
+    s3 = K.System(cfg, nt_max=10)
     s3.step(4)
     with pytest.raises(K.KbeError):       # energy is not an admissible loss
         s3.adjoint_gradient("Etot")

@@ -68,7 +68,7 @@ def _set_sigma(S, m, sig):
     dst[:, 2, :, :m + 1].copy_(t[:, 1] - t[:, 0])
 
 
-# ---------------------------------------------------------------- a-2: self-energy row
+# ---------------------------------------------------------------- self-energy row
 @pytest.mark.parametrize("nkx,nky,nb,m", [(16, 1, 2, 5), (6, 4, 2, 70), (5, 3, 1, 9), (3, 5, 3, 9),
                                           (4, 4, 4, 9), (24, 24, 2, 3), (7, 1, 2, 0)])
 def test_sigma_row_parity(K, nkx, nky, nb, m):
@@ -88,7 +88,7 @@ def test_sigma_row_parity(K, nkx, nky, nb, m):
     assert np.abs(sr - (pl[:, 1] - pl[:, 0])).max() <= 1e-15 * max(1.0, np.abs(pl).max())
 
 
-# ---------------------------------------------------------------- a-3 + a-4: collision row
+# ---------------------------------------------------------------- collision row
 @pytest.mark.parametrize("nkx,nky,nb,m", [(3, 2, 2, 130), (4, 1, 1, 64), (2, 2, 3, 65), (2, 1, 4, 70),
                                           (2, 2, 2, 1), (2, 2, 2, 2), (1, 3, 2, 63), (2, 1, 2, 200)])
 def test_collision_row_parity(K, nkx, nky, nb, m):
@@ -112,7 +112,7 @@ def test_collision_row_parity(K, nkx, nky, nb, m):
     assert relerr(D, Il + np.conj(np.swapaxes(Il, -1, -2))) < KERNEL_TOL
 
 
-# ---------------------------------------------------------------- a-1: propagators
+# ---------------------------------------------------------------- propagators
 @pytest.mark.parametrize("nkx,nky,nb", [(4, 3, 2), (8, 1, 1), (3, 3, 3), (2, 2, 4)])
 def test_propagators_parity(K, nkx, nky, nb):
     _say(f"propagators parity nk={nkx}x{nky} nb={nb}")

@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # HBM traffic of the FP64 history-sum kernel per launch, averaged over the 2000 launches of
 # this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by what the same counters
 # read for a plain 1 GiB device copy (x2.000 and x1.000); summary and commands in
-# profiles/k_hist_bulk_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
+# profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
 # (SHA-1 of kbe_kernels.hip + kbe_device.hpp); reported as null once that source changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2727e10, "fetch_over_algorithmic": 1.021,
-                    "write_over_algorithmic": 0.0116,
-                    "source_sha1": "84f646eed9f5a469e749a502b55de5263de5020b"}
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0215,
+                    "write_over_algorithmic": 0.0077,
+                    "source_sha1": "48b17e976a36f1bdc275da61fd78fe3b353273b0"}
 
 
 def _kernel_source_sha1():
@@ -270,7 +270,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM fetch + write)",
-                     "kernel": "k_hist_bulk", "launches": launches, "kernel_ms": kms},
+                     "kernel": "k_hist_pair" if cfg.nb <= 2 else ("k_hist_bulk_split" if cfg.nb == 4 else "k_hist_bulk"),
+                     "launches": launches, "kernel_ms": kms},
         "cpu_baseline": cpu,
         "fp32_form": fp32,
         "adjoint": adj,

@@ -64,6 +64,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.Smax = (c->nt_max + 63) / 64;
   d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
   d.rps = c->nb == 4 ? 2 : 1;
+  d.spb = c->nb <= 2 ? 2 : 1;
   d.N = c->nt_max + 1;
   d.P = kbe::strip_base((d.N + 63) / 64, d.N);
   const size_t cz = sizeof(cplx);

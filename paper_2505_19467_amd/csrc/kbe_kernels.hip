@@ -377,165 +377,19 @@ __device__ __forceinline__ void load_stream32x2(const float2* p, float2& a, floa
   b = make_float2(v.z, v.w);
 }
 
-// Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
-// each with weight 1 (end-point weights are corrected in k_row):
-//   column term -> output t':  SR_j G^{<,>}_{j t'}                    (SR = Sigma^> - Sigma^<)
-//   row term    -> output j:   -Sigma^>_{t'} (G^<_{j t'})^dag + Sigma^<_{t'} (G^>_{j t'})^dag,
-//                               t' < j, shared by I^< and I^>    (G_{t' j} = -G_{j t'}^dag)
-// Block = (64-column strip s, k); strips with the most rows are launched first. Lane l owns
-// column t' = 64 s + l and keeps its column sums in registers; each wavefront takes R
-// consecutive rows per iteration (R x 2nb^2 loads of 1 KB-contiguous data in flight, one per
-// row and component; R = 4, 2, 1 for nb = 1, 2, >= 3 to stay within the register
-// file), so every stored block is read from HBM exactly once. The R rows' row terms are
-// reduced over the 64 lanes with a reduce-scatter (half-wave and 16-lane-row permlane swaps,
-// then DPP within rows) and stored per strip (rowpart); the 4 wavefronts' column sums are
-// combined in LDS. Deterministic: no atomics.
-template <int NB>
-__global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restrict__ hist,
-                                                   const cplx* __restrict__ sig, cplx* __restrict__ colsum,
-                                                   cplx* __restrict__ rowpart, int m) {
-  constexpr int NBB = NB * NB, C = 2 * NBB;
-  constexpr int CH = (C < 8) ? C : 8;  // components per LDS combine round
-  constexpr int R = NB == 1 ? 4 : (NB == 2 ? 2 : 1);  // rows per wavefront iteration
-  // nb >= 3: the per-column Sigma of the row term lives in LDS instead of registers
-  constexpr bool SLDS = NB >= 3;
-  constexpr int NS = SLDS ? NBB : 1;
-  __shared__ cplx red[3][CH][64];
-  __shared__ cplx sS[2][NS][64];
-  int s = blockIdx.x / d.nk;  // strips with the most rows first
-  int k = blockIdx.x - s * d.nk;
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int tp = 64 * s + lane;
-  bool colv = tp < m;
-  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
-  cplx Sl[SLDS ? 1 : NBB], Sg[SLDS ? 1 : NBB];
-  if constexpr (SLDS) {
-    for (int i = threadIdx.x; i < 2 * NBB * 64; i += 256) {
-      int x = i / (NBB * 64), e = (i / 64) % NBB, l = i % 64;
-      int t = 64 * s + l;
-      sS[x][e][l] = t < m ? sk[(x * NBB + e) * d.Tp + t] : czero();
-    }
-    __syncthreads();
-  } else {
-#pragma unroll
-    for (int e = 0; e < NBB; ++e) {
-      Sl[e] = colv ? sk[(0 * NBB + e) * d.Tp + tp] : czero();
-      Sg[e] = colv ? sk[(1 * NBB + e) * d.Tp + tp] : czero();
-    }
-  }
-  cplx acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = czero();
-  // strip s of k: rows j >= 64 s, each a run of C component segments of 64 elements
-  const cplx* hk = hist + strip_lane_base(d, k, s, lane);
-  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
-  for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
-    cplx G[R][C];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int j = jb + r;
-      bool v = colv && tp <= j && j < m;
-      const cplx* row = hk + 64 * (int64_t)C * j;
-#pragma unroll
-      for (int c = 0; c < C; ++c) G[r][c] = v ? load_stream(row + 64 * c) : czero();
-    }
-    double rt[R][2 * NBB];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int j = jb + r;
-      int jc = j < m ? j : m - 1;
-      cplx SR[NBB];
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
-      mm_acc<NB>(acc, SR, G[r]);
-      mm_acc<NB>(acc + NBB, SR, G[r] + NBB);
-      bool rv = tp < j;
-      if constexpr (SLDS) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) {
-            cplx a = czero(), u = czero();
-#pragma unroll
-            for (int l = 0; l < NB; ++l) {
-              cmacc(a, sS[0][i * NB + l][lane], G[r][NBB + jj * NB + l]);
-              cmacc(u, sS[1][i * NB + l][lane], G[r][jj * NB + l]);
-            }
-            int e = i * NB + jj;
-            rt[r][2 * e] = rv ? a.x - u.x : 0.0;
-            rt[r][2 * e + 1] = rv ? a.y - u.y : 0.0;
-          }
-      } else {
-        cplx a[NBB], u[NBB];
-        mat_zero<NB>(a);
-        mat_zero<NB>(u);
-        mm_acc_bdag<NB>(a, Sl, G[r] + NBB);
-        mm_acc_bdag<NB>(u, Sg, G[r]);
-#pragma unroll
-        for (int e = 0; e < NBB; ++e) {
-          rt[r][2 * e] = rv ? a[e].x - u[e].x : 0.0;
-          rt[r][2 * e + 1] = rv ? a[e].y - u[e].y : 0.0;
-        }
-      }
-    }
-    // reduce-scatter over the 64 lanes; afterwards lane groups hold whole-row sums:
-    //   R = 4: lanes 0-15 row 0, 32-47 row 1, 16-31 row 2, 48-63 row 3
-    //   R = 2: lanes 0-31 row 0, 32-63 row 1;   R = 1: every lane row 0
-#pragma unroll
-    for (int q = 0; q < 2 * NBB; ++q) {
-      double y;
-      if constexpr (R == 4) {
-        y = rs_row(rs_half(rt[0][q], rt[1][q]), rs_half(rt[2][q], rt[3][q]));
-      } else if constexpr (R == 2) {
-        double x = rs_half(rt[0][q], rt[1][q]);
-        y = rs_row(x, x);
-      } else {
-        double x = rs_half(rt[0][q], rt[0][q]);
-        y = rs_row(x, x);
-      }
-      rt[0][q] = row16_sum(y);
-    }
-    int rsel = -1;
-    if constexpr (R == 4) {
-      if ((lane & 15) == 0) rsel = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
-    } else if constexpr (R == 2) {
-      if ((lane & 31) == 0) rsel = lane >> 5;
-    } else {
-      if (lane == 0) rsel = 0;
-    }
-    if (rsel >= 0 && jb + rsel < m) {
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + jb + rsel] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
-    }
-  }
-  // combine the 4 wavefronts' column sums
-#pragma unroll
-  for (int c0 = 0; c0 < C; c0 += CH) {
-    if (wv > 0) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) red[wv - 1][c][lane] = acc[c0 + c];
-    }
-    __syncthreads();
-    if (wv == 0) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        cplx a = acc[c0 + c];
-        a = cadd(a, red[0][c][lane]);
-        a = cadd(a, red[1][c][lane]);
-        a = cadd(a, red[2][c][lane]);
-        if (colv) colsum[rowbuf_idx(d, k, c0 + c, tp)] = a;
-      }
-    }
-    __syncthreads();
-  }
+// Streaming store of one complex value (row partials are not read again in this pass).
+__device__ __forceinline__ void store_stream(cplx* p, cplx v) {
+  kbe_d2v w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<kbe_d2v*>(p));
+}
+// Keep the compiler from moving LDS accesses of one wavefront across this point (the lanes of
+// a wavefront exchange values through LDS; the hardware executes them in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------------ history sums, FP32 form
-// Same structure as k_hist_bulk over an FP32-stored history (complex64, half the bytes):
-// products and the 64-lane row reductions in FP32; the column sums accumulate in FP32 over
-// tiles of 16 rows per wavefront and are then added into FP64 registers; row partials and
-// column sums leave the kernel in FP64 (the cross-strip reduction, the end points, the
-// update and the density matrix stay FP64).
 typedef float2 cplx32;
 __device__ __forceinline__ void cmac32(cplx32& acc, cplx32 a, cplx32 b) {
   acc.x = fmaf(a.x, b.x, acc.x);
@@ -572,18 +426,452 @@ __device__ __forceinline__ float row16_sum32(float x) {
   return x;
 }
 
+// Reduce-scatter of the row terms of R rows (R = 1, 2, 4) over the 64 lanes: half-wave and
+// 16-lane-row permlane swaps, then DPP within rows. Afterwards rt[0][q] holds whole-row sums
+// in the lanes for which reduced_row<R>(lane) >= 0 names the row:
+//   R = 4: lanes 0-15 row 0, 32-47 row 1, 16-31 row 2, 48-63 row 3
+//   R = 2: lanes 0-31 row 0, 32-63 row 1;   R = 1: every lane row 0
+template <int R, int Q>
+__device__ __forceinline__ void reduce_rows(double (&rt)[R][Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double y;
+    if constexpr (R == 4) {
+      y = rs_row(rs_half(rt[0][q], rt[1][q]), rs_half(rt[2][q], rt[3][q]));
+    } else if constexpr (R == 2) {
+      double x = rs_half(rt[0][q], rt[1][q]);
+      y = rs_row(x, x);
+    } else {
+      double x = rs_half(rt[0][q], rt[0][q]);
+      y = rs_row(x, x);
+    }
+    rt[0][q] = row16_sum(y);
+  }
+}
+template <int R, int Q>
+__device__ __forceinline__ void reduce_rows32(float (&rt)[R][Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float y;
+    if constexpr (R == 4) {
+      y = rs_row32(rs_half32(rt[0][q], rt[1][q]), rs_half32(rt[2][q], rt[3][q]));
+    } else if constexpr (R == 2) {
+      float x = rs_half32(rt[0][q], rt[1][q]);
+      y = rs_row32(x, x);
+    } else {
+      float x = rs_half32(rt[0][q], rt[0][q]);
+      y = rs_row32(x, x);
+    }
+    rt[0][q] = row16_sum32(y);
+  }
+}
+// the one lane per row that stores it (-1: none)
+template <int R>
+__device__ __forceinline__ int reduced_row(int lane) {
+  if constexpr (R == 4) {
+    return (lane & 15) == 0 ? (((lane >> 5) & 1) | (((lane >> 4) & 1) << 1)) : -1;
+  } else if constexpr (R == 2) {
+    return (lane & 31) == 0 ? (lane >> 5) : -1;
+  } else {
+    return lane == 0 ? 0 : -1;
+  }
+}
+// A wavefront's 16 staged rows (st[e * 16 + r], nb^2 components) to rows rb .. rb + 15 of a
+// row-partial slot: 16 consecutive rows per component, 256 contiguous bytes, streaming stores.
+template <int NBB>
+__device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int rb, int m, int lane) {
+  wave_sync();
+#pragma unroll
+  for (int q = lane; q < NBB * 16; q += 64) {
+    int row = rb + (q & 15);
+    if (row < m) store_stream(rp + (int64_t)(q >> 4) * Tp + row, st[q]);
+  }
+  wave_sync();
+}
+
+// Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
+// each with weight 1 (end-point weights are corrected in k_row):
+//   column term -> output t':  SR_j G^{<,>}_{j t'}                    (SR = Sigma^> - Sigma^<)
+//   row term    -> output j:   -Sigma^>_{t'} (G^<_{j t'})^dag + Sigma^<_{t'} (G^>_{j t'})^dag,
+//                               t' < j, shared by I^< and I^>    (G_{t' j} = -G_{j t'}^dag)
+// nb <= 2, FP64. Block = (pair of 64-column strips 2 sp, 2 sp + 1; k), the pairs with the
+// most rows launched first. Lane l owns columns 128 sp + l and 128 sp + 64 + l and keeps both
+// column sums in registers; the Sigma of its two columns (row term) sits in LDS. Each
+// wavefront takes 16 consecutive rows of every 64-row chunk, R rows per iteration (R = 1 at
+// nb = 2: 2 x 8 loads of 1 KB-contiguous data in flight; R = 4 at nb = 1), so every stored
+// block is read from HBM once. The row terms of the two strips are added before the 64-lane
+// reduce-scatter, so one row partial covers 128 columns: the writes that interleave with the
+// read stream are half of what one strip per block would produce, and they leave as whole
+// 256-byte runs (a wavefront's 16 rows staged in LDS, streaming stores). Both measures keep
+// the read stream from stalling on scattered write-backs. Row partials go to slot sp; the 4
+// wavefronts' column sums are combined in LDS. Deterministic: no atomics.
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restrict__ hist,
+                                                   const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+                                                   cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  constexpr int R = NB == 1 ? 4 : 1;
+  __shared__ cplx red[3][C][64];
+  __shared__ cplx stg[4][NBB * 16];
+  __shared__ cplx sS[2][2][NBB][64];  // [strip of the pair][Sigma^<, Sigma^>][e][lane]
+  const int sp = blockIdx.x / d.nk;
+  const int k = blockIdx.x - sp * d.nk;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // rows and Sigma^R wavefront-uniform
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  for (int q = threadIdx.x; q < 4 * NBB * 64; q += 256) {
+    int l = q & 63, e = (q >> 6) % NBB, x = (q >> 6) / NBB;
+    int t = 64 * (2 * sp + (x >> 1)) + l;
+    sS[x >> 1][x & 1][e][l] = t < m ? sk[((x & 1) * NBB + e) * d.Tp + t] : czero();
+  }
+  __syncthreads();
+  // the pair's second strip exists only if its first column is below m
+  const bool two = 64 * (2 * sp + 1) < m;
+  int tp[2];
+  bool colv[2];
+  const cplx* hk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    tp[h] = 64 * (2 * sp + h) + lane;
+    colv[h] = tp[h] < m;
+    hk[h] = hist + strip_lane_base(d, k, (h && two) ? 2 * sp + 1 : 2 * sp, lane);
+  }
+  cplx acc[2][C];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[h][c] = czero();
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
+  cplx* st = stg[wv];
+  for (int cb = 128 * sp; cb < m; cb += 64) {
+    const int rb = cb + 16 * wv;
+    for (int i = 0; i < 16 / R; ++i) {
+      const int jb = rb + R * i;
+      if (jb >= m) break;
+      cplx G[R][2][C];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int j = jb + r;
+          bool v = colv[h] && tp[h] <= j && j < m;
+          const cplx* row = hk[h] + 64 * (int64_t)C * j;
+#pragma unroll
+          for (int c = 0; c < C; ++c) G[r][h][c] = v ? load_stream(row + 64 * c) : czero();
+        }
+      double rt[R][2 * NBB];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int j = jb + r;
+        int jc = j < m ? j : m - 1;
+        cplx SR[NBB];
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
+#pragma unroll
+        for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          mm_acc<NB>(acc[h], SR, G[r][h]);
+          mm_acc<NB>(acc[h] + NBB, SR, G[r][h] + NBB);
+          cplx Sl[NBB], Sg[NBB], a[NBB], u[NBB];
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) {
+            Sl[e] = sS[h][0][e][lane];
+            Sg[e] = sS[h][1][e][lane];
+          }
+          mat_zero<NB>(a);
+          mat_zero<NB>(u);
+          mm_acc_bdag<NB>(a, Sl, G[r][h] + NBB);
+          mm_acc_bdag<NB>(u, Sg, G[r][h]);
+          bool rv = tp[h] < j;
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) {
+            rt[r][2 * e] += rv ? a[e].x - u[e].x : 0.0;
+            rt[r][2 * e + 1] += rv ? a[e].y - u[e].y : 0.0;
+          }
+        }
+      }
+      reduce_rows<R>(rt);
+      int rr = reduced_row<R>(lane);
+      if (rr >= 0) {
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+      }
+    }
+    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+  }
+  // combine the 4 wavefronts' column sums, strip by strip
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (wv > 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[wv - 1][c][lane] = acc[h][c];
+    }
+    __syncthreads();
+    if (wv == 0 && colv[h]) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        cplx a = acc[h][c];
+        a = cadd(a, red[0][c][lane]);
+        a = cadd(a, red[1][c][lane]);
+        a = cadd(a, red[2][c][lane]);
+        colsum[rowbuf_idx(d, k, c, tp[h])] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ history sums, FP32 form
+// Same structure as k_hist_pair over an FP32-stored history (complex64, half the bytes, a
+// column's component pairs in one 16-byte load): R = 2 rows per iteration at nb = 2 (2 rows x
+// 2 strips x 4 loads in flight per wavefront), R = 4 at nb = 1. Products and the 64-lane row
+// reductions in FP32; the column sums accumulate in FP32 over each wavefront's 16-row groups
+// and are then added into FP64 registers; row partials and column sums leave the kernel in
+// FP64 (the cross-strip reduction, the end points, the update and the density matrix stay
+// FP64).
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __restrict__ hist,
+                                                     const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+                                                     cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  constexpr int R = NB == 1 ? 4 : 2;
+  __shared__ cplx red[3][C][64];
+  __shared__ cplx stg[4][NBB * 16];
+  __shared__ cplx32 sS[2][2][NBB][64];
+  const int sp = blockIdx.x / d.nk;
+  const int k = blockIdx.x - sp * d.nk;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  for (int q = threadIdx.x; q < 4 * NBB * 64; q += 256) {
+    int l = q & 63, e = (q >> 6) % NBB, x = (q >> 6) / NBB;
+    int t = 64 * (2 * sp + (x >> 1)) + l;
+    sS[x >> 1][x & 1][e][l] = to32(t < m ? sk[((x & 1) * NBB + e) * d.Tp + t] : czero());
+  }
+  __syncthreads();
+  const bool two = 64 * (2 * sp + 1) < m;
+  int tp[2];
+  bool colv[2];
+  const cplx32* hk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    tp[h] = 64 * (2 * sp + h) + lane;
+    colv[h] = tp[h] < m;
+    hk[h] = hist + strip_lane_base(d, k, (h && two) ? 2 * sp + 1 : 2 * sp, lane);
+  }
+  cplx acc[2][C];
+  cplx32 acc32[2][C];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      acc[h][c] = czero();
+      acc32[h][c] = make_float2(0.f, 0.f);
+    }
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
+  cplx* st = stg[wv];
+  for (int cb = 128 * sp; cb < m; cb += 64) {
+    const int rb = cb + 16 * wv;
+    for (int i = 0; i < 16 / R; ++i) {
+      const int jb = rb + R * i;
+      if (jb >= m) break;
+      cplx32 G[R][2][C];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int j = jb + r;
+          bool v = colv[h] && tp[h] <= j && j < m;
+          const cplx32* row = hk[h] + 64 * (int64_t)C * j;
+#pragma unroll
+          for (int c2 = 0; c2 < C / 2; ++c2) {
+            if (v) {
+              load_stream32x2(row + 128 * c2, G[r][h][2 * c2], G[r][h][2 * c2 + 1]);
+            } else {
+              G[r][h][2 * c2] = make_float2(0.f, 0.f);
+              G[r][h][2 * c2 + 1] = make_float2(0.f, 0.f);
+            }
+          }
+        }
+      float rt[R][2 * NBB];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int j = jb + r;
+        int jc = j < m ? j : m - 1;
+        cplx32 SR[NBB];
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) SR[e] = to32(sk[(2 * NBB + e) * d.Tp + jc]);
+#pragma unroll
+        for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int l = 0; l < NB; ++l)
+                  cmac32(acc32[h][sc * NBB + a * NB + b], SR[a * NB + l], G[r][h][sc * NBB + l * NB + b]);
+          bool rv = tp[h] < j;
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              cplx32 x = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
+#pragma unroll
+              for (int l = 0; l < NB; ++l) {
+                cmacc32(x, sS[h][0][a * NB + l][lane], G[r][h][NBB + b * NB + l]);
+                cmacc32(u, sS[h][1][a * NB + l][lane], G[r][h][b * NB + l]);
+              }
+              int e = a * NB + b;
+              rt[r][2 * e] += rv ? x.x - u.x : 0.f;
+              rt[r][2 * e + 1] += rv ? x.y - u.y : 0.f;
+            }
+        }
+      }
+      reduce_rows32<R>(rt);
+      int rr = reduced_row<R>(lane);
+      if (rr >= 0) {
+#pragma unroll
+        for (int e = 0; e < NBB; ++e)
+          st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+      }
+    }
+    // the group's FP32 column sums into the FP64 accumulators
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[h][c].x += (double)acc32[h][c].x;
+        acc[h][c].y += (double)acc32[h][c].y;
+        acc32[h][c] = make_float2(0.f, 0.f);
+      }
+    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (wv > 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[wv - 1][c][lane] = acc[h][c];
+    }
+    __syncthreads();
+    if (wv == 0 && colv[h]) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        cplx a = acc[h][c];
+        a = cadd(a, red[0][c][lane]);
+        a = cadd(a, red[1][c][lane]);
+        a = cadd(a, red[2][c][lane]);
+        colsum[rowbuf_idx(d, k, c, tp[h])] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ history sums, nb = 3
+// One 64-column strip per block (row partials in slot s), every wavefront over every fourth
+// row; the 18 components of a block leave no registers for a second strip. FP64: one row per
+// iteration, the per-column Sigma of the row term in LDS. Row partials stored by lane 0.
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_bulk(Dims d, const cplx* __restrict__ hist,
+                                                   const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+                                                   cplx* __restrict__ rowpart, int m) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  constexpr int CH = (C < 8) ? C : 8;  // components per LDS combine round
+  __shared__ cplx red[3][CH][64];
+  __shared__ cplx sS[2][NBB][64];
+  int s = blockIdx.x / d.nk;  // strips with the most rows first
+  int k = blockIdx.x - s * d.nk;
+  int lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int tp = 64 * s + lane;
+  bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  for (int i = threadIdx.x; i < 2 * NBB * 64; i += 256) {
+    int x = i / (NBB * 64), e = (i / 64) % NBB, l = i % 64;
+    int t = 64 * s + l;
+    sS[x][e][l] = t < m ? sk[(x * NBB + e) * d.Tp + t] : czero();
+  }
+  __syncthreads();
+  cplx acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = czero();
+  const cplx* hk = hist + strip_lane_base(d, k, s, lane);
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
+  for (int j = 64 * s + wv; j < m; j += 4) {
+    bool v = colv && tp <= j;
+    const cplx* row = hk + 64 * (int64_t)C * j;
+    cplx G[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) G[c] = v ? load_stream(row + 64 * c) : czero();
+    cplx SR[NBB];
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + j];
+    mm_acc<NB>(acc, SR, G);
+    mm_acc<NB>(acc + NBB, SR, G + NBB);
+    bool rv = tp < j;
+    double rt[1][2 * NBB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        cplx x = czero(), u = czero();
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+          cmacc(x, sS[0][a * NB + l][lane], G[NBB + b * NB + l]);
+          cmacc(u, sS[1][a * NB + l][lane], G[b * NB + l]);
+        }
+        int e = a * NB + b;
+        rt[0][2 * e] = rv ? x.x - u.x : 0.0;
+        rt[0][2 * e + 1] = rv ? x.y - u.y : 0.0;
+      }
+    reduce_rows<1>(rt);
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + j] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+    }
+  }
+  // combine the 4 wavefronts' column sums
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    if (wv > 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) red[wv - 1][c][lane] = acc[c0 + c];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        cplx a = acc[c0 + c];
+        a = cadd(a, red[0][c][lane]);
+        a = cadd(a, red[1][c][lane]);
+        a = cadd(a, red[2][c][lane]);
+        if (colv) colsum[rowbuf_idx(d, k, c0 + c, tp)] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// FP32 form at nb = 3: two rows per iteration, Sigma of the row term in registers; FP32 tiles
+// of 16 rows per wavefront added into FP64 accumulators.
 template <int NB>
 __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __restrict__ hist,
                                                      const cplx* __restrict__ sig, cplx* __restrict__ colsum,
                                                      cplx* __restrict__ rowpart, int m) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int CH = (C < 8) ? C : 8;
-  constexpr int R = NB <= 2 ? 4 : 2;  // rows per wavefront iteration
-  constexpr int FLUSH = 16 / R;       // iterations per FP32 accumulation tile (16 rows)
+  constexpr int R = 2;
+  constexpr int FLUSH = 16 / R;  // iterations per FP32 accumulation tile (16 rows)
   __shared__ cplx red[3][CH][64];
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int tp = 64 * s + lane;
   bool colv = tp < m;
   const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
@@ -661,23 +949,8 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
         acc32[c] = make_float2(0.f, 0.f);
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2 * NBB; ++q) {
-      float y;
-      if constexpr (R == 4) {
-        y = rs_row32(rs_half32(rt[0][q], rt[1][q]), rs_half32(rt[2][q], rt[3][q]));
-      } else {
-        float x = rs_half32(rt[0][q], rt[1][q]);
-        y = rs_row32(x, x);
-      }
-      rt[0][q] = row16_sum32(y);
-    }
-    int rsel = -1;
-    if constexpr (R == 4) {
-      if ((lane & 15) == 0) rsel = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
-    } else {
-      if ((lane & 31) == 0) rsel = lane >> 5;
-    }
+    reduce_rows32<R>(rt);
+    int rsel = reduced_row<R>(lane);
     if (rsel >= 0 && jb + rsel < m) {
 #pragma unroll
       for (int e = 0; e < NBB; ++e)
@@ -937,7 +1210,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
       for (int c = 0; c < C; ++c) In[c] = colsum[rowbuf_idx(d, k, c, tp)];
       cplx rs[NBB];
       mat_zero<NB>(rs);
-      int nslot = ((tp >> 6) + 1) * d.rps;
+      int nslot = ((tp >> 6) / d.spb + 1) * d.rps;
       for (int q = 0; q < nslot; ++q) {
         const cplx* rp = rowpart_slot(d, rowpart, k, q);
 #pragma unroll
@@ -1252,7 +1525,15 @@ struct Launch {
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     if (m < 1) return hipSuccess;
     int ns = (m + 63) / 64;
-    if constexpr (NB == 4) {
+    if constexpr (NB <= 2) {
+      int np = (ns + 1) / 2;  // pairs of strips
+      if (d.fp32)
+        hipLaunchKernelGGL(k_hist_pair32<NB>, dim3(np * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+      else
+        hipLaunchKernelGGL(k_hist_pair<NB>, dim3(np * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                           (const cplx*)a.sig, a.colsum, a.rowpart, m);
+    } else if constexpr (NB == 4) {
       if (d.fp32)
         hipLaunchKernelGGL(k_hist_bulk32_split<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx32*)a.hist,
                            (const cplx*)a.sig, a.colsum, a.rowpart, m);

@@ -263,7 +263,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: 2D 24x24 k-grid, nb=2, nt={cfg.nt}, dt={cfg.dt}, "
+        "config": {"workload": f"{cfg.name}: 2D {cfg.nkx}x{cfg.nky} k-grid, nb={cfg.nb}, nt={cfg.nt}, dt={cfg.dt}, "
                                f"second Born + HF, K={cfg.n_corr} corrector pass, FP64",
                    "nk": cfg.nk, "nb": cfg.nb, "nt": cfg.nt, "steps_timed_from_t0": K,
                    "history_passes_per_step": cfg.n_corr + 1, "history_GB": round(hist_gb, 2)},

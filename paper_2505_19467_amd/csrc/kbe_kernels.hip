@@ -986,18 +986,24 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
 // ------------------------------------------------------------------ history sums, nb = 4
 // With nb = 4 a stored block has 2 nb^2 = 32 components, too many for one wavefront's
 // registers next to its column sums. The block's components are split by half: waves 0 and 2
-// stream G^< (components 0..15), waves 1 and 3 stream G^> (16..31), each over every second row
-// of the strip (R = 1 row per iteration: 16 contiguous 1 KB segments in flight per wavefront).
-// Half 0 contributes -Sigma^>_{t'} (G^<_{j t'})^dag to the row term, half 1 +Sigma^<_{t'}
-// (G^>_{j t'})^dag; each half's row partials go to their own slot (strip * 2 + half), summed by
-// k_row. The per-column Sigma of the row term is read from LDS. FP64 storage.
+// stream G^< (components 0..15), waves 1 and 3 stream G^> (16..31); the row pair (0, 1) takes
+// rows 0-15 of every 32-row chunk of the strip, the pair (2, 3) rows 16-31 (16 contiguous 1 KB
+// segments in flight per wavefront). Half 0 contributes -Sigma^>_{t'} (G^<_{j t'})^dag to the
+// row term, half 1 +Sigma^<_{t'} (G^>_{j t'})^dag, each to its own row-partial slot
+// (strip * 2 + half), summed by k_row. The four block rows of a row term go through one
+// 64-lane reduce-scatter together (4 quantities for the instructions of one), and a
+// wavefront's 16 row partials are staged in LDS and stored as 256-byte runs with streaming
+// stores. The per-column Sigma of the row term is read from LDS. FP64 storage; 2 waves per
+// SIMD.
 template <int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hist_bulk_split(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_bulk_split(
     Dims d, const cplx* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
     cplx* __restrict__ rowpart, int m) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
+  static_assert(NB == 4, "the four block rows share one reduce-scatter");
   __shared__ cplx sS[2][NBB][64];  // [half][e][lane]: half 0 needs Sigma^>, half 1 Sigma^<;
                                    // reused for the column-sum combine after the row loop
+  __shared__ cplx stg[2][2][NBB * 16];  // [row pair][half][e * 16 + row]
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63;
@@ -1017,45 +1023,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   for (int e = 0; e < NBB; ++e) acc[e] = czero();
   const cplx* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
+  cplx* st = stg[rg][h];
   const double sgn = h ? 1.0 : -1.0;
-  for (int j = 64 * s + rg; j < m; j += 2) {
-    bool v = colv && tp <= j;
-    const cplx* row = hk + 64 * (int64_t)C * j;
-    cplx G[NBB];
+  for (int cb = 64 * s; cb < m; cb += 32) {
+    const int rb = cb + 16 * rg;
+    for (int i = 0; i < 16; ++i) {
+      const int j = rb + i;
+      if (j >= m) break;
+      bool v = colv && tp <= j;
+      const cplx* row = hk + 64 * (int64_t)C * j;
+      cplx G[NBB];
 #pragma unroll
-    for (int e = 0; e < NBB; ++e) G[e] = v ? load_stream(row + 64 * e) : czero();
-    bool rv = tp < j;
+      for (int e = 0; e < NBB; ++e) G[e] = v ? load_stream(row + 64 * e) : czero();
+      bool rv = tp < j;
+      double x[NB][2 * NB];  // row term of block row a, column b: x[a][2 b], x[a][2 b + 1]
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      cplx SRi[NB];
+      for (int a = 0; a < NB; ++a) {
+        cplx SRa[NB];
 #pragma unroll
-      for (int l = 0; l < NB; ++l) SRi[l] = sk[(2 * NBB + i * NB + l) * d.Tp + j];
-      // column term, row i:  acc[i][jj] += sum_l SR[i][l] G[l][jj]
+        for (int l = 0; l < NB; ++l) SRa[l] = sk[(2 * NBB + a * NB + l) * d.Tp + j];
+        // column term, block row a:  acc[a][b] += sum_l SR[a][l] G[l][b]
 #pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int l = 0; l < NB; ++l) cmac(acc[i * NB + jj], SRi[l], G[l * NB + jj]);
-      // row term, row i:  sgn * sum_l S[i][l] conj(G[jj][l]), reduced over the 64 lanes
-      double x[2 * NB];
+          for (int l = 0; l < NB; ++l) cmac(acc[a * NB + b], SRa[l], G[l * NB + b]);
+        // row term, block row a:  sgn * sum_l S[a][l] conj(G[b][l])
 #pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        cplx a = czero();
+        for (int b = 0; b < NB; ++b) {
+          cplx t = czero();
 #pragma unroll
-        for (int l = 0; l < NB; ++l) cmacc(a, sS[h][i * NB + l][lane], G[jj * NB + l]);
-        x[2 * jj] = rv ? sgn * a.x : 0.0;
-        x[2 * jj + 1] = rv ? sgn * a.y : 0.0;
+          for (int l = 0; l < NB; ++l) cmacc(t, sS[h][a * NB + l][lane], G[b * NB + l]);
+          x[a][2 * b] = rv ? sgn * t.x : 0.0;
+          x[a][2 * b + 1] = rv ? sgn * t.y : 0.0;
+        }
       }
+      reduce_rows<NB>(x);
+      int ra = reduced_row<NB>(lane);
+      if (ra >= 0) {
 #pragma unroll
-      for (int q = 0; q < 2 * NB; ++q) {
-        double y = rs_half(x[q], x[q]);
-        x[q] = row16_sum(rs_row(y, y));
+        for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk(x[0][2 * b], x[0][2 * b + 1]);
       }
-      if (lane == 0) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) rp[(int64_t)(i * NB + jj) * d.Tp + j] = cmk(x[2 * jj], x[2 * jj + 1]);
-      }
-      asm volatile("" ::: "memory");  // keep the next row i's loads after this one (register pressure)
     }
+    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
   }
   __syncthreads();  // every wavefront is done with sS
   cplx (*red)[NBB][64] = sS;
@@ -1071,22 +1080,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 }
 
 // FP32 form of k_hist_bulk_split: each half's 16 components are 8 column-interleaved pairs,
-// one 16-byte load each; FP32 products and row reductions, column sums in FP32 over tiles of
-// 16 rows per wavefront, then FP64.
+// one 16-byte load each; FP32 products and row reductions, column sums in FP32 over each
+// wavefront's 16-row groups, then FP64.
 template <int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_hist_bulk32_split(Dims d, const cplx32* __restrict__ hist,
-                                                           const cplx* __restrict__ sig,
-                                                           cplx* __restrict__ colsum, cplx* __restrict__ rowpart,
-                                                           int m) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_bulk32_split(
+    Dims d, const cplx32* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+    cplx* __restrict__ rowpart, int m) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
+  static_assert(NB == 4, "the four block rows share one reduce-scatter");
   static_assert(NBB % 2 == 0, "component pairs must not straddle the halves");
-  constexpr int FLUSH = 16;
   __shared__ cplx32 sS[2][NBB][64];
   __shared__ cplx red[2][NBB][64];
+  __shared__ cplx stg[2][2][NBB * 16];
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63;
-  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform: rows and Sigma^R in SGPRs
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int h = wv & 1, rg = wv >> 1;
   int tp = 64 * s + lane;
   bool colv = tp < m;
@@ -1106,66 +1115,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   }
   const cplx32* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
+  cplx* st = stg[rg][h];
   const float sgn = h ? 1.f : -1.f;
-  int it = 0;
-  for (int j = 64 * s + rg; j < m; j += 2) {
-    bool v = colv && tp <= j;
-    const cplx32* row = hk + 64 * (int64_t)C * j;
-    cplx32 G[NBB];
+  for (int cb = 64 * s; cb < m; cb += 32) {
+    const int rb = cb + 16 * rg;
+    for (int i = 0; i < 16; ++i) {
+      const int j = rb + i;
+      if (j >= m) break;
+      bool v = colv && tp <= j;
+      const cplx32* row = hk + 64 * (int64_t)C * j;
+      cplx32 G[NBB];
 #pragma unroll
-    for (int p = 0; p < NBB / 2; ++p) {
-      if (v) {
-        load_stream32x2(row + 128 * p, G[2 * p], G[2 * p + 1]);
-      } else {
-        G[2 * p] = make_float2(0.f, 0.f);
-        G[2 * p + 1] = make_float2(0.f, 0.f);
+      for (int p = 0; p < NBB / 2; ++p) {
+        if (v) {
+          load_stream32x2(row + 128 * p, G[2 * p], G[2 * p + 1]);
+        } else {
+          G[2 * p] = make_float2(0.f, 0.f);
+          G[2 * p + 1] = make_float2(0.f, 0.f);
+        }
+      }
+      bool rv = tp < j;
+      float x[NB][2 * NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        cplx32 SRa[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) SRa[l] = to32(sk[(2 * NBB + a * NB + l) * d.Tp + j]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int l = 0; l < NB; ++l) cmac32(acc32[a * NB + b], SRa[l], G[l * NB + b]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          cplx32 t = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int l = 0; l < NB; ++l) cmacc32(t, sS[h][a * NB + l][lane], G[b * NB + l]);
+          x[a][2 * b] = rv ? sgn * t.x : 0.f;
+          x[a][2 * b + 1] = rv ? sgn * t.y : 0.f;
+        }
+      }
+      reduce_rows32<NB>(x);
+      int ra = reduced_row<NB>(lane);
+      if (ra >= 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk((double)x[0][2 * b], (double)x[0][2 * b + 1]);
       }
     }
-    bool rv = tp < j;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      cplx32 SRi[NB];
-#pragma unroll
-      for (int l = 0; l < NB; ++l) SRi[l] = to32(sk[(2 * NBB + i * NB + l) * d.Tp + j]);
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-#pragma unroll
-        for (int l = 0; l < NB; ++l) cmac32(acc32[i * NB + jj], SRi[l], G[l * NB + jj]);
-      float x[2 * NB];
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        cplx32 a = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int l = 0; l < NB; ++l) cmacc32(a, sS[h][i * NB + l][lane], G[jj * NB + l]);
-        x[2 * jj] = rv ? sgn * a.x : 0.f;
-        x[2 * jj + 1] = rv ? sgn * a.y : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < 2 * NB; ++q) {
-        float y = rs_half32(x[q], x[q]);
-        x[q] = row16_sum32(rs_row32(y, y));
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj)
-          rp[(int64_t)(i * NB + jj) * d.Tp + j] = cmk((double)x[2 * jj], (double)x[2 * jj + 1]);
-      }
-      asm volatile("" ::: "memory");
+    for (int e = 0; e < NBB; ++e) {
+      acc[e].x += (double)acc32[e].x;
+      acc[e].y += (double)acc32[e].y;
+      acc32[e] = make_float2(0.f, 0.f);
     }
-    if (++it == FLUSH) {
-      it = 0;
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        acc[e].x += (double)acc32[e].x;
-        acc[e].y += (double)acc32[e].y;
-        acc32[e] = make_float2(0.f, 0.f);
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < NBB; ++e) {
-    acc[e].x += (double)acc32[e].x;
-    acc[e].y += (double)acc32[e].y;
+    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
   }
   if (rg == 1) {
 #pragma unroll

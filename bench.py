@@ -32,17 +32,23 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by what the same counters
 # read for a plain 1 GiB device copy (x2.000 and x1.000); summary and commands in
 # profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
-# (SHA-1 of kbe_kernels.hip + kbe_device.hpp); reported as null once that source changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0215,
+# (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
+# once that code changes.
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2686e10, "fetch_over_algorithmic": 1.0216,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "48b17e976a36f1bdc275da61fd78fe3b353273b0"}
+                    "source_sha1": "d0eb86085dbd1f8bf395dc7c4b543cfd075ea9ee"}
 
 
 def _kernel_source_sha1():
+    """SHA-1 of the kernel sources with comments and blank lines removed (code changes only)."""
     import hashlib
+    import re
     d = os.path.join(ROOT, "paper_2505_19467_amd", "csrc")
-    data = b"".join(open(os.path.join(d, f), "rb").read() for f in ("kbe_kernels.hip", "kbe_device.hpp"))
-    return hashlib.sha1(data).hexdigest()
+    code = []
+    for f in ("kbe_kernels.hip", "kbe_device.hpp"):
+        text = re.sub(r"/\*.*?\*/", "", open(os.path.join(d, f)).read(), flags=re.S)
+        code += [ln.split("//")[0].rstrip() for ln in text.splitlines()]
+    return hashlib.sha1("\n".join(ln for ln in code if ln).encode()).hexdigest()
 
 
 def _energy_balance(obs, cfg):

@@ -500,7 +500,8 @@ __device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int
 // wavefront takes 16 consecutive rows of every 64-row chunk, R rows per iteration (R = 1 at
 // nb = 2: 2 x 8 loads of 1 KB-contiguous data in flight; R = 4 at nb = 1), so every stored
 // block is read from HBM once. The row terms of the two strips are added before the 64-lane
-// reduce-scatter, so one row partial covers 128 columns: the writes that interleave with the
+// reduce-scatter (at nb = 2 the four components of the row term share one reduce-scatter as
+// four groups), so one row partial covers 128 columns: the writes that interleave with the
 // read stream are half of what one strip per block would produce, and they leave as whole
 // 256-byte runs (a wavefront's 16 rows staged in LDS, streaming stores). Both measures keep
 // the read stream from stalling on scattered write-backs. Row partials go to slot sp; the 4
@@ -591,11 +592,25 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
         }
       }
-      reduce_rows<R>(rt);
-      int rr = reduced_row<R>(lane);
-      if (rr >= 0) {
+      if constexpr (R == 1 && NBB == 4) {
+        // one row, four components: each component's (re, im) is one group of a 4-group
+        // reduce-scatter (2 lane reductions instead of 8)
+        double xg[4][2];
 #pragma unroll
-        for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+        for (int e = 0; e < 4; ++e) {
+          xg[e][0] = rt[0][2 * e];
+          xg[e][1] = rt[0][2 * e + 1];
+        }
+        reduce_rows<4>(xg);
+        int e = reduced_row<4>(lane);
+        if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
+      } else {
+        reduce_rows<R>(rt);
+        int rr = reduced_row<R>(lane);
+        if (rr >= 0) {
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+        }
       }
     }
     flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
@@ -732,12 +747,32 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
             }
         }
       }
-      reduce_rows32<R>(rt);
-      int rr = reduced_row<R>(lane);
-      if (rr >= 0) {
+      if constexpr (R == 2 && NBB == 4) {
+        // two rows, four components: groups (row, component pair) of a 4-group reduce-scatter
+        // (4 lane reductions instead of 8); group g = 2 r + p holds components 2 p, 2 p + 1
+        float xg[4][4];
 #pragma unroll
-        for (int e = 0; e < NBB; ++e)
-          st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xg[2 * r + p2][q] = rt[r][4 * p2 + q];
+        reduce_rows32<4>(xg);
+        int g = reduced_row<4>(lane);
+        if (g >= 0) {
+          int r = g >> 1, p2 = g & 1;
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            st[(2 * p2 + c) * 16 + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
+        }
+      } else {
+        reduce_rows32<R>(rt);
+        int rr = reduced_row<R>(lane);
+        if (rr >= 0) {
+#pragma unroll
+          for (int e = 0; e < NBB; ++e)
+            st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+        }
       }
     }
     // the group's FP32 column sums into the FP64 accumulators

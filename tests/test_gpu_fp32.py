@@ -40,7 +40,8 @@ def _rel(got, ref):
     return np.abs(np.asarray(got) - np.asarray(ref)).max() / np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nkx,nky,nb,m", [(3, 2, 2, 130), (2, 2, 1, 70), (2, 1, 3, 66), (1, 2, 2, 1), (2, 1, 2, 17)])
+@pytest.mark.parametrize("nkx,nky,nb,m", [(3, 2, 2, 130), (2, 2, 1, 70), (2, 1, 3, 66), (1, 2, 2, 1), (2, 1, 2, 17),
+                                          (2, 1, 2, 129), (1, 2, 1, 257), (1, 1, 4, 129), (2, 1, 2, 64)])
 def test_fp32_collision_row(K, nkx, nky, nb, m):
     import torch
     _say(f"fp32 collision nk={nkx}x{nky} nb={nb} m={m}")

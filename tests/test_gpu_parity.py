@@ -89,8 +89,12 @@ def test_sigma_row_parity(K, nkx, nky, nb, m):
 
 
 # ---------------------------------------------------------------- collision row
+# m spans the strip-pair boundaries of the nb <= 2 kernels: 64 (one strip), 65 (the pair's second
+# strip holds one column), 128 / 129 (a second pair without / with its first column), 192, 257
 @pytest.mark.parametrize("nkx,nky,nb,m", [(3, 2, 2, 130), (4, 1, 1, 64), (2, 2, 3, 65), (2, 1, 4, 70),
-                                          (2, 2, 2, 1), (2, 2, 2, 2), (1, 3, 2, 63), (2, 1, 2, 200)])
+                                          (2, 2, 2, 1), (2, 2, 2, 2), (1, 3, 2, 63), (2, 1, 2, 200),
+                                          (2, 2, 2, 128), (2, 1, 1, 129), (1, 2, 2, 192), (2, 1, 2, 257),
+                                          (1, 2, 1, 65), (1, 1, 4, 129)])
 def test_collision_row_parity(K, nkx, nky, nb, m):
     import torch
     _say(f"collision parity nk={nkx}x{nky} nb={nb} m={m}")

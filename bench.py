@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # once that code changes.
 MEASURED_TRAFFIC = {"bytes_per_launch": 1.2686e10, "fetch_over_algorithmic": 1.0216,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "d0eb86085dbd1f8bf395dc7c4b543cfd075ea9ee"}
+                    "source_sha1": "e82dd0efb4ca1bd0f66625529cde19913aa4e82d"}
 
 
 def _kernel_source_sha1():

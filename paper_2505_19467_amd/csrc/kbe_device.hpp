@@ -432,12 +432,87 @@ __device__ __forceinline__ void axis_dft(cplx* __restrict__ x0, cplx* __restrict
   __syncthreads();
 }
 
+// fft_split for sizes known at compile time
+constexpr int fft_split_ct(int n) {
+  int best = 1;
+  for (int f = 2; f * f <= n; ++f)
+    if (n % f == 0) best = f;
+  return best;
+}
+
+// axis_dft with the line length, line count and layout fixed at compile time: the same two
+// Cooley-Tukey stages, with every loop unrolled so that the Horner chains of different outputs
+// are independent instruction streams (composite n only).
+template <int N, int NLINES, int LM, int ST>
+__device__ __forceinline__ void axis_dft_ct(cplx* __restrict__ x0, cplx* __restrict__ x1, cplx* __restrict__ t0,
+                                            cplx* __restrict__ t1, const cplx* __restrict__ tw, int sgn, double scale) {
+  constexpr int N1 = fft_split_ct(N), N2 = N / N1;
+  static_assert(N1 > 1, "prime line lengths take the runtime transform");
+  constexpr int IA = 2 * NLINES * N2;  // stage A items: (array, line, p2)
+#pragma unroll
+  for (int it0 = 0; it0 < IA; it0 += 256) {
+    int it = it0 + threadIdx.x;
+    if (it < IA) {
+      int arr = it / (NLINES * N2);
+      int rem = it - arr * NLINES * N2;
+      int line = rem / N2, p2 = rem - (rem / N2) * N2;
+      const cplx* x = (arr ? x1 : x0) + line * LM;
+      cplx* t = (arr ? t1 : t0) + line * LM;
+      cplx v[N1];
+#pragma unroll
+      for (int p1 = 0; p1 < N1; ++p1) v[p1] = x[(p1 * N2 + p2) * ST];
+#pragma unroll
+      for (int q1 = 0; q1 < N1; ++q1) {
+        cplx r = root(tw, (N2 * q1) % N, sgn), acc = czero();
+#pragma unroll
+        for (int p1 = N1 - 1; p1 >= 0; --p1) acc = cadd(cmul(acc, r), v[p1]);
+        t[(q1 * N2 + p2) * ST] = cmul(acc, root(tw, (p2 * q1) % N, sgn));
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int IB = 2 * NLINES * N1;  // stage B items: (array, line, q1), all N2 outputs each
+#pragma unroll
+  for (int it0 = 0; it0 < IB; it0 += 256) {
+    int it = it0 + threadIdx.x;
+    if (it < IB) {
+      int arr = it / (NLINES * N1);
+      int rem = it - arr * NLINES * N1;
+      int line = rem / N1, q1 = rem - (rem / N1) * N1;
+      const cplx* t = (arr ? t1 : t0) + line * LM + q1 * N2 * ST;
+      cplx* x = (arr ? x1 : x0) + line * LM;
+      cplx z[N2], acc[N2];
+#pragma unroll
+      for (int q2 = 0; q2 < N2; ++q2) {
+        z[q2] = root(tw, (q2 * N1) % N, sgn);
+        acc[q2] = czero();
+      }
+#pragma unroll
+      for (int p2 = N2 - 1; p2 >= 0; --p2) {
+        cplx v = t[p2 * ST];
+#pragma unroll
+        for (int q2 = 0; q2 < N2; ++q2) acc[q2] = cadd(cmul(acc[q2], z[q2]), v);
+      }
+#pragma unroll
+      for (int q2 = 0; q2 < N2; ++q2) x[(q1 + N1 * q2) * ST] = cscal(acc[q2], scale);
+    }
+  }
+  __syncthreads();
+}
+
 // Index transform of an nx x ny grid (k = ix * ny + iy) for two arrays in place:
 //   x(R) <- scale * sum_k e^{sgn 2 pi i (ix Rx / nx + iy Ry / ny)} x(k); y lines, then x lines.
 __device__ __forceinline__ void grid_dft(cplx* x0, cplx* x1, cplx* t0, cplx* t1, int nx, int ny, const cplx* twx,
                                          const cplx* twy, int sgn, double scale) {
   axis_dft(x0, x1, t0, t1, ny, nx, ny, 1, twy, sgn, 1.0);
   axis_dft(x0, x1, t0, t1, nx, ny, 1, ny, twx, sgn, scale);
+}
+// grid_dft for grid sizes fixed at compile time (NY = 1: a chain, only the x lines)
+template <int NX, int NY>
+__device__ __forceinline__ void grid_dft_ct(cplx* x0, cplx* x1, cplx* t0, cplx* t1, const cplx* twx, const cplx* twy,
+                                            int sgn, double scale) {
+  if constexpr (NY > 1) axis_dft_ct<NY, NX, NY, 1>(x0, x1, t0, t1, twy, sgn, 1.0);
+  axis_dft_ct<NX, NY, 1, NY>(x0, x1, t0, t1, twx, sgn, scale);
 }
 
 }  // namespace kbe

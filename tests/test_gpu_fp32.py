@@ -67,6 +67,35 @@ def test_fp32_collision_row(K, nkx, nky, nb, m):
     assert err < PASS_TOL
 
 
+@pytest.mark.parametrize("name,ks", [("c2", (0, 313, 575)), ("c5", (0, 129, 255))])
+def test_fp32_collision_full_size_sampled(K, name, ks):
+    """The FP32-form history sums at the full workload sizes (24x24, nb = 2, m = 1000 and
+    16x16, nb = 4, m = 1600: 87 GB of complex64), in the launch configuration the benchmark
+    times; sampled k-points recomputed by the oracle from the stored FP32 blocks."""
+    from tests.sampled import collision_reference
+    import torch
+    cfg = inputs.WORKLOADS[name]().replace(precision=inputs.PRECISION_FP32)
+    m = cfg.nt
+    _say(f"full-size fp32 collision {name} m={m} nk={cfg.nk} nb={cfg.nb}")
+    S = K.System(cfg)
+    assert S.history.dtype == torch.complex64
+    inputs.fill_normal_(S.history, seed=31, scale=0.3)
+    inputs.fill_normal_(S.sigma_planes(), seed=32, scale=0.3)
+    sp = S.sigma_planes()
+    sp[:, 2].copy_(sp[:, 1] - sp[:, 0])
+    S.rebuild_aux(m)
+    S.stage_collision(m)
+    got_all = S.collision_row(m).cpu().numpy()
+    sig_all = S.sigma_row(m).cpu().numpy()
+    for k in ks:
+        ref = collision_reference(K, S, cfg, m, k, sig_all)
+        err = _rel(got_all[:, k:k + 1], ref)
+        _say(f"  k={k}: relative error {err:.2e}")
+        assert err < PASS_TOL
+    S.close()
+    del S
+
+
 SERIES = ["N", "Ekin", "EHF", "Ecorr", "Etot", "Jx", "n_orb0", "n_orb1", "n_band0", "n_band1"]
 
 

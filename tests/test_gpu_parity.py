@@ -271,6 +271,33 @@ def test_collision_full_size_sampled(K):
         assert err < KERNEL_TOL
 
 
+def test_collision_full_size_sampled_nb4(K):
+    """The nb = 4 history sums at the 16x16 workload's largest pass (m = 1600, 256 k-points,
+    a 175 GB history of ~1.1e10 complex elements, so the element offsets pass 2^31); sampled
+    k-points, among them the last, recomputed one by one by the oracle."""
+    from tests.sampled import collision_reference
+    cfg = inputs.c5()
+    m = cfg.nt
+    _say(f"full-size nb = 4 collision m={m} nk={cfg.nk}")
+    S = K.System(cfg)
+    assert S.history.numel() > 2 ** 31
+    inputs.fill_normal_(S.history, seed=2026, scale=0.3)
+    inputs.fill_normal_(S.sigma_planes(), seed=2027, scale=0.3)
+    sp = S.sigma_planes()
+    sp[:, 2].copy_(sp[:, 1] - sp[:, 0])
+    S.rebuild_aux(m)
+    S.stage_collision(m)
+    got_all = S.collision_row(m).cpu().numpy()
+    sig_all = S.sigma_row(m).cpu().numpy()
+    for k in (0, 129, cfg.nk - 1):
+        ref = collision_reference(K, S, cfg, m, k, sig_all)
+        err = relerr(got_all[:, k:k + 1], ref)
+        _say(f"  k={k}: rel err {err:.2e}")
+        assert err < KERNEL_TOL
+    S.close()
+    del S
+
+
 def test_sigma_full_size_sampled(K):
     """Self-energy of the 24x24 workload's last slice (m = 1000), sampled t_j compared
     with the oracle (Sigma(t_m, t_j) depends only on G(t_m, t_j))."""

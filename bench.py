@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
 # (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
 # once that code changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2686e10, "fetch_over_algorithmic": 1.0216,
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2687e10, "fetch_over_algorithmic": 1.0217,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "e82dd0efb4ca1bd0f66625529cde19913aa4e82d"}
+                    "source_sha1": "a15608e463eb2158a06374a8fb4278c612016c21"}
 
 
 def _kernel_source_sha1():
@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=60, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the run with the corrector's stopping rule (tolerance mode)")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the plain copy/read bandwidth probe")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not record HIP events around the history-sum launches (for counter-collection runs)")
@@ -223,6 +225,33 @@ def main():
         torch.cuda.empty_cache()
         S = kbe.System(cfg)
 
+    adaptive = None
+    if not args.no_adaptive and args.workload == "c2":
+        # Algorithm "prop"'s stopping rule on the same workload: at most 4 corrector passes, stop
+        # once the row changes by <= 6e-9 (a wide gap of the changes: 3 passes on every step)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        ca = cfg.replace(n_corr=4, corr_tol=6e-9)
+        S, ra = run(ca)
+        passes, _ = S.corrector_log(1, K)
+        oa = ra["obs"]
+        dev = {n: float(np.abs(oa[:, i] - obs[:, i]).max() / np.abs(obs[:, i]).max())
+               for n, i in {"n_band1": 14, "Jx": 6, "Etot": 5}.items()}
+        adaptive = {"value": K / ra["elapsed"], "unit": "steps/s", "corr_tol": ca.corr_tol, "max_passes": ca.n_corr,
+                    "mean_passes": float(passes.mean()), "pass_histogram": np.bincount(passes).tolist(),
+                    "history_passes_per_step": 1.0 + float(passes.mean()),
+                    "max_rel_dev_vs_one_pass": dev,
+                    "workload": f"{ca.name}: corrector passes until the row changes by <= {ca.corr_tol:g} "
+                                f"(at most {ca.n_corr}), FP64"}
+        print(f"[bench] stopping rule: {K} steps in {ra['elapsed']:.3f} s = {K / ra['elapsed']:.1f} steps/s; "
+              f"{passes.mean():.2f} corrector passes per step; deviation from one pass "
+              f"{max(dev.values()):.1e}", file=sys.stderr, flush=True)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        S = kbe.System(cfg)
+
     adj = None
     if not args.no_adjoint:
         S.close()
@@ -280,6 +309,7 @@ def main():
                      "launches": launches, "kernel_ms": kms},
         "cpu_baseline": cpu,
         "fp32_form": fp32,
+        "adaptive_corrector": adaptive,
         "adjoint": adj,
         "hbm_ceiling": ceiling,
         "checks": {"N_drift": n_drift, "energy_balance_max": e_bal, "finite": finite},

@@ -79,10 +79,18 @@ typedef struct {
   int32_t interaction;  /* KBE_INT_* */
   int32_t hf;           /* 1: include the first-order (Hartree-Fock) self-energy in h */
   int32_t corr;         /* 1: include the second-Born correlation self-energy */
-  int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes */
+  int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes.
+                           With corr_tol > 0 the most passes a step may take. */
   int32_t nt_max;       /* largest step index the buffers hold */
   int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
   double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
+  double corr_tol;      /* 0: every step runs n_corr corrector passes. > 0: the stopping rule of
+                           Algorithm "prop" (its max and epsilon): after each pass the largest
+                           modulus of the change of row m (every t', k, component and orbital
+                           pair, the equal-time block included) is brought to the host, and the
+                           passes stop once it is <= corr_tol or n_corr passes have run. This
+                           synchronises the stream once per pass; kbe_corrector_log reports the
+                           passes taken. The adjoint needs corr_tol = 0. */
 } kbe_config;
 
 /* Peierls pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2) along pol = (pol[0], pol[1]). */
@@ -139,6 +147,12 @@ int kbe_step(kbe_ctx* ctx, int32_t nsteps);
 
 /* Index of the last completed step (0 after kbe_create). */
 int32_t kbe_current_step(const kbe_ctx* ctx);
+
+/* Corrector log (host-side record, no synchronisation): for steps first .. first + count - 1,
+ * passes[i] = corrector passes taken (0 for step 0 and for steps not yet run); if changes is
+ * not NULL, changes[i * n_corr + p] = the row change after pass p of that step (only recorded
+ * with corr_tol > 0; -1 where no pass ran). KBE_ERR_INVALID_ARG outside 0 .. nt_max. */
+int kbe_corrector_log(const kbe_ctx* ctx, int32_t first, int32_t count, int32_t* passes, double* changes);
 
 /* Synchronise the stream and copy observable rows first..first+count-1 to host_out
  * (count x KBE_NOBS doubles). Returns KBE_ERR_NONFINITE if the state is not finite. */

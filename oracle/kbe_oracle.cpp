@@ -16,8 +16,9 @@
 //   self-energy ....... eq. (2BSE) (second Born), evaluated in real space
 //   collision integral  eq. (CI) in its Langreth "left" form, trapezoid rule
 //                       ("standard second order numerical integration")
-//   propagation ....... Algorithm "prop" (predictor, fixed number of corrector
-//                       passes, re-evaluation after the step) with an
+//   propagation ....... Algorithm "prop" (predictor, corrector passes -- a fixed
+//                       number, or up to that number until the row changes by at
+//                       most a tolerance -- and re-evaluation after the step) with an
 //                       exponential-midpoint solve of eq. (Green)
 //
 // Conventions: G^<(t,t') = i<c^dag(t') c(t)>, G^>(t,t') = -i<c(t) c^dag(t')>;
@@ -45,6 +46,9 @@
 //                     lower one to rounding (Hubbard and interband presets); rho Hermitian
 //   tangent-linear .. R = double run reproduced bit-for-bit by the value part; derivatives
 //                     against central finite differences of the double oracle
+//   corrector tol ... tolerance 0 reproduces the fixed-count run bit for bit, an infinite one
+//                     the single-pass run; the changes shrink geometrically pass by pass and
+//                     the stopping pass is the first whose change is at most the tolerance
 
 #include <algorithm>
 #include <cmath>
@@ -137,6 +141,7 @@ template <class R> inline Cx<R> imag_unit() { return Cx<R>(R(0.0), R(1.0)); }
 struct Params {
   int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, pad_;
   double dt, U, temp, filling, amp, omega, t0, width, polx, poly;
+  double corr_tol;  // > 0: corrector passes stop once the row changes by at most this
 };
 enum { INT_HUBBARD = 0, INT_INTERBAND = 1 };
 enum {
@@ -342,6 +347,8 @@ struct State {
   std::vector<C> rho_prev, rho_cur, D_prev, D_cur;  // [k][a][b]
   std::vector<C> I_prev, I_cur;    // [t'][k][comp][a][b], t' = 0..m
   std::vector<C> sig;              // [j][k][comp][a][b], j = 0..m
+  std::vector<int> passes;         // corrector passes taken at each step (index m)
+  std::vector<double> changes;     // after each pass: max |G_new - G_old| over row m
   State(const Params& pp, const Theta<R>& t, const double* hopd) : p(pp), th(t), g(pp) {
     nbb = g.nb * g.nb;
     blk = 2 * nbb;
@@ -769,15 +776,42 @@ void update_row(State<R>& st, int m, bool corrector) {
   for (int k = 0; k < nk; ++k) set_diag_block(nb, &st.rho_cur[k * nbb], st.at(m, m, k));
 }
 
+// Largest modulus of the change of row m between two iterates (every t', k, component and
+// orbital pair, the equal-time block included): the norm of the stopping test of
+// Algorithm "prop", which the paper leaves unspecified.
+template <class R>
+double row_change(const std::vector<Cx<R>>& a, const std::vector<Cx<R>>& b) {
+  double mx = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    double dr = val(a[i].re) - val(b[i].re), di = val(a[i].im) - val(b[i].im);
+    mx = std::max(mx, std::sqrt(dr * dr + di * di));
+  }
+  return mx;
+}
+
+// One step of Algorithm "prop": predictor, then at most n_corr corrector passes; with
+// corr_tol > 0 the passes stop at the first whose change of the row is <= corr_tol (the
+// algorithm's max and epsilon), otherwise all n_corr passes run.
 template <class R>
 void step(State<R>& st, int m) {
   int nk = st.g.nk, blk = st.blk;
   st.rows.emplace_back((size_t)(m + 1) * nk * blk);
   update_row(st, m, false);
+  int passes = 0;
   for (int it = 0; it < st.p.n_corr; ++it) {
+    std::vector<Cx<R>> before;
+    if (st.p.corr_tol > 0.0) before = st.rows[m];
     sigma_and_collision(st, m);
     update_row(st, m, true);
+    ++passes;
+    if (st.p.corr_tol > 0.0) {
+      double ch = row_change(st.rows[m], before);
+      st.changes.push_back(ch);
+      if (ch <= st.p.corr_tol) break;
+    }
   }
+  if ((int)st.passes.size() <= m) st.passes.resize(m + 1, 0);
+  st.passes[m] = passes;
   sigma_and_collision(st, m);
   st.I_prev = st.I_cur;
   st.D_prev = st.D_cur;
@@ -1014,6 +1048,31 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
     }
   }
   if (rho_out) to_doubles(st.rho_cur.data(), st.rho_cur.size(), rho_out);
+  return 0;
+}
+
+// oracle_run with the corrector log: passes[m] = corrector passes of step m (passes[0] = 0);
+// changes[(m - 1) * n_corr + i] = row change after pass i of step m (-1 where no pass ran;
+// only filled when corr_tol > 0).
+int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* obs, int32_t* passes,
+                   double* changes) {
+  if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
+  if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  Theta<double> th{p->amp, p->omega, p->U};
+  State<double> st(*p, th, hop);
+  init(st);
+  if (obs) observables(st, 0, obs);
+  if (changes)
+    for (int64_t i = 0; i < (int64_t)nsteps * p->n_corr; ++i) changes[i] = -1.0;
+  for (int m = 1; m <= nsteps; ++m) {
+    size_t c0 = st.changes.size();
+    step(st, m);
+    if (obs) observables(st, m, obs + (size_t)m * NOBS);
+    if (changes)
+      for (size_t i = c0; i < st.changes.size(); ++i) changes[(size_t)(m - 1) * p->n_corr + (i - c0)] = st.changes[i];
+  }
+  if (passes)
+    for (int m = 0; m <= nsteps; ++m) passes[m] = m < (int)st.passes.size() ? st.passes[m] : 0;
   return 0;
 }
 

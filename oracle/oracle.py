@@ -42,7 +42,7 @@ class OracleParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt", "pad_")] + \
                [(n, ctypes.c_double) for n in
-                ("dt", "U", "temp", "filling", "amp", "omega", "t0", "width", "polx", "poly")]
+                ("dt", "U", "temp", "filling", "amp", "omega", "t0", "width", "polx", "poly", "corr_tol")]
 
 
 _lib = None
@@ -62,6 +62,7 @@ def lib():
         _lib.oracle_initial_state.argtypes = [P, dp, dp, dp]
         _lib.oracle_h0.argtypes = [P, dp, ctypes.c_double, dp]
         _lib.oracle_tlm_run.argtypes = [P, dp, ctypes.c_int32, dp, dp]
+        _lib.oracle_run_log.argtypes = [P, dp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int32), dp]
         _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
     return _lib
 
@@ -79,7 +80,7 @@ def params(cfg) -> OracleParams:
                         interaction=cfg.interaction, hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
                         nt=cfg.nt, pad_=0, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling,
                         amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
-                        polx=pu.pol[0], poly=pu.pol[1])
+                        polx=pu.pol[0], poly=pu.pol[1], corr_tol=cfg.corr_tol)
 
 
 def _hop(cfg) -> np.ndarray:
@@ -112,6 +113,22 @@ def run(cfg, nsteps: int | None = None, history: bool = False):
             off += sz
         out["rows"] = rows
     return out
+
+
+def run_log(cfg, nsteps: int | None = None):
+    """Propagation with the corrector log (Algorithm "prop"'s max / epsilon loop).
+    Returns (obs, passes, changes): passes[m] corrector passes of step m, changes[m - 1, i] the
+    row change after pass i of step m (-1: no such pass; only with cfg.corr_tol > 0)."""
+    n = cfg.nt if nsteps is None else nsteps
+    obs = np.zeros((n + 1, NOBS))
+    passes = np.zeros(n + 1, np.int32)
+    changes = np.zeros((max(n, 1), max(cfg.n_corr, 1)))
+    p = params(cfg)
+    rc = lib().oracle_run_log(ctypes.byref(p), _ptr(_hop(cfg)), n, _ptr(obs),
+                              passes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(changes))
+    if rc != 0:
+        raise ValueError(f"oracle_run_log rejected the configuration (rc={rc})")
+    return obs, passes, changes[:n, :cfg.n_corr]
 
 
 def tlm_run(cfg, nsteps: int | None = None):

@@ -21,7 +21,7 @@ namespace {
 
 enum {
   B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
-  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_COUNT
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_CHG, B_CHGMAX, B_COUNT
 };
 
 struct Layout {
@@ -49,6 +49,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   }
   if (c->precision != KBE_FP64 && c->precision != KBE_FP32) { *why = "precision must be KBE_FP64 or KBE_FP32"; return KBE_ERR_INVALID_ARG; }
   if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
+  if (!(c->corr_tol >= 0.0) || !std::isfinite(c->corr_tol)) { *why = "corr_tol must be finite and >= 0"; return KBE_ERR_INVALID_ARG; }
+  if (c->corr_tol > 0.0 && c->n_corr < 1) { *why = "corr_tol > 0 needs n_corr >= 1 (the most passes)"; return KBE_ERR_INVALID_ARG; }
   if (!(c->dt > 0.0) || !(c->temp > 0.0) || !std::isfinite(c->U) || c->spin_deg < 1 || c->spin_deg > 2) {
     *why = "dt and temp must be positive, U finite, spin_deg 1 or 2";
     return KBE_ERR_INVALID_ARG;
@@ -82,6 +84,9 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_EIGU] = nk * d.nbb * cz;
   sz[B_MU] = sizeof(double);
   sz[B_ROW64] = 2 * nk * d.C * d.Tp * cz;
+  // corrector change per (k, t') and its maximum, only when the corrector stops on a tolerance
+  sz[B_CHG] = c->corr_tol > 0.0 ? nk * d.Tp * sizeof(double) : 0;
+  sz[B_CHGMAX] = c->corr_tol > 0.0 ? sizeof(double) : 0;
   size_t off = 0;
   for (int i = 0; i < B_COUNT; ++i) {
     L->off[i] = off;
@@ -165,6 +170,9 @@ struct kbe_ctx {
   int adj_m;     // next step to reverse
   int adj_cur;   // role of the double-buffered adjoint rows
   bool frozen;   // working buffers overwritten by a reverse sweep
+  // corrector log (host): passes taken per step, and the row change after each pass
+  std::vector<int32_t> passes;
+  std::vector<double> changes;
 
   template <class T>
   T* buf(int b) const { return reinterpret_cast<T*>(ws + L.off[b]); }
@@ -192,6 +200,7 @@ struct kbe_ctx {
     a.mu = buf<double>(B_MU);
     a.obs = obs;
     a.commit = 1;
+    a.chg = nullptr;
     a.Ax = a.Ay = 0.0;
     a.polx = pulse.pol[0];
     a.poly = pulse.pol[1];
@@ -263,11 +272,37 @@ struct kbe_ctx {
     LaunchArgs a = args();
     int rc = props(a, m, 0);
     if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_PREDICT, st), "predictor launch");
+    // Corrector passes of Algorithm "prop": all n_corr of them, or (corr_tol > 0) until the
+    // largest change of row m is <= corr_tol, which needs the change on the host after each
+    // pass (one stream synchronisation per pass in that mode).
+    const bool tol = cfg.corr_tol > 0.0;
+    int taken = 0;
     for (int it = 0; it < cfg.n_corr && !rc; ++it) {
       rc = collision_parts(a, m);
       if (!rc) rc = props(a, m, 1);
+      a.chg = tol ? buf<double>(B_CHG) : nullptr;
       if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_CORRECT, st), "corrector launch");
+      a.chg = nullptr;
+      if (rc) break;
+      ++taken;
+      if (tol) {
+        double ch = 0.0;
+        rc = check(kbe::launch_change_max(L.d, buf<double>(B_CHG), m, buf<double>(B_CHGMAX), st),
+                   "corrector change launch");
+        if (!rc)
+          rc = check(hipMemcpyAsync(&ch, buf<double>(B_CHGMAX), sizeof(double), hipMemcpyDeviceToHost, st),
+                     "corrector change copy");
+        if (!rc) rc = check(hipStreamSynchronize(st), "stream synchronisation");
+        if (rc) break;
+        if (!std::isfinite(ch)) {
+          rc = fail(KBE_ERR_NONFINITE, "non-finite corrector change");
+          break;
+        }
+        changes[(size_t)m * cfg.n_corr + it] = ch;
+        if (ch <= cfg.corr_tol) break;
+      }
     }
+    if (!rc) passes[m] = taken;
     if (!rc) rc = collision_parts(a, m);
     if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_EVAL, st), "collision-row launch");
     if (!rc) rc = observe(m);
@@ -467,6 +502,8 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   c->adj_m = 0;
   c->adj_cur = 0;
   c->frozen = false;
+  c->passes.assign((size_t)cfg->nt_max + 1, 0);
+  c->changes.assign((size_t)(cfg->nt_max + 1) * (cfg->n_corr > 0 ? cfg->n_corr : 1), -1.0);
   const Dims& d = c->L.d;
   c->hop_host.resize(3 * d.nbb);
   for (int i = 0; i < 3 * d.nbb; ++i) c->hop_host[i] = make_double2(hop[2 * i], hop[2 * i + 1]);
@@ -506,6 +543,18 @@ int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
 }
 
 int32_t kbe_current_step(const kbe_ctx* ctx) { return ctx ? ctx->step : -1; }
+
+int kbe_corrector_log(const kbe_ctx* ctx, int32_t first, int32_t count, int32_t* passes, double* changes) {
+  if (!ctx || first < 0 || count < 0 || first + count > ctx->cfg.nt_max + 1) return KBE_ERR_INVALID_ARG;
+  const int K = ctx->cfg.n_corr > 0 ? ctx->cfg.n_corr : 1;
+  for (int i = 0; i < count; ++i) {
+    int m = first + i;
+    if (passes) passes[i] = ctx->passes[m];
+    if (changes)
+      for (int p = 0; p < ctx->cfg.n_corr; ++p) changes[(size_t)i * ctx->cfg.n_corr + p] = ctx->changes[(size_t)m * K + p];
+  }
+  return KBE_OK;
+}
 
 int kbe_observables(kbe_ctx* ctx, int32_t first, int32_t count, double* host_out) {
   if (!ctx || !host_out || first < 0 || count < 0 || first + count > ctx->cfg.nt_max + 1)
@@ -649,15 +698,15 @@ int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
   std::string why;
   int rc = make_layout(cfg, &L, &why);
   if (rc) return rc;
-  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->nb > 2) return KBE_ERR_SHAPE;
+  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->corr_tol != 0.0 || cfg->nb > 2) return KBE_ERR_SHAPE;
   *adjoint_bytes = adj_layout(L, nullptr);
   return KBE_OK;
 }
 
 int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes) {
   if (!ctx || !d_adjoint) return KBE_ERR_INVALID_ARG;
-  if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->L.d.nb > 2)
-    return ctx->fail(KBE_ERR_SHAPE, "the adjoint needs precision KBE_FP64, n_corr = 1 and nb <= 2");
+  if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->cfg.corr_tol != 0.0 || ctx->L.d.nb > 2)
+    return ctx->fail(KBE_ERR_SHAPE, "the adjoint needs precision KBE_FP64, a fixed n_corr = 1 (corr_tol = 0) and nb <= 2");
   if (ctx->adj_obs >= 0) return ctx->fail(KBE_ERR_STATE, "a reverse sweep is in progress");
   size_t need = adj_layout(ctx->L, ctx->adj_off);
   if (bytes < need) return ctx->fail(KBE_ERR_INVALID_ARG, "adjoint workspace smaller than kbe_adjoint_query");

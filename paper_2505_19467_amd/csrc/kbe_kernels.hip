@@ -1241,7 +1241,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              cplx* __restrict__ Icur, const cplx* __restrict__ props,
                                              const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
                                              const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
-                                             double dt, int commit) {
+                                             double dt, int commit, double* __restrict__ chg) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   int k = blockIdx.y;
   int tp = blockIdx.x * 256 + threadIdx.x;
@@ -1343,6 +1343,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         V[e] = P[e];
         Phi[e] = P[2 * NBB + e];
       }
+      double dmax = 0.0;
 #pragma unroll
       for (int sc = 0; sc < 2; ++sc) {
         cplx g[NBB];
@@ -1352,6 +1353,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
           int c = sc * NBB + e;
+          if (MODE == KBE_ROW_CORRECT && chg) {  // change against the iterate this pass started from
+            cplx dg = csub(g[e], row64[row64_idx(d, m, k, c, tp)]);
+            dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
+          }
           row64[row64_idx(d, m, k, c, tp)] = g[e];
           if (commit) {
             commit_store(d, hist, k, c, m, tp, g[e]);
@@ -1359,10 +1364,12 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
           }
         }
       }
+      if (MODE == KBE_ROW_CORRECT && chg) chg[(int64_t)k * d.Tp + tp] = dmax;
     }
   } else {
     // tp == m, PREDICT or CORRECT: density matrix and equal-time block
     cplx V[NBB], Vh[NBB], r0[NBB], Db[NBB], t1[NBB], rho[NBB], t2[NBB];
+    double dmax = 0.0;
 #pragma unroll
     for (int e = 0; e < NBB; ++e) {
       V[e] = P[e];
@@ -1392,6 +1399,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
 #pragma unroll
         for (int sc = 0; sc < 2; ++sc) {
           int c = sc * NBB + e;
+          if (MODE == KBE_ROW_CORRECT && chg) {
+            cplx dg = csub(g[sc], row64[row64_idx(d, m, k, c, m)]);
+            dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
+          }
           row64[row64_idx(d, m, k, c, m)] = g[sc];
           if (commit) {
             commit_store(d, hist, k, c, m, m, g[sc]);
@@ -1399,7 +1410,25 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
           }
         }
       }
+    if (MODE == KBE_ROW_CORRECT && chg) chg[(int64_t)k * d.Tp + m] = dmax;
   }
+}
+
+// Largest change of the corrector's row: out[0] = max over k and t' <= m of chg[k][t'].
+// One block, a fixed reduction order (max is exact, so any order gives the same value).
+__global__ __launch_bounds__(1024) void k_change_max(const double* __restrict__ chg, int nk, int Tp, int m,
+                                                     double* __restrict__ out) {
+  __shared__ double red[1024];
+  double mx = 0.0;
+  for (int k = 0; k < nk; ++k)
+    for (int t = threadIdx.x; t <= m; t += 1024) mx = fmax(mx, chg[(int64_t)k * Tp + t]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ------------------------------------------------------------------ observables
@@ -1605,7 +1634,7 @@ struct Launch {
 #define KBE_ROW_ARGS                                                                                      \
   d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
-      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit
+      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit, a.chg
     if (mode == KBE_ROW_PREDICT)
       hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
     else if (mode == KBE_ROW_CORRECT)
@@ -1660,6 +1689,10 @@ hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st
 }
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
   KBE_DISPATCH(d.nb, row(d, a, m, mode, st));
+}
+hipError_t launch_change_max(const Dims& d, const double* chg, int m, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_change_max, dim3(1), dim3(1024), 0, st, chg, d.nk, d.Tp, m, out);
+  return hipGetLastError();
 }
 hipError_t launch_obs(const Dims& d, const LaunchArgs& a, int m, double t, double A, hipStream_t st) {
   KBE_DISPATCH(d.nb, obs(d, a, m, t, A, st));

@@ -41,6 +41,7 @@ struct LaunchArgs {
   double* mu;
   double* obs;
   int commit;      // 0: the row kernel writes only the FP64 working row (recomputation)
+  double* chg;     // if set, the corrector row kernel writes max |G_new - G_old| per (k, t') here ([k][Tp])
   double Ax, Ay;  // A(t) * pol for the launch at hand
   double polx, poly;  // pulse polarisation
   double dt, U, UU, temp, target, spin;
@@ -55,6 +56,8 @@ hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t s
 hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st);
+// out[0] = max over k and t' <= m of chg[k][t'] (one block, deterministic)
+hipError_t launch_change_max(const Dims& d, const double* chg, int m, double* out, hipStream_t st);
 hipError_t launch_obs(const Dims& d, const LaunchArgs& a, int m, double t, double A, hipStream_t st);
 hipError_t launch_aux(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 

@@ -54,7 +54,8 @@ class Config:
     interaction: int = INTERACTION_HUBBARD
     hf: int = 1                         # include the first-order (Hartree-Fock) self-energy
     corr: int = 1                       # include the second-Born correlation self-energy
-    n_corr: int = 1                     # corrector passes K per step
+    n_corr: int = 1                     # corrector passes K per step (the maximum when corr_tol > 0)
+    corr_tol: float = 0.0               # > 0: stop the corrector once the row changes by <= corr_tol
     temp: float = 0.1
     filling: float = 0.5                # electrons per orbital per spin
     precision: int = PRECISION_FP64

@@ -39,7 +39,7 @@ BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_C
 class KbeConfig(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision")] + \
-               [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling")]
+               [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling", "corr_tol")]
 
 
 class KbePulse(ctypes.Structure):
@@ -58,6 +58,7 @@ _lib.kbe_step.argtypes = [_vp, _i32]
 _lib.kbe_current_step.argtypes = [_vp]
 _lib.kbe_current_step.restype = _i32
 _lib.kbe_observables.argtypes = [_vp, _i32, _i32, ctypes.POINTER(ctypes.c_double)]
+_lib.kbe_corrector_log.argtypes = [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]
 _lib.kbe_destroy.argtypes = [_vp]
 _lib.kbe_destroy.restype = None
 _lib.kbe_last_error.argtypes = [_vp]
@@ -74,7 +75,7 @@ _lib.kbe_adjoint_query.argtypes = [ctypes.POINTER(KbeConfig), _szp]
 _lib.kbe_adjoint_attach.argtypes = [_vp, _vp, ctypes.c_size_t]
 _lib.kbe_adjoint_step.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 
-EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_observables",
+EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_corrector_log", "kbe_observables",
            "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma",
            "kbe_stage_collision", "kbe_stage_update", "kbe_stage_observables", "kbe_stage_commit",
            "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query", "kbe_adjoint_query", "kbe_adjoint_attach",
@@ -89,7 +90,7 @@ def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
     return KbeConfig(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg, interaction=cfg.interaction,
                      hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
                      nt_max=cfg.nt if nt_max is None else nt_max, precision=cfg.precision,
-                     dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
+                     dt=cfg.dt, corr_tol=cfg.corr_tol, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
 
 
 def workspace_query(cfg: _inputs.Config, nt_max: int | None = None):
@@ -227,6 +228,18 @@ class System:
     @property
     def current_step(self) -> int:
         return int(_lib.kbe_current_step(self._ctx))
+
+    def corrector_log(self, first: int = 0, count: int | None = None):
+        """(passes, changes): corrector passes taken at steps first.., and the row change after
+        each pass ([step][pass], -1 where none ran; recorded only with corr_tol > 0)."""
+        n = self.current_step + 1 - first if count is None else count
+        passes = np.zeros(n, np.int32)
+        K = max(self.cfg.n_corr, 1)
+        changes = np.zeros((n, K))
+        self._check(_lib.kbe_corrector_log(self._ctx, first, n, passes.ctypes.data_as(ctypes.POINTER(_i32)),
+                                           changes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "kbe_corrector_log")
+        return passes, changes[:, :self.cfg.n_corr]
 
     def observables(self, first: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:

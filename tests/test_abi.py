@@ -123,3 +123,23 @@ def test_adjoint_query():
     # K = 2, the FP32 form and nb > 2 are outside the reverse sweep
     for bad in (cfg.replace(n_corr=2), cfg.replace(precision=inputs.PRECISION_FP32), inputs.c5()):
         assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(bad, None)), ctypes.byref(n)) == -2
+
+
+def test_corrector_tolerance_sizes_and_errors():
+    """corr_tol > 0 adds the per-(k, t') change buffer (and its maximum) to the workspace;
+    negative or non-finite tolerances, and a tolerance without corrector passes, are refused;
+    the adjoint needs the fixed-count corrector."""
+    from paper_2505_19467_amd import kbe
+    cfg = inputs.c2()
+    _, w0, _ = kbe.workspace_query(cfg)
+    _, w1, _ = kbe.workspace_query(cfg.replace(n_corr=4, corr_tol=1e-8))
+    need = cfg.nk * (((cfg.nt + 1 + 7) // 8) * 8) * 8
+    assert need <= w1 - w0 <= need + 1024
+    for bad in (cfg.replace(corr_tol=-1.0), cfg.replace(corr_tol=float("nan")), cfg.replace(corr_tol=float("inf")),
+                cfg.replace(n_corr=0, corr_tol=1e-8)):
+        with pytest.raises(kbe.KbeError):
+            kbe.workspace_query(bad)
+    n = ctypes.c_size_t()
+    tol = inputs.c4().replace(n_corr=1, corr_tol=1e-8)
+    assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(tol, None)), ctypes.byref(n)) == -2
+    assert kbe._lib.kbe_corrector_log(None, 0, 1, None, None) == -1

@@ -337,3 +337,52 @@ def test_two_time_symmetry_full_square(name, mods, n):
     assert asym < 1e-13, asym
     assert herm < 1e-14, herm
     assert lower < 1e-13, lower
+
+
+# ---------------------------------------------------------------- corrector stopping rule
+# Algorithm "prop": at most `max` corrector passes, stopping once the new row differs from
+# the previous iterate by at most epsilon (norm: largest modulus over the row, a reading).
+def test_corrector_tolerance_limits_reproduce_fixed_counts():
+    """epsilon = 0 never stops early: the run equals the fixed-count run with max passes, bit for
+    bit; an epsilon above every change stops after one pass: the fixed single-pass run."""
+    cfg = inputs.c1()
+    n = 40
+    fixed4 = O.run(cfg.replace(n_corr=4), n)["obs"]
+    obs0, passes0, ch0 = O.run_log(cfg.replace(n_corr=4, corr_tol=0.0), n)
+    assert np.array_equal(obs0, fixed4) and np.all(passes0[1:] == 4) and passes0[0] == 0
+    assert np.all(ch0 == -1.0)  # no change is measured in the fixed-count mode
+    fixed1 = O.run(cfg.replace(n_corr=1), n)["obs"]
+    obs_inf, passes_inf, ch_inf = O.run_log(cfg.replace(n_corr=4, corr_tol=1e30), n)
+    assert np.array_equal(obs_inf, fixed1) and np.all(passes_inf[1:] == 1)
+    assert np.all(ch_inf[:, 0] > 0) and np.all(ch_inf[:, 1:] == -1.0)
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9, 1e-12])
+def test_corrector_stops_at_first_small_change(tol):
+    """The passes of each step stop at the first change <= epsilon (earlier ones are larger),
+    and the corrector is a contraction: each pass changes the row far less than the one before."""
+    cfg = inputs.c1().replace(n_corr=6, corr_tol=tol)
+    obs, passes, ch = O.run_log(cfg, 60)
+    for m in range(1, 61):
+        p = passes[m]
+        assert 1 <= p <= cfg.n_corr
+        taken = ch[m - 1, :p]
+        assert np.all(taken > 0)
+        assert np.all(taken[:-1] > tol) and (taken[-1] <= tol or p == cfg.n_corr)
+        assert np.all(ch[m - 1, p:] == -1.0)
+        assert np.all(taken[1:] < 0.1 * taken[:-1])
+
+
+def test_corrector_tolerance_approaches_the_fixed_point():
+    """The converged corrector is the fixed point of the implicit (trapezoid-in-time) update:
+    runs with decreasing epsilon approach the run with many passes, each within ~epsilon."""
+    cfg = inputs.c1()
+    n = 50
+    ref = O.run(cfg.replace(n_corr=10), n)["obs"]
+    scale = np.abs(ref).max(axis=0) + 1e-300
+    errs = []
+    for tol in (1e-5, 1e-8, 1e-11):
+        obs, passes, _ = O.run_log(cfg.replace(n_corr=10, corr_tol=tol), n)
+        errs.append(np.max(np.abs(obs - ref) / scale))
+        assert errs[-1] < 1e3 * tol
+    assert errs[0] > errs[1] > errs[2]

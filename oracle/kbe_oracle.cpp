@@ -15,7 +15,8 @@
 //                       Peierls substitution k -> k - A(t) pol for the pulse
 //   self-energy ....... eq. (2BSE) (second Born), evaluated in real space
 //   collision integral  eq. (CI) in its Langreth "left" form, trapezoid rule
-//                       ("standard second order numerical integration")
+//                       ("standard second order numerical integration"), or Gregory end
+//                       corrections with more points per end (quad_points > 1)
 //   propagation ....... Algorithm "prop" (predictor, corrector passes -- a fixed
 //                       number, or up to that number until the row changes by at
 //                       most a tolerance -- and re-evaluation after the step) with an
@@ -37,6 +38,9 @@
 //                     paper's allind_kpk index map) and the Hubbard momentum convolution;
 //                     conserving pairing (sum_k tr[S^> G^< - S^< G^>] imaginary)
 //   collision_row ... exact on piecewise-linear integrands (trapezoid), zero at t = 0
+//   quadrature ...... Gregory weights: the classical 3- and 4-point values, exactness on
+//                     polynomials of the expected degree for every interval length, exact
+//                     collision rows on polynomial histories
 //   propagators ..... scipy expm of -i h dt and of the augmented phi_1 matrix
 //   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
 //   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
@@ -139,7 +143,7 @@ template <class R> inline Cx<R> imag_unit() { return Cx<R>(R(0.0), R(1.0)); }
 // ---------------------------------------------------------------- parameters
 // Mirrors OracleParams in oracle/oracle.py (ctypes); plain data.
 struct Params {
-  int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, pad_;
+  int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, quad_points;
   double dt, U, temp, filling, amp, omega, t0, width, polx, poly;
   double corr_tol;  // > 0: corrector passes stop once the row changes by at most this
 };
@@ -548,11 +552,79 @@ void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const 
 }
 
 // ---------------------------------------------------------------- collision integral
-// Trapezoid weight of node j on [0, p] (eq. (CI) with the paper's "standard second
-// order" rule): 1/2 at both ends, 1 inside, nothing on an empty interval.
-double trap(int j, int pend) {
-  if (pend <= 0) return 0.0;
-  return (j == 0 || j == pend) ? 0.5 : 1.0;
+// Quadrature weights of eq. (CI). The paper integrates with the "standard second order"
+// rule, the trapezoid; with quad_points = q > 1 the end weights carry Gregory corrections.
+// The trapezoid sum of a polynomial f on the nodes 0..N differs from its integral only by
+// end terms (Euler-Maclaurin): sum_j f(j) - int_0^N f = (f(0) + f(N))/2
+//   + sum_{k>=1} B_{2k}/(2k)! [f^{(2k-1)}(N) - f^{(2k-1)}(0)].
+// Corrections c_0..c_{q-1} on the first q nodes cancel the left end's terms for every
+// f of degree < q:  sum_{j<q} c_j j^d = -1/2 [d = 0] + [d odd] B_{d+1} / (d+1),  d = 0..q-1,
+// and the mirrored ones the right end's. On [0, N] node j gets
+//   w_j = 1 + c_j [j < q'] + c_{N-j} [N - j < q'],  q' = min(q, N + 1),
+// so short intervals use fewer points (q' = N + 1 gives the closed Newton-Cotes rule on all
+// nodes, q' = 1 the trapezoid, N = 0 the empty integral). q = 1 is the trapezoid rule.
+const int QUAD_MAX = 8;
+
+// Bernoulli numbers B_0..B_n from their recurrence sum_{k<=n} C(n+1, k) B_k = 0 (B_0 = 1).
+std::vector<double> bernoulli(int n) {
+  std::vector<double> B(n + 1, 0.0);
+  B[0] = 1.0;
+  for (int i = 1; i <= n; ++i) {
+    double s = 0.0, binom = 1.0;  // C(i + 1, k)
+    for (int k = 0; k < i; ++k) {
+      s += binom * B[k];
+      binom = binom * (i + 1 - k) / (k + 1);
+    }
+    B[i] = -s / (i + 1);
+  }
+  return B;
+}
+
+// c[q][j], q = 1..QUAD_MAX: the end corrections above, by Gaussian elimination with partial
+// pivoting on the q x q system.
+const std::vector<std::vector<double>>& gregory_corrections() {
+  static const std::vector<std::vector<double>> table = [] {
+    std::vector<std::vector<double>> c(QUAD_MAX + 1);
+    std::vector<double> B = bernoulli(QUAD_MAX + 1);
+    for (int q = 1; q <= QUAD_MAX; ++q) {
+      std::vector<double> A(q * q), b(q);
+      for (int d = 0; d < q; ++d) {
+        for (int j = 0; j < q; ++j) A[d * q + j] = std::pow((double)j, d);  // 0^0 = 1
+        b[d] = (d == 0 ? -0.5 : 0.0) + (d % 2 == 1 ? B[d + 1] / (d + 1) : 0.0);
+      }
+      for (int col = 0; col < q; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < q; ++r)
+          if (std::fabs(A[r * q + col]) > std::fabs(A[piv * q + col])) piv = r;
+        for (int j = 0; j < q; ++j) std::swap(A[col * q + j], A[piv * q + j]);
+        std::swap(b[col], b[piv]);
+        for (int r = col + 1; r < q; ++r) {
+          double f = A[r * q + col] / A[col * q + col];
+          for (int j = col; j < q; ++j) A[r * q + j] -= f * A[col * q + j];
+          b[r] -= f * b[col];
+        }
+      }
+      c[q].assign(q, 0.0);
+      for (int r = q - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < q; ++j) s -= A[r * q + j] * c[q][j];
+        c[q][r] = s / A[r * q + r];
+      }
+    }
+    return c;
+  }();
+  return table;
+}
+
+// Weight of node j on [0, N] (N = 0: the empty integral).
+double quad_weight(const Params& p, int j, int N) {
+  if (N <= 0) return 0.0;
+  int q = std::min<int>(std::max<int>(p.quad_points, 1), N + 1);
+  const std::vector<double>& c = gregory_corrections()[q];
+  double w = 1.0;
+  if (j < q) w += c[j];
+  if (N - j < q) w += c[N - j];
+  return w;
 }
 
 // Collision integrals of row m, eq. (CI), in the Langreth left form (reading of the
@@ -560,7 +632,7 @@ double trap(int j, int pend) {
 //   I^{<,>}(t_m, t') = int_0^{t_m} dtb Sigma^R(t_m, tb) G^{<,>}(tb, t')
 //                    + int_0^{t'}  dtb Sigma^{<,>}(t_m, tb) G^A(tb, t'),
 //   Sigma^R = Sigma^> - Sigma^< (tb < t_m),  G^A(tb,t') = -(G^> - G^<)(tb, t') (tb < t'),
-// on the grid with trapezoid weights, for t' = t_0 .. t_m.
+// on the grid with the weights of quad_weight (trapezoid by default), for t' = t_0 .. t_m.
 // hist(j, t', k) returns the stored block (j >= t'); blocks above the diagonal come from
 // G(j, t') = -[G(t', j)]^dag, unless full_square, when hist returns G(t_j, t') for any pair.
 template <class R, class Hist>
@@ -591,8 +663,8 @@ void collision_row(const Params& p, const Grid& g, int m, Hist hist, const Cx<R>
           SR[i] = S[nbb + i] - S[i];
           GR[i] = Gb[nbb + i] - Gb[i];
         }
-        double w1 = trap(j, m) * dt;
-        double w2 = (j <= tp) ? trap(j, tp) * dt : 0.0;
+        double w1 = quad_weight(p, j, m) * dt;
+        double w2 = (j <= tp) ? quad_weight(p, j, tp) * dt : 0.0;
         for (int c = 0; c < 2; ++c) {
           if (w1 != 0.0) {
             mm(nb, SR.data(), &Gb[c * nbb], tmp.data());
@@ -849,8 +921,8 @@ typedef Cx<double> C;
 // line from the lower). Both triangles feed each other's collision integrals and self-energies;
 // the diagonal follows the density matrix as in the plain scheme.
 
-// Right-form collision integrals of column m: IR[j] = I_R(t_j, t_m), j = 0..m, with trapezoid
-// weights; Gat(i, j, k) gives G(t_i, t_j) for any pair; sigcol[l] = Sigma(t_l, t_m).
+// Right-form collision integrals of column m: IR[j] = I_R(t_j, t_m), j = 0..m, with the
+// weights of quad_weight; Gat(i, j, k) gives G(t_i, t_j) for any pair; sigcol[l] = Sigma(t_l, t_m).
 template <class GA>
 void collision_col(const Params& p, const Grid& g, int m, GA Gat, const C* sigcol, C* IR) {
   int nb = g.nb, nbb = nb * nb, blk = 2 * nbb, nk = g.nk;
@@ -862,7 +934,7 @@ void collision_col(const Params& p, const Grid& g, int m, GA Gat, const C* sigco
       std::fill(acc.begin(), acc.end(), C());
       // int_0^{t_j} G^R(t_j, t_l) Sigma^{<,>}(t_l, t_m),  G^R = G^> - G^< (t_l < t_j)
       for (int l = 0; l <= j; ++l) {
-        double w = trap(l, j) * dt;
+        double w = quad_weight(p, l, j) * dt;
         if (w == 0.0) continue;
         const C* G = Gat(j, l, k);
         for (int i = 0; i < nbb; ++i) GR[i] = G[nbb + i] - G[i];
@@ -874,7 +946,7 @@ void collision_col(const Params& p, const Grid& g, int m, GA Gat, const C* sigco
       }
       // int_0^{t_m} G^{<,>}(t_j, t_l) Sigma^A(t_l, t_m),  Sigma^A = -(Sigma^> - Sigma^<) (t_l < t_m)
       for (int l = 0; l <= m; ++l) {
-        double w = trap(l, m) * dt;
+        double w = quad_weight(p, l, m) * dt;
         if (w == 0.0) continue;
         const C* G = Gat(j, l, k);
         const C* S = sigcol + ((size_t)l * nk + k) * blk;
@@ -1022,6 +1094,15 @@ void from_doubles(const double* src, size_t n, C* dst) {
 extern "C" {
 
 int oracle_nobs() { return NOBS; }
+
+// Quadrature weights of eq. (CI) on [0, N]: out[j] = weight of node j, j = 0..N.
+int oracle_quad_weights(int32_t quad_points, int32_t N, double* out) {
+  if (quad_points < 1 || quad_points > QUAD_MAX || N < 0 || !out) return -1;
+  Params p{};
+  p.quad_points = quad_points;
+  for (int j = 0; j <= N; ++j) out[j] = quad_weight(p, j, N);
+  return 0;
+}
 
 // Full propagation: nsteps steps from the initial state. obs: (nsteps+1) x NOBS.
 // final_row (optional): row nsteps, [t'][k][comp][a][b] complex (interleaved re/im).

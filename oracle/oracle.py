@@ -40,7 +40,7 @@ def build(force: bool = False) -> str:
 
 class OracleParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt", "pad_")] + \
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt", "quad_points")] + \
                [(n, ctypes.c_double) for n in
                 ("dt", "U", "temp", "filling", "amp", "omega", "t0", "width", "polx", "poly", "corr_tol")]
 
@@ -63,6 +63,7 @@ def lib():
         _lib.oracle_h0.argtypes = [P, dp, ctypes.c_double, dp]
         _lib.oracle_tlm_run.argtypes = [P, dp, ctypes.c_int32, dp, dp]
         _lib.oracle_run_log.argtypes = [P, dp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int32), dp]
+        _lib.oracle_quad_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, dp]
         _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
     return _lib
 
@@ -78,7 +79,7 @@ def params(cfg) -> OracleParams:
     pu = cfg.pulse
     return OracleParams(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg,
                         interaction=cfg.interaction, hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
-                        nt=cfg.nt, pad_=0, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling,
+                        nt=cfg.nt, quad_points=cfg.quad_points, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling,
                         amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
                         polx=pu.pol[0], poly=pu.pol[1], corr_tol=cfg.corr_tol)
 
@@ -112,6 +113,16 @@ def run(cfg, nsteps: int | None = None, history: bool = False):
             rows.append(hist[off:off + sz].reshape(j + 1, nk, 2, nb, nb))
             off += sz
         out["rows"] = rows
+    return out
+
+
+def quad_weights(quad_points: int, N: int) -> np.ndarray:
+    """Weights of the collision-integral quadrature on the nodes 0..N (trapezoid for
+    quad_points = 1, Gregory end corrections with quad_points nodes per end otherwise)."""
+    out = np.zeros(N + 1)
+    rc = lib().oracle_quad_weights(quad_points, N, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_quad_weights rejected quad_points={quad_points}, N={N}")
     return out
 
 

@@ -56,6 +56,8 @@ class Config:
     corr: int = 1                       # include the second-Born correlation self-energy
     n_corr: int = 1                     # corrector passes K per step (the maximum when corr_tol > 0)
     corr_tol: float = 0.0               # > 0: stop the corrector once the row changes by <= corr_tol
+    quad_points: int = 1                # collision-integral quadrature: 1 = trapezoid, q > 1 = Gregory
+                                        # end corrections on q nodes per end
     temp: float = 0.1
     filling: float = 0.5                # electrons per orbital per spin
     precision: int = PRECISION_FP64

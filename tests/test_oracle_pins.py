@@ -323,6 +323,8 @@ def test_tlm_matches_central_differences(cfg_name):
     ("c4", dict(nkx=3, nky=4, dt=0.05), 25),
     ("c1", dict(nkx=4, hf=0, n_corr=2), 20),
     ("c1", dict(nkx=5, interaction=inputs.INTERACTION_INTERBAND, hf=0), 20),
+    ("c1", dict(nkx=4, quad_points=3), 25),
+    ("c4", dict(nkx=3, nky=3, dt=0.05, quad_points=4), 20),
 ])
 def test_two_time_symmetry_full_square(name, mods, n):
     """G^{<,>}(t,t')^dag = -G^{<,>}(t',t): a full-square run propagates the upper triangle on
@@ -386,3 +388,75 @@ def test_corrector_tolerance_approaches_the_fixed_point():
         errs.append(np.max(np.abs(obs - ref) / scale))
         assert errs[-1] < 1e3 * tol
     assert errs[0] > errs[1] > errs[2]
+
+
+# ---------------------------------------------------------------- Gregory end corrections
+def _exact_degree(q, N):
+    """Highest polynomial degree the rule integrates exactly on [0, N]: q' = min(q, N + 1)
+    correction nodes per end give degree q' - 1, one more for odd q' (the symmetric rule
+    integrates the next odd power exactly)."""
+    qq = min(q, N + 1)
+    return qq if qq % 2 == 1 else qq - 1
+
+
+def test_gregory_weights_classical_values():
+    from fractions import Fraction
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "gregory_weights.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        q, *ws = line.split()
+        ref = np.array([float(Fraction(x)) for x in ws])
+        w = O.quad_weights(int(q), 40)
+        assert np.abs(w[:len(ref)] - ref).max() < 1e-14 and np.abs(w[::-1][:len(ref)] - ref).max() < 1e-14
+        assert np.all(w[len(ref):-len(ref)] == 1.0)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6])
+def test_gregory_weights_exact_on_polynomials(q):
+    """Every interval length N = 0..40: the weights integrate t^d exactly up to the expected
+    degree (N = 0: the empty integral) and fail at the next degree (N >= 2, the order is
+    not higher than claimed)."""
+    for N in range(0, 41):
+        w = O.quad_weights(q, N)
+        j = np.arange(N + 1, dtype=float)
+        D = _exact_degree(q, N)
+        for d in range(D + 1):
+            exact = N ** (d + 1) / (d + 1)
+            assert abs((w * j ** d).sum() - exact) <= 1e-11 * max(1.0, exact), (q, N, d)
+        if N >= 2 and D + 1 <= N + 1:
+            # the error at the next degree is an O(1) constant, far above the rounding level
+            exact = N ** (D + 2) / (D + 2)
+            assert abs((w * j ** (D + 1)).sum() - exact) > 1e-12 * max(1.0, exact), (q, N)
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5])
+def test_collision_gregory_exact_on_polynomials(q):
+    """G(t, s) = sum_ab A_ab t^a s^b with A_ab = -A_ba^dag (one polynomial on the whole square,
+    so the upper triangle -G(s,t)^dag continues it) and Sigma constant: with Gregory weights
+    both integrals of eq. (CI) are exact when the degree in the integration variable stays
+    within the rule's exact degree (intervals of at least q - 1 steps)."""
+    nk, nb, dt, m = 2, 2, 0.07, 12
+    D = _exact_degree(q, m)
+    rng = np.random.default_rng(40 + q)
+    cplx = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    dag = lambda x: np.conj(np.swapaxes(x, -1, -2))
+    A = cplx(D + 1, D + 1, nk, 2, nb, nb)
+    A = 0.5 * (A - dag(np.swapaxes(A, 0, 1)))      # A[a, b] = -A[b, a]^dag
+    G = lambda t, s: sum(A[a, b] * t ** a * s ** b for a in range(D + 1) for b in range(D + 1))
+    assert np.abs(G(0.3, 0.2) + dag(G(0.2, 0.3))).max() < 1e-14
+    rows = [np.array([G(j * dt, p * dt) for p in range(j + 1)]) for j in range(m + 1)]
+    S = cplx(nk, 2, nb, nb)
+    sig = np.array([S for _ in range(m + 1)])
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=nb, hop=np.zeros((3, nb, nb), complex), U=1.0,
+                        dt=dt, nt=m, quad_points=q)
+    I = O.collision_row(cfg, m, rows, sig)
+    tm, SR = m * dt, S[:, 1] - S[:, 0]
+    for tp in range(q - 1, m + 1):
+        s = tp * dt
+        F1 = sum(A[a, b] * s ** b * tm ** (a + 1) / (a + 1) for a in range(D + 1) for b in range(D + 1))
+        F2 = sum(A[a, b] * s ** (a + b + 1) / (a + 1) for a in range(D + 1) for b in range(D + 1))
+        for c in range(2):
+            ref = SR @ F1[:, c] - S[:, c] @ (F2[:, 1] - F2[:, 0])
+            assert np.abs(I[tp, :, c] - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max()), (q, tp, c)

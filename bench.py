@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
 # (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
 # once that code changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2687e10, "fetch_over_algorithmic": 1.0217,
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0216,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "a15608e463eb2158a06374a8fb4278c612016c21"}
+                    "source_sha1": "1bda2ff22bdb501f1128bf7506ded375a0c5ca9d"}
 
 
 def _kernel_source_sha1():
@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the run with the corrector's stopping rule (tolerance mode)")
+    ap.add_argument("--no-gregory", action="store_true",
+                    help="skip the run with Gregory end corrections of the collision-integral quadrature")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the plain copy/read bandwidth probe")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not record HIP events around the history-sum launches (for counter-collection runs)")
@@ -252,6 +254,30 @@ def main():
         torch.cuda.empty_cache()
         S = kbe.System(cfg)
 
+    gregory = None
+    if not args.no_gregory and args.workload == "c2":
+        # the same workload with the quadrature's higher-order end corrections (5 nodes per end)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        cq = cfg.replace(quad_points=5)
+        S, rq = run(cq)
+        oq = rq["obs"]
+        dev = {n: float(np.abs(oq[:, i] - obs[:, i]).max() / np.abs(obs[:, i]).max())
+               for n, i in {"n_band1": 14, "Jx": 6, "Etot": 5, "Ecorr": 3}.items()}
+        achq = rq["kbytes"] / (rq["kms"] * 1e-3) / 1e9 if rq["kms"] > 0 else None
+        gregory = {"value": K / rq["elapsed"], "unit": "steps/s", "quad_points": cq.quad_points,
+                   "history_sums_GBs": achq, "max_rel_dev_vs_trapezoid": dev,
+                   "N_drift": float(np.abs(oq[:, 1] - oq[0, 1]).max()),
+                   "energy_balance_max": float(np.abs(_energy_balance(oq, cq)).max()),
+                   "workload": f"{cq.name}: Gregory end corrections, {cq.quad_points} nodes per end, FP64"}
+        print(f"[bench] Gregory q={cq.quad_points}: {K} steps in {rq['elapsed']:.3f} s = {K / rq['elapsed']:.1f} "
+              f"steps/s; deviation from the trapezoid {max(dev.values()):.1e}", file=sys.stderr, flush=True)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        S = kbe.System(cfg)
+
     adj = None
     if not args.no_adjoint:
         S.close()
@@ -310,6 +336,7 @@ def main():
         "cpu_baseline": cpu,
         "fp32_form": fp32,
         "adaptive_corrector": adaptive,
+        "gregory": gregory,
         "adjoint": adj,
         "hbm_ceiling": ceiling,
         "checks": {"N_drift": n_drift, "energy_balance_max": e_bal, "finite": finite},

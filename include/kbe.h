@@ -83,6 +83,12 @@ typedef struct {
                            With corr_tol > 0 the most passes a step may take. */
   int32_t nt_max;       /* largest step index the buffers hold */
   int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
+  int32_t quad_points;  /* quadrature of eq. (CI): 0 or 1 = the trapezoid rule (the second-order
+                           quadrature of Sec. "Computational Kernels"); q = 2..6 = Gregory end corrections on q
+                           nodes per end of each interval [0, N]: node j weighs
+                           1 + c_j [j < q'] + c_{N-j} [N-j < q'], q' = min(q, N + 1), with the c
+                           cancelling the Euler-Maclaurin end terms of the trapezoid sum through
+                           polynomial degree q' - 1 (q' for odd q'). The adjoint needs q <= 1. */
   double dt, U, temp, filling; /* time step; interaction; initial temperature; electrons per orbital per spin */
   double corr_tol;      /* 0: every step runs n_corr corrector passes. > 0: the stopping rule of
                            Algorithm "prop" (its max and epsilon): after each pass the largest
@@ -180,9 +186,9 @@ enum {
   KBE_BUF_D_PREV = 5,   /* [k][nb^2]: D = I^<(t,t) + I^<(t,t)^dag */
   KBE_BUF_D_CUR = 6,
   KBE_BUF_PROP = 7,     /* [k][3][nb^2]: V = e^{-i hbar dt}, Vh = e^{-i hbar dt/2}, Phi = (V-1) hbar^{-1} */
-  KBE_BUF_COL0 = 8,     /* [k][C][Tp]: G(t_j, t_0) copy of history column 0 */
-  KBE_BUF_DIAG = 9,     /* [k][C][Tp]: G(t_j, t_j) copy of the history diagonal */
-  KBE_BUF_ROWS = 10,    /* [2][k][C][Tp]: FP64 copies of history rows m-1 and m, slot = row & 1 */
+  KBE_BUF_COL0 = 8,     /* [k][C][q][Tp]: G(t_j, t_i), i < q (q = max(quad_points, 1)): history columns 0..q-1 */
+  KBE_BUF_DIAG = 9,     /* [k][C][q][Tp]: G(t_j, t_{j-i}), i < q: the history diagonal band */
+  KBE_BUF_ROWS = 10,    /* [R][k][C][Tp]: FP64 copies of the last R = max(2, q) history rows, slot = row % R */
   KBE_NBUF = 11
 };
 /* Tp = 8 * ceil((nt_max + 1) / 8). Current device pointer and size of a sub-buffer (the

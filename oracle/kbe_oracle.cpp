@@ -14,8 +14,8 @@
 //   Hamiltonian ....... Sec. "Computational Kernels", eq. (Htotal)/(ham), with a
 //                       Peierls substitution k -> k - A(t) pol for the pulse
 //   self-energy ....... eq. (2BSE) (second Born), evaluated in real space
-//   collision integral  eq. (CI) in its Langreth "left" form, trapezoid rule
-//                       ("standard second order numerical integration"), or Gregory end
+//   collision integral  eq. (CI) in its Langreth "left" form, trapezoid rule (the
+//                       second-order quadrature the paper states), or Gregory end
 //                       corrections with more points per end (quad_points > 1)
 //   propagation ....... Algorithm "prop" (predictor, corrector passes -- a fixed
 //                       number, or up to that number until the row changes by at
@@ -552,8 +552,8 @@ void sigma_row(const Params& p, const Theta<R>& th, const Grid& g, int m, const 
 }
 
 // ---------------------------------------------------------------- collision integral
-// Quadrature weights of eq. (CI). The paper integrates with the "standard second order"
-// rule, the trapezoid; with quad_points = q > 1 the end weights carry Gregory corrections.
+// Quadrature weights of eq. (CI). The paper states a second-order rule, taken here as the
+// trapezoid; with quad_points = q > 1 the end weights carry Gregory corrections.
 // The trapezoid sum of a polynomial f on the nodes 0..N differs from its integral only by
 // end terms (Euler-Maclaurin): sum_j f(j) - int_0^N f = (f(0) + f(N))/2
 //   + sum_{k>=1} B_{2k}/(2k)! [f^{(2k-1)}(N) - f^{(2k-1)}(0)].

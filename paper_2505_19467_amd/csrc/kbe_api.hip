@@ -51,6 +51,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
   if (!(c->corr_tol >= 0.0) || !std::isfinite(c->corr_tol)) { *why = "corr_tol must be finite and >= 0"; return KBE_ERR_INVALID_ARG; }
   if (c->corr_tol > 0.0 && c->n_corr < 1) { *why = "corr_tol > 0 needs n_corr >= 1 (the most passes)"; return KBE_ERR_INVALID_ARG; }
+  if (c->quad_points < 0 || c->quad_points > kbe::KBE_QMAX) { *why = "quad_points must be 0..6 (0 or 1: trapezoid)"; return KBE_ERR_INVALID_ARG; }
   if (!(c->dt > 0.0) || !(c->temp > 0.0) || !std::isfinite(c->U) || c->spin_deg < 1 || c->spin_deg > 2) {
     *why = "dt and temp must be positive, U finite, spin_deg 1 or 2";
     return KBE_ERR_INVALID_ARG;
@@ -67,6 +68,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
   d.rps = c->nb == 4 ? 2 : 1;
   d.spb = c->nb <= 2 ? 2 : 1;
+  d.qp = c->quad_points > 1 ? c->quad_points : 1;
+  d.rring = d.qp > 2 ? d.qp : 2;
   d.N = c->nt_max + 1;
   d.P = kbe::strip_base((d.N + 63) / 64, d.N);
   const size_t cz = sizeof(cplx);
@@ -76,14 +79,15 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_IA] = sz[B_IB] = nk * d.C * d.Tp * cz;
   sz[B_RHOA] = sz[B_RHOB] = sz[B_DA] = sz[B_DB] = nk * d.nbb * cz;
   sz[B_PROP] = nk * 3 * d.nbb * cz;
-  sz[B_COL0] = sz[B_DIAG] = sz[B_COLSUM] = nk * d.C * d.Tp * cz;
+  sz[B_COLSUM] = nk * d.C * d.Tp * cz;
+  sz[B_COL0] = sz[B_DIAG] = nk * d.C * (size_t)d.qp * d.Tp * cz;  // qp columns / band offsets
   sz[B_ROWPART] = nk * (size_t)d.Smax * d.rps * d.nbb * d.Tp * cz;
   sz[B_HF] = d.nbb * cz;
   sz[B_HOP] = 3 * d.nbb * cz;
   sz[B_EIGW] = nk * d.nb * sizeof(double);
   sz[B_EIGU] = nk * d.nbb * cz;
   sz[B_MU] = sizeof(double);
-  sz[B_ROW64] = 2 * nk * d.C * d.Tp * cz;
+  sz[B_ROW64] = (size_t)d.rring * nk * d.C * d.Tp * cz;
   // corrector change per (k, t') and its maximum, only when the corrector stops on a tolerance
   sz[B_CHG] = c->corr_tol > 0.0 ? nk * d.Tp * sizeof(double) : 0;
   sz[B_CHGMAX] = c->corr_tol > 0.0 ? sizeof(double) : 0;
@@ -97,6 +101,54 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   L->hist_bytes = (size_t)nk * d.C * (size_t)d.P * (d.fp32 ? sizeof(float2) : cz);
   L->obs_bytes = (size_t)(c->nt_max + 1) * KBE_NOBS * sizeof(double);
   return KBE_OK;
+}
+
+// End corrections of the collision-integral quadrature for q = 1..qp nodes per end. The
+// trapezoid sum of a polynomial differs from its integral by end terms only
+// (Euler-Maclaurin); corrections c_0..c_{q-1} on the first q nodes cancel the left end's
+// terms for every polynomial of degree < q, i.e. for f = x^d the moments
+//   sum_{j<q} c_j j^d = -1/2 [d = 0] + [d odd] B_{d+1} / (d + 1),  d = 0..q-1,
+// with B_n the Bernoulli numbers (generating function x / (e^x - 1)). Solved here by
+// Gauss-Jordan elimination; q = 1 gives the trapezoid's -1/2.
+kbe::QuadW quad_corrections(int qp) {
+  kbe::QuadW Q{};
+  Q.q = qp;
+  // Bernoulli numbers from B_n = -1/(n+1) sum_{k<n} binom(n+1, k) B_k
+  double B[kbe::KBE_QMAX + 2] = {1.0};
+  for (int n = 1; n <= kbe::KBE_QMAX + 1; ++n) {
+    double acc = 0.0, binom = 1.0;
+    for (int k = 0; k < n; ++k) {
+      acc += binom * B[k];
+      binom *= (double)(n + 1 - k) / (double)(k + 1);
+    }
+    B[n] = -acc / (n + 1);
+  }
+  for (int q = 1; q <= qp; ++q) {
+    double M[kbe::KBE_QMAX][kbe::KBE_QMAX + 1];
+    for (int row = 0; row < q; ++row) {
+      double pw = 1.0;  // j^row, 0^0 = 1
+      for (int j = 0; j < q; ++j) {
+        pw = 1.0;
+        for (int e = 0; e < row; ++e) pw *= j;
+        M[row][j] = pw;
+      }
+      M[row][q] = (row == 0 ? -0.5 : 0.0) + (row % 2 == 1 ? B[row + 1] / (row + 1) : 0.0);
+    }
+    for (int col = 0; col < q; ++col) {
+      int best = col;
+      for (int r = col + 1; r < q; ++r)
+        if (std::fabs(M[r][col]) > std::fabs(M[best][col])) best = r;
+      if (best != col)
+        for (int x = 0; x <= q; ++x) std::swap(M[col][x], M[best][x]);
+      for (int r = 0; r < q; ++r) {
+        if (r == col) continue;
+        double f = M[r][col] / M[col][col];
+        for (int x = col; x <= q; ++x) M[r][x] -= f * M[col][x];
+      }
+    }
+    for (int j = 0; j < q; ++j) Q.c[q][j] = M[j][q] / M[j][j];
+  }
+  return Q;
 }
 
 double pulse_A(const kbe_pulse& p, double t) {
@@ -170,6 +222,7 @@ struct kbe_ctx {
   int adj_m;     // next step to reverse
   int adj_cur;   // role of the double-buffered adjoint rows
   bool frozen;   // working buffers overwritten by a reverse sweep
+  kbe::QuadW quad;  // end corrections of the collision-integral quadrature
   // corrector log (host): passes taken per step, and the row change after each pass
   std::vector<int32_t> passes;
   std::vector<double> changes;
@@ -201,6 +254,7 @@ struct kbe_ctx {
     a.obs = obs;
     a.commit = 1;
     a.chg = nullptr;
+    a.quad = quad;
     a.Ax = a.Ay = 0.0;
     a.polx = pulse.pol[0];
     a.poly = pulse.pol[1];
@@ -502,6 +556,7 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   c->adj_m = 0;
   c->adj_cur = 0;
   c->frozen = false;
+  c->quad = quad_corrections(c->L.d.qp);
   c->passes.assign((size_t)cfg->nt_max + 1, 0);
   c->changes.assign((size_t)(cfg->nt_max + 1) * (cfg->n_corr > 0 ? cfg->n_corr : 1), -1.0);
   const Dims& d = c->L.d;
@@ -698,15 +753,19 @@ int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
   std::string why;
   int rc = make_layout(cfg, &L, &why);
   if (rc) return rc;
-  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->corr_tol != 0.0 || cfg->nb > 2) return KBE_ERR_SHAPE;
+  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->corr_tol != 0.0 || cfg->quad_points > 1 || cfg->nb > 2)
+    return KBE_ERR_SHAPE;
   *adjoint_bytes = adj_layout(L, nullptr);
   return KBE_OK;
 }
 
 int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes) {
   if (!ctx || !d_adjoint) return KBE_ERR_INVALID_ARG;
-  if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->cfg.corr_tol != 0.0 || ctx->L.d.nb > 2)
-    return ctx->fail(KBE_ERR_SHAPE, "the adjoint needs precision KBE_FP64, a fixed n_corr = 1 (corr_tol = 0) and nb <= 2");
+  if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->cfg.corr_tol != 0.0 || ctx->L.d.qp > 1 ||
+      ctx->L.d.nb > 2)
+    return ctx->fail(KBE_ERR_SHAPE,
+                     "the adjoint needs precision KBE_FP64, a fixed n_corr = 1 (corr_tol = 0), the trapezoid rule "
+                     "(quad_points <= 1) and nb <= 2");
   if (ctx->adj_obs >= 0) return ctx->fail(KBE_ERR_STATE, "a reverse sweep is in progress");
   size_t need = adj_layout(ctx->L, ctx->adj_off);
   if (bytes < need) return ctx->fail(KBE_ERR_INVALID_ARG, "adjoint workspace smaller than kbe_adjoint_query");

@@ -88,6 +88,8 @@ struct Dims {
                    // components between two wavefronts (nb = 4), else 1
   int spb;         // 64-column strips per row-partial slot group: 2 when one history-sum block
                    // covers a pair of strips (nb <= 2), else 1
+  int qp;          // quadrature nodes per end carrying end corrections (1: trapezoid)
+  int rring;       // FP64 working rows kept (the last rring rows, max(2, qp))
   int64_t P;       // history elements per (k, component): one k occupies C * P elements
 };
 
@@ -107,9 +109,17 @@ __host__ __device__ __forceinline__ int64_t strip_lane_base(const Dims& d, int k
   return (int64_t)k * d.C * d.P + (int64_t)d.C * (strip_base(s, d.N) - 64 * 64 * (int64_t)s) +
          (d.fp32 ? 2 * lane : lane);
 }
-// FP64 working copy of history rows m-1 and m: [slot = row & 1][k][C][Tp].
+// FP64 working copies of the last rring history rows: [slot = row % rring][k][C][Tp].
 __host__ __device__ __forceinline__ int64_t row64_idx(const Dims& d, int row, int k, int c, int t) {
-  return (((int64_t)(row & 1) * d.nk + k) * d.C + c) * d.Tp + t;
+  return (((int64_t)(row % d.rring) * d.nk + k) * d.C + c) * d.Tp + t;
+}
+// FP64 copies of history columns 0..qp-1: element (row, col), col < qp, row >= col.
+__host__ __device__ __forceinline__ int64_t colq_idx(const Dims& d, int k, int c, int row, int col) {
+  return (((int64_t)k * d.C + c) * d.qp + col) * d.Tp + row;
+}
+// FP64 copies of the history diagonal band: element (row, row - off), off < qp, off <= row.
+__host__ __device__ __forceinline__ int64_t band_idx(const Dims& d, int k, int c, int row, int off) {
+  return (((int64_t)k * d.C + c) * d.qp + off) * d.Tp + row;
 }
 // Row-partial sums of the history sums: [k][slot][nb^2][Tp], slot = (strip / spb) * rps + half.
 __host__ __device__ __forceinline__ const cplx* rowpart_slot(const Dims& d, const cplx* rowpart, int k, int slot) {
@@ -121,6 +131,24 @@ __host__ __device__ __forceinline__ int64_t rowbuf_idx(const Dims& d, int k, int
 // Sigma row: [k][3][nb^2][Tp] with components 0: Sigma^<, 1: Sigma^>, 2: Sigma^> - Sigma^<.
 __host__ __device__ __forceinline__ int64_t sig_idx(const Dims& d, int k, int s, int e, int t) {
   return (((int64_t)k * 3 + s) * d.nbb + e) * d.Tp + t;
+}
+
+// ------------------------------------------------------------------ quadrature of eq. (CI)
+// End corrections of the collision-integral quadrature, filled on the host: with q nodes per
+// end, node j of [0, N] weighs 1 + c[q'][j] [j < q'] + c[q'][N - j] [N - j < q'],
+// q' = min(q, N + 1); q = 1 is the trapezoid rule (c[1][0] = -1/2), N = 0 the empty integral.
+constexpr int KBE_QMAX = 6;
+struct QuadW {
+  int q;
+  double c[KBE_QMAX + 1][KBE_QMAX];
+};
+__host__ __device__ __forceinline__ double quad_w(const QuadW& Q, int j, int N) {
+  if (N <= 0) return 0.0;
+  int qq = Q.q < N + 1 ? Q.q : N + 1;
+  double w = 1.0;
+  if (j < qq) w += Q.c[qq][j];
+  if (N - j < qq) w += Q.c[qq][N - j];
+  return w;
 }
 
 // ------------------------------------------------------------------ model

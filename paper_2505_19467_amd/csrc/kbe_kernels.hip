@@ -134,8 +134,8 @@ __global__ __launch_bounds__(64) void k_init_rho(Dims d, const double* __restric
         int c = sc * NBB + e;
         commit_store(d, hist, k, c, 0, 0, g[sc]);
         row64[row64_idx(d, 0, k, c, 0)] = g[sc];
-        col0[rowbuf_idx(d, k, c, 0)] = g[sc];
-        diag[rowbuf_idx(d, k, c, 0)] = g[sc];
+        col0[colq_idx(d, k, c, 0, 0)] = g[sc];
+        diag[band_idx(d, k, c, 0, 0)] = g[sc];
       }
     }
 }
@@ -317,12 +317,13 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
 
 // ------------------------------------------------------------------ equal-time collision
 // I^<(t_m, t_m) = dt sum_j a_j [Sigma^>_mj G^<_jm - Sigma^<_mj G^>_jm],  G_jm = -(G_mj)^dag
-// for j < m, a_j the trapezoid weights on [0, t_m]; I^>(t_m, t_m) is the same matrix (both
-// integrals of eq. (CI) run over [0, t_m] and combine term by term). One block per k.
+// for j < m, a_j the quadrature weights on [0, t_m] (trapezoid, or with Gregory end
+// corrections); I^>(t_m, t_m) is the same matrix (both integrals of eq. (CI) run over
+// [0, t_m] and combine term by term). One block per k.
 template <int NB>
 __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__ row64,
                                                 const cplx* __restrict__ sig, cplx* __restrict__ Icur,
-                                                cplx* __restrict__ Dcur, int m, double dt) {
+                                                cplx* __restrict__ Dcur, int m, double dt, QuadW Q) {
   constexpr int NBB = NB * NB;
   __shared__ cplx lds[NBB * 256];
   int k = blockIdx.x;
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
   mat_zero<NB>(acc);
   if (m > 0) {
     for (int j = threadIdx.x; j <= m; j += 256) {
-      double wgt = (j == 0 || j == m) ? 0.5 : 1.0;
+      double wgt = quad_w(Q, j, m);
       cplx Gl[NBB], Gg[NBB], Sl[NBB], Sg[NBB], t[NBB];
 #pragma unroll
       for (int e = 0; e < NBB; ++e) {
@@ -1233,7 +1234,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 //  PREDICT/CORRECT, t' < m: G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t').
 //  PREDICT/CORRECT, t' = m: rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag and the
 //   equal-time block G^< = i rho_m, G^> = -i (1 - rho_m).
-template <int NB, int MODE>
+// G_{j t'} (both components) for the end corrections of output t' < m: the diagonal from the
+// band copy; stored blocks j > t' from the ring of recent rows (row m: the current iterate) or
+// the column copies (j < qp); blocks above the diagonal as -G_{t' j}^dag from the column copies
+// (j < qp) or the band (t' - j < qp). Every node the corrections visit is one of these.
+template <int NB>
+__device__ __forceinline__ void end_block(const Dims& d, const cplx* __restrict__ row64, const cplx* __restrict__ colq,
+                                          const cplx* __restrict__ band, int k, int m, int j, int tp, cplx* G) {
+  constexpr int NBB = NB * NB, C = 2 * NBB;
+  if (j == tp) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) G[c] = band[band_idx(d, k, c, tp, 0)];
+  } else if (j > tp) {
+    if (j > m - d.rring) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) G[c] = row64[row64_idx(d, j, k, c, tp)];
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) G[c] = colq[colq_idx(d, k, c, j, tp)];
+    }
+  } else {
+#pragma unroll
+    for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          int cs = sc * NBB + b * NB + a;
+          cplx v = j < d.qp ? colq[colq_idx(d, k, cs, tp, j)] : band[band_idx(d, k, cs, tp, tp - j)];
+          G[sc * NBB + a * NB + b] = cneg(cconj(v));
+        }
+  }
+}
+
+template <int NB, int MODE, bool GREG>
 __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cplx* __restrict__ row64,
                                              const cplx* __restrict__ sig, const cplx* __restrict__ colsum,
                                              const cplx* __restrict__ rowpart, cplx* __restrict__ col0,
@@ -1241,7 +1275,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              cplx* __restrict__ Icur, const cplx* __restrict__ props,
                                              const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
                                              const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
-                                             double dt, int commit, double* __restrict__ chg) {
+                                             double dt, int commit, double* __restrict__ chg, QuadW Q) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   int k = blockIdx.y;
   int tp = blockIdx.x * 256 + threadIdx.x;
@@ -1267,60 +1301,113 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         In[NBB + e] = cadd(In[NBB + e], rs[e]);
       }
       // end-point terms
-      cplx SRmm[NBB], SRm0[NBB], Gm[C], G0[C];
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        SRmm[e] = sig[sig_idx(d, k, 2, e, m)];
-        SRm0[e] = sig[sig_idx(d, k, 2, e, 0)];
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) Gm[c] = row64[row64_idx(d, m, k, c, tp)];
-      if (tp == 0) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) G0[c] = col0[rowbuf_idx(d, k, c, 0)];
-      } else {
-#pragma unroll
-        for (int sc = 0; sc < 2; ++sc)
-#pragma unroll
-          for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-              G0[sc * NBB + a * NB + b] = cneg(cconj(col0[rowbuf_idx(d, k, sc * NBB + b * NB + a, tp)]));
-      }
       cplx E[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) E[c] = czero();
-#pragma unroll
-      for (int sc = 0; sc < 2; ++sc) {
-        cplx x1[NBB], x0[NBB];
-        mat_zero<NB>(x1);
-        mat_zero<NB>(x0);
-        mm_acc<NB>(x1, SRmm, Gm + sc * NBB);
-        mm_acc<NB>(x0, SRm0, G0 + sc * NBB);
-#pragma unroll
-        for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cscal(csub(x1[e], x0[e]), 0.5);
-      }
-      if (tp > 0) {
-        cplx GRtt[NBB], GR0t[NBB];
+      if constexpr (!GREG) {
+        // trapezoid: half weights at j = 0 and j = m (first integral), j = 0 and j = t' (second)
+        cplx SRmm[NBB], SRm0[NBB], Gm[C], G0[C];
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
-          GRtt[e] = csub(diag[rowbuf_idx(d, k, NBB + e, tp)], diag[rowbuf_idx(d, k, e, tp)]);
-          GR0t[e] = csub(G0[NBB + e], G0[e]);
+          SRmm[e] = sig[sig_idx(d, k, 2, e, m)];
+          SRm0[e] = sig[sig_idx(d, k, 2, e, 0)];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) Gm[c] = row64[row64_idx(d, m, k, c, tp)];
+        if (tp == 0) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) G0[c] = col0[colq_idx(d, k, c, 0, 0)];
+        } else {
+#pragma unroll
+          for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+                G0[sc * NBB + a * NB + b] = cneg(cconj(col0[colq_idx(d, k, sc * NBB + b * NB + a, tp, 0)]));
         }
 #pragma unroll
         for (int sc = 0; sc < 2; ++sc) {
-          cplx St[NBB], S0[NBB], y1[NBB], y0[NBB];
+          cplx x1[NBB], x0[NBB];
+          mat_zero<NB>(x1);
+          mat_zero<NB>(x0);
+          mm_acc<NB>(x1, SRmm, Gm + sc * NBB);
+          mm_acc<NB>(x0, SRm0, G0 + sc * NBB);
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cscal(csub(x1[e], x0[e]), 0.5);
+        }
+        if (tp > 0) {
+          cplx GRtt[NBB], GR0t[NBB];
 #pragma unroll
           for (int e = 0; e < NBB; ++e) {
-            St[e] = sig[sig_idx(d, k, sc, e, tp)];
-            S0[e] = sig[sig_idx(d, k, sc, e, 0)];
+            GRtt[e] = csub(diag[band_idx(d, k, NBB + e, tp, 0)], diag[band_idx(d, k, e, tp, 0)]);
+            GR0t[e] = csub(G0[NBB + e], G0[e]);
           }
-          mat_zero<NB>(y1);
-          mat_zero<NB>(y0);
-          mm_acc<NB>(y1, St, GRtt);
-          mm_acc<NB>(y0, S0, GR0t);
 #pragma unroll
-          for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(csub(y0[e], y1[e]), 0.5));
+          for (int sc = 0; sc < 2; ++sc) {
+            cplx St[NBB], S0[NBB], y1[NBB], y0[NBB];
+#pragma unroll
+            for (int e = 0; e < NBB; ++e) {
+              St[e] = sig[sig_idx(d, k, sc, e, tp)];
+              S0[e] = sig[sig_idx(d, k, sc, e, 0)];
+            }
+            mat_zero<NB>(y1);
+            mat_zero<NB>(y0);
+            mm_acc<NB>(y1, St, GRtt);
+            mm_acc<NB>(y0, S0, GR0t);
+#pragma unroll
+            for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(csub(y0[e], y1[e]), 0.5));
+          }
+        }
+      } else {
+        // Gregory end corrections (d.qp nodes per end): against the bulk's unit weights,
+        //   E = sum_j (w^(m)_j - [j < m]) SR_mj G_jt'  +  sum_{j <= t'} (w^(t')_j - [j < t']) Sigma_mj GA_jt',
+        // nonzero on the nodes j < q' and j > N - q' of each interval (q' = min(qp, N + 1)).
+        const int qm = d.qp < m + 1 ? d.qp : m + 1;
+        for (int r = 0; r < 2; ++r) {
+          int j0 = r == 0 ? 0 : (qm > m - qm + 1 ? qm : m - qm + 1);
+          int j1 = r == 0 ? qm : m + 1;
+          for (int j = j0; j < j1; ++j) {
+            double w = quad_w(Q, j, m) - (j < m ? 1.0 : 0.0);
+            if (w == 0.0) continue;
+            cplx G[C], SR[NBB];
+            end_block<NB>(d, row64, col0, diag, k, m, j, tp, G);
+#pragma unroll
+            for (int e = 0; e < NBB; ++e) SR[e] = sig[sig_idx(d, k, 2, e, j)];
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+              cplx x[NBB];
+              mat_zero<NB>(x);
+              mm_acc<NB>(x, SR, G + sc * NBB);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(x[e], w));
+            }
+          }
+        }
+        if (tp > 0) {
+          const int qt = d.qp < tp + 1 ? d.qp : tp + 1;
+          for (int r = 0; r < 2; ++r) {
+            int j0 = r == 0 ? 0 : (qt > tp - qt + 1 ? qt : tp - qt + 1);
+            int j1 = r == 0 ? qt : tp + 1;
+            for (int j = j0; j < j1; ++j) {
+              double w = quad_w(Q, j, tp) - (j < tp ? 1.0 : 0.0);
+              if (w == 0.0) continue;
+              cplx G[C], GA[NBB];
+              end_block<NB>(d, row64, col0, diag, k, m, j, tp, G);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) GA[e] = csub(G[e], G[NBB + e]);  // -(G^> - G^<)
+#pragma unroll
+              for (int sc = 0; sc < 2; ++sc) {
+                cplx S[NBB], x[NBB];
+#pragma unroll
+                for (int e = 0; e < NBB; ++e) S[e] = sig[sig_idx(d, k, sc, e, j)];
+                mat_zero<NB>(x);
+                mm_acc<NB>(x, S, GA);
+#pragma unroll
+                for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(x[e], w));
+              }
+            }
+          }
         }
       }
 #pragma unroll
@@ -1360,7 +1447,8 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
           row64[row64_idx(d, m, k, c, tp)] = g[e];
           if (commit) {
             commit_store(d, hist, k, c, m, tp, g[e]);
-            if (tp == 0) col0[rowbuf_idx(d, k, c, m)] = g[e];
+            if (tp < d.qp) col0[colq_idx(d, k, c, m, tp)] = g[e];
+            if (m - tp < d.qp) diag[band_idx(d, k, c, m, m - tp)] = g[e];
           }
         }
       }
@@ -1406,7 +1494,8 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
           row64[row64_idx(d, m, k, c, m)] = g[sc];
           if (commit) {
             commit_store(d, hist, k, c, m, m, g[sc]);
-            diag[rowbuf_idx(d, k, c, m)] = g[sc];
+            diag[band_idx(d, k, c, m, 0)] = g[sc];
+            if (m < d.qp) col0[colq_idx(d, k, c, m, m)] = g[sc];
           }
         }
       }
@@ -1546,7 +1635,8 @@ __global__ __launch_bounds__(256) void k_obs(Dims d, const cplx* __restrict__ ho
 }
 
 // ------------------------------------------------------------------ aux copies
-// Refresh the FP64 working copies from history rows 0..m: column 0, diagonal, rows m-1, m.
+// Refresh the FP64 working copies from history rows 0..m: columns 0..qp-1, the diagonal band
+// of width qp, and the ring of the last rring rows (m - rring + 1 .. m).
 template <int NB>
 __global__ void k_aux(Dims d, const void* __restrict__ hist, cplx* __restrict__ row64, cplx* __restrict__ col0,
                       cplx* __restrict__ diag, int m) {
@@ -1554,10 +1644,12 @@ __global__ void k_aux(Dims d, const void* __restrict__ hist, cplx* __restrict__ 
   int kc = blockIdx.y;
   if (j > m) return;
   int k = kc / d.C, c = kc - (kc / d.C) * d.C;
-  col0[rowbuf_idx(d, k, c, j)] = history_load(d, hist, k, c, j, 0);
-  diag[rowbuf_idx(d, k, c, j)] = history_load(d, hist, k, c, j, j);
-  row64[row64_idx(d, m, k, c, j)] = history_load(d, hist, k, c, m, j);
-  if (m >= 1 && j < m) row64[row64_idx(d, m - 1, k, c, j)] = history_load(d, hist, k, c, m - 1, j);
+  for (int q = 0; q < d.qp && q <= j; ++q) {
+    col0[colq_idx(d, k, c, j, q)] = history_load(d, hist, k, c, j, q);
+    diag[band_idx(d, k, c, j, q)] = history_load(d, hist, k, c, j, j - q);
+  }
+  for (int r = m; r >= 0 && r > m - d.rring; --r)
+    if (j <= r) row64[row64_idx(d, r, k, c, j)] = history_load(d, hist, k, c, r, j);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1598,7 +1690,7 @@ struct Launch {
   }
   static hipError_t diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     hipLaunchKernelGGL(k_diag_I<NB>, dim3(d.nk), dim3(256), 0, st, d, (const cplx*)a.row64, (const cplx*)a.sig,
-                       a.I_cur, a.D_cur, m, a.dt);
+                       a.I_cur, a.D_cur, m, a.dt, a.quad);
     return hipGetLastError();
   }
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
@@ -1634,13 +1726,23 @@ struct Launch {
 #define KBE_ROW_ARGS                                                                                      \
   d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \
-      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit, a.chg
-    if (mode == KBE_ROW_PREDICT)
-      hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
-    else if (mode == KBE_ROW_CORRECT)
-      hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
-    else
-      hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      (const cplx*)a.D_prev, (const cplx*)a.D_cur, m, a.dt, a.commit, a.chg, a.quad
+    // the trapezoid's end terms are a fixed handful; Gregory corrections loop over their nodes
+    if (d.qp > 1) {
+      if (mode == KBE_ROW_PREDICT)
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      else if (mode == KBE_ROW_CORRECT)
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      else
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+    } else {
+      if (mode == KBE_ROW_PREDICT)
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      else if (mode == KBE_ROW_CORRECT)
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      else
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+    }
 #undef KBE_ROW_ARGS
     return hipGetLastError();
   }

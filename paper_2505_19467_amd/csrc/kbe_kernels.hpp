@@ -42,6 +42,7 @@ struct LaunchArgs {
   double* obs;
   int commit;      // 0: the row kernel writes only the FP64 working row (recomputation)
   double* chg;     // if set, the corrector row kernel writes max |G_new - G_old| per (k, t') here ([k][Tp])
+  QuadW quad;      // quadrature weights of eq. (CI)
   double Ax, Ay;  // A(t) * pol for the launch at hand
   double polx, poly;  // pulse polarisation
   double dt, U, UU, temp, target, spin;

@@ -38,7 +38,8 @@ BUF_SIGMA, BUF_I_PREV, BUF_I_CUR, BUF_RHO_PREV, BUF_RHO_CUR, BUF_D_PREV, BUF_D_C
 
 class KbeConfig(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision")] + \
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt_max", "precision",
+                 "quad_points")] + \
                [(n, ctypes.c_double) for n in ("dt", "U", "temp", "filling", "corr_tol")]
 
 
@@ -90,6 +91,7 @@ def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
     return KbeConfig(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg, interaction=cfg.interaction,
                      hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
                      nt_max=cfg.nt if nt_max is None else nt_max, precision=cfg.precision,
+                     quad_points=cfg.quad_points,
                      dt=cfg.dt, corr_tol=cfg.corr_tol, U=cfg.U, temp=cfg.temp, filling=cfg.filling)
 
 
@@ -301,14 +303,19 @@ class System:
         self.history_blocks().index_copy_(1, self._row_index(j), src.reshape(self.nk, -1).contiguous())
 
     def row64(self, j: int) -> torch.Tensor:
-        """FP64 working copy of history row j (j = m-1 or m of the current step), as a
-        [t'][k][</>][a][b] tensor (copy)."""
+        """FP64 working copy of history row j (one of the last R = max(2, quad_points) rows of
+        the current step), as a [t'][k][</>][a][b] tensor (copy)."""
         nb = self.nb
-        r = self.buffer(BUF_ROWS).view(2, self.nk, self.C, self.Tp)[j & 1, :, :, :j + 1]
+        R = max(2, self.cfg.quad_points)
+        r = self.buffer(BUF_ROWS).view(R, self.nk, self.C, self.Tp)[j % R, :, :, :j + 1]
         return r.permute(2, 0, 1).reshape(j + 1, self.nk, 2, nb, nb).contiguous()
 
     def rowbuf(self, which: int) -> torch.Tensor:
-        """A [k][C][Tp] row buffer (I rows, COL0, DIAG) as a [t'][k][</>][a][b] view helper."""
+        """A [k][C][Tp] row buffer (I rows; COL0 and DIAG hold max(1, quad_points) of them per
+        component: column / band offset 0 is returned) as a [k][C][Tp] view."""
+        if which in (BUF_COL0, BUF_DIAG):
+            q = max(1, self.cfg.quad_points)
+            return self.buffer(which).view(self.nk, self.C, q, self.Tp)[:, :, 0, :]
         return self.buffer(which).view(self.nk, self.C, self.Tp)
 
     def sigma_planes(self) -> torch.Tensor:

@@ -21,6 +21,8 @@
 //                       number, or up to that number until the row changes by at
 //                       most a tolerance -- and re-evaluation after the step) with an
 //                       exponential-midpoint solve of eq. (Green)
+//   dipole pulse ...... eq. (dipole): E(t) = I delta(t - t0), d_k = 1, coupling bands 0 (v)
+//                       and 1 (c), integrated across the delta as the kick exp(-i I sigma_x)
 //
 // Conventions: G^<(t,t') = i<c^dag(t') c(t)>, G^>(t,t') = -i<c(t) c^dag(t')>;
 // G^{<,>}(t',t) = -[G^{<,>}(t,t')]^dag; rho(t) = -i G^<(t,t).
@@ -43,6 +45,8 @@
 //                     collision rows on polynomial histories
 //   propagators ..... scipy expm of -i h dt and of the augmented phi_1 matrix
 //   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
+//   dipole kick ..... U = 0 closed form with the kick (the order of the kick and the band
+//                     propagation, its phase and its step), exact N conservation
 //   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
 //                     dt-convergence ratio 4, TDHF limit vs RK4
 //   symmetry ........ full-square mode: the upper triangle propagated on its own with the
@@ -143,11 +147,12 @@ template <class R> inline Cx<R> imag_unit() { return Cx<R>(R(0.0), R(1.0)); }
 // ---------------------------------------------------------------- parameters
 // Mirrors OracleParams in oracle/oracle.py (ctypes); plain data.
 struct Params {
-  int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, quad_points;
+  int32_t nkx, nky, nb, spin_deg, interaction, hf, corr, n_corr, nt, quad_points, pulse_kind;
   double dt, U, temp, filling, amp, omega, t0, width, polx, poly;
   double corr_tol;  // > 0: corrector passes stop once the row changes by at most this
 };
 enum { INT_HUBBARD = 0, INT_INTERBAND = 1 };
+enum { PULSE_PEIERLS = 0, PULSE_DIPOLE_KICK = 1 };
 enum {
   OBS_T = 0, OBS_N, OBS_EKIN, OBS_EHF, OBS_ECORR, OBS_ETOT, OBS_JX, OBS_JY, OBS_A,
   OBS_NORB = 9, OBS_NBAND = 13, NOBS = 17
@@ -268,9 +273,11 @@ void matfun(int n, const Cx<R>* h, F f, Cx<R>* out) {
 }
 
 // ---------------------------------------------------------------- model
-// Pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2), along pol.
+// Pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2), along pol (the dipole pulse has
+// no vector potential).
 template <class R>
 R pulse_A(const Params& p, const Theta<R>& th, double t) {
+  if (p.pulse_kind == PULSE_DIPOLE_KICK) return R(0.0);
   double x = (t - p.t0) / p.width;
   return th.amp * sin(th.omega * t) * std::exp(-x * x);
 }
@@ -329,6 +336,24 @@ void hf_field(const Params& p, const Theta<R>& th, const Grid& g, const std::vec
     out[1] = scale(loc[1], -th.U);
     out[2] = scale(loc[2], -th.U);
   }
+}
+
+// The dipole pulse of eq. (dipole), E(t) = I delta(t - t0) with d_k = 1: H_ext(t) = E(t) X,
+// X the matrix with ones between band 0 (v) and band 1 (c). Across the delta the equation of
+// motion reduces to i dG/dt = E(t) X G, so G(t0+, t') = exp(-i I X) G(t0-, t') with
+// exp(-i I X) = cos(I) 1 - i sin(I) X. On the time grid the kick sits at the grid time
+// t_{m0} nearest t0 (m0 = floor(t0 / dt + 1/2)): slice m0 is taken before it, and the step
+// m0 -> m0 + 1 starts from the kicked state, i.e. its homogeneous propagator becomes V K.
+inline int kick_step(const Params& p) { return (int)std::floor(p.t0 / p.dt + 0.5) + 1; }
+template <class R>
+void kick_matrix(const Theta<R>& th, Cx<R>* K) {
+  using std::cos;
+  using std::sin;
+  R c = cos(th.amp), s = sin(th.amp);
+  K[0] = Cx<R>(c);
+  K[3] = Cx<R>(c);
+  K[1] = Cx<R>(R(0.0), -s);
+  K[2] = Cx<R>(R(0.0), -s);
 }
 
 // k-independent one-body term: the -U c_c^dag c_c term of eq. (ham) (interband only).
@@ -820,6 +845,12 @@ void update_row(State<R>& st, int m, bool corrector) {
     h0(p, g, st.hop.data(), k, Amid, h.data());
     for (int i = 0; i < nbb; ++i) h[i] += hf[i];
     propagators(nb, p.dt, h.data(), V.data(), Vh.data(), Phi.data());
+    if (p.pulse_kind == PULSE_DIPOLE_KICK && m == kick_step(p)) {
+      std::vector<C> K(nbb);
+      kick_matrix(st.th, K.data());
+      mm(nb, V.data(), K.data(), t1.data());
+      V = t1;
+    }
     for (int tp = 0; tp < m; ++tp) {
       const C* Ip = &st.I_prev[((size_t)tp * nk + k) * blk];
       for (int i = 0; i < blk; ++i)
@@ -1112,6 +1143,8 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
                double* hist, double* rho_out) {
   if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
   if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  if (p->pulse_kind != PULSE_PEIERLS && (p->pulse_kind != PULSE_DIPOLE_KICK || p->nb != 2 || !(p->t0 >= 0.0)))
+    return -1;
   Theta<double> th{p->amp, p->omega, p->U};
   State<double> st(*p, th, hop);
   init(st);
@@ -1139,6 +1172,8 @@ int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* o
                    double* changes) {
   if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
   if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  if (p->pulse_kind != PULSE_PEIERLS && (p->pulse_kind != PULSE_DIPOLE_KICK || p->nb != 2 || !(p->t0 >= 0.0)))
+    return -1;
   Theta<double> th{p->amp, p->omega, p->U};
   State<double> st(*p, th, hop);
   init(st);
@@ -1163,6 +1198,8 @@ int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* o
 int oracle_tlm_run(const Params* p, const double* hop, int32_t nsteps, double* obs, double* dobs) {
   if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
   if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
+  if (p->pulse_kind != PULSE_PEIERLS && (p->pulse_kind != PULSE_DIPOLE_KICK || p->nb != 2 || !(p->t0 >= 0.0)))
+    return -1;
   Theta<D3> th;
   th.amp = D3(p->amp);
   th.amp.d[0] = 1.0;
@@ -1274,7 +1311,7 @@ int oracle_h0(const Params* p, const double* hop, double A, double* out) {
 // i < j, out[1] = max |rho - rho^dag| over all steps' final rho, out[2] = max relative difference
 // of the lower triangle from the plain run's rows (which take the upper triangle as -G^dag).
 int oracle_full_square_check(const Params* p, const double* hop, int32_t nsteps, double* out) {
-  if (p->nt < nsteps) return -1;
+  if (p->nt < nsteps || p->pulse_kind != PULSE_PEIERLS) return -1;
   FullSquare fsq(*p, hop, nsteps);
   fsq.run();
   int nk = fsq.nk, nb = fsq.nb, nbb = fsq.nbb, blk = fsq.blk, n = nsteps;

@@ -40,7 +40,8 @@ def build(force: bool = False) -> str:
 
 class OracleParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt", "quad_points")] + \
+                ("nkx", "nky", "nb", "spin_deg", "interaction", "hf", "corr", "n_corr", "nt", "quad_points",
+                 "pulse_kind")] + \
                [(n, ctypes.c_double) for n in
                 ("dt", "U", "temp", "filling", "amp", "omega", "t0", "width", "polx", "poly", "corr_tol")]
 
@@ -79,7 +80,7 @@ def params(cfg) -> OracleParams:
     pu = cfg.pulse
     return OracleParams(nkx=cfg.nkx, nky=cfg.nky, nb=cfg.nb, spin_deg=cfg.spin_deg,
                         interaction=cfg.interaction, hf=cfg.hf, corr=cfg.corr, n_corr=cfg.n_corr,
-                        nt=cfg.nt, quad_points=cfg.quad_points, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling,
+                        nt=cfg.nt, quad_points=cfg.quad_points, pulse_kind=pu.kind, dt=cfg.dt, U=cfg.U, temp=cfg.temp, filling=cfg.filling,
                         amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
                         polx=pu.pol[0], poly=pu.pol[1], corr_tol=cfg.corr_tol)
 

@@ -12,7 +12,8 @@ variant with a Peierls pulse, see the design notes):
 * ``hop[0]`` is the on-site block T0, ``hop[1]`` the nearest-neighbour block
   along x, ``hop[2]`` along y (zero in 1D). All are complex nb x nb.
 * The pulse is A(t) = amp * sin(omega * t) * exp(-((t - t0) / width)**2) along
-  the unit vector ``pol``.
+  the unit vector ``pol`` (Peierls kind), or the dipole pulse of eq. (dipole),
+  E(t) = amp * delta(t - t0) between bands 0 and 1 with d_k = 1 (dipole-kick kind).
 """
 from __future__ import annotations
 
@@ -25,6 +26,9 @@ import numpy as np
 INTERACTION_HUBBARD = 0   # spin-degenerate, intra-orbital on-site U (opposite spin only)
 INTERACTION_INTERBAND = 1  # the paper's spinless two-band model, eq. (ham) / eq. (2BSE)
 
+PULSE_PEIERLS = 0      # vector potential A(t) in the Bloch Hamiltonian
+PULSE_DIPOLE_KICK = 1  # eq. (dipole): E(t) = amp * delta(t - t0), d_k = 1 (nb = 2)
+
 PRECISION_FP64 = 0
 PRECISION_FP32 = 1
 
@@ -36,6 +40,7 @@ class Pulse:
     t0: float = 2.0
     width: float = 1.0
     pol: tuple = (1.0, 0.0)
+    kind: int = PULSE_PEIERLS
 
 
 @dataclass
@@ -150,7 +155,23 @@ def c5(seed: int = 20250520) -> Config:
                   dt=0.015, nt=1600)
 
 
-WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+def paper_chain(nk: int = 1024, nt: int = 500) -> Config:
+    """The paper's model problem (Sec. "Computational Kernels"): a spinless two-band chain with
+    the band energies eps_v = -2(1 - cos k) - Eg/2 and eps_c = 2(1 - cos k) + Eg/2 (Eg = 1), the
+    interband interaction of eq. (ham) with its -U n_c term, and the dipole pulse of
+    eq. (dipole), E(t) = I delta(t - 0.5) with d_k = 1; n_k = 1024 and a 500-step history as in
+    the paper's timing runs. U = 1, I = 0.25, dt = 0.02 and T = 0.1 (valence band filled) are
+    not given by the paper."""
+    eg = 1.0
+    hop = np.zeros((3, 2, 2), complex)
+    hop[0] = np.diag([-2.0 - eg / 2, 2.0 + eg / 2])
+    hop[1] = np.diag([1.0, -1.0])
+    return Config(name=f"p1_chain{nk}_interband", nkx=nk, nky=1, nb=2, hop=hop, U=1.0, dt=0.02, nt=nt,
+                  pulse=Pulse(amp=0.25, omega=0.0, t0=0.5, width=1.0, pol=(1.0, 0.0), kind=PULSE_DIPOLE_KICK),
+                  spin_deg=1, interaction=INTERACTION_INTERBAND)
+
+
+WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "p1": paper_chain}
 
 
 # ----------------------------------------------------------------------------

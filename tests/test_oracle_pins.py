@@ -202,6 +202,66 @@ def test_free_propagation_closed_form():
     assert worst < 1e-13
 
 
+def _kick_closed_form_rows(cfg, rho0, m, kick_step):
+    """Rows of G^<, G^> at U = 0 with the dipole kick exp(-i I X) (X: ones between bands 0 and
+    1) at the start of step kick_step: the evolution operator is e^{-i h t_m} before it and
+    e^{-i h (t_m - t_{m0})} K e^{-i h t_{m0}} after it (m0 = kick_step - 1)."""
+    w, v = np.linalg.eigh(brute.h0_numpy(cfg.hop, cfg.nkx, cfg.nky, 0.0))
+    I = cfg.pulse.amp
+    K = np.cos(I) * np.eye(2) - 1j * np.sin(I) * np.array([[0, 1], [1, 0]])
+    m0 = kick_step - 1
+
+    def evo(n):
+        def e(s):
+            return np.einsum("kab,kb,kcb->kac", v, np.exp(-1j * w * s * cfg.dt), v.conj())
+        return e(n) if n <= m0 else e(n - m0) @ K @ e(m0)
+    Um = evo(m)
+    out = []
+    for j in range(m + 1):
+        Uj = evo(j)
+        gl = 1j * Um @ rho0 @ np.conj(np.swapaxes(Uj, -1, -2))
+        gg = -1j * Um @ (np.eye(2) - rho0) @ np.conj(np.swapaxes(Uj, -1, -2))
+        out.append((gl, gg))
+    return out
+
+
+@pytest.mark.parametrize("t0,kick_step", [(0.1, 6), (0.111, 7), (0.0, 1)])
+def test_dipole_kick_closed_form(t0, kick_step):
+    """eq. (dipole) at U = 0: the kick exp(-i I X) lands between slices m0 and m0 + 1, with
+    t_{m0} the grid time nearest t0, and acts on the left of the band propagation. A kick
+    applied after the step's propagation, with the opposite phase, with angle 2I, or one step
+    off fails this."""
+    cfg = inputs.paper_chain(nk=8, nt=40).replace(U=0.0, pulse=inputs.Pulse(
+        amp=0.7, omega=0.0, t0=t0, width=1.0, kind=inputs.PULSE_DIPOLE_KICK))
+    n = 30
+    r = O.run(cfg, n, history=True)
+    rho0, _ = O.initial_state(cfg)
+    worst = 0.0
+    for m in (kick_step - 1, kick_step, kick_step + 1, n):
+        if m < 1:
+            continue
+        ref = _kick_closed_form_rows(cfg, rho0, m, kick_step)
+        for j in range(m + 1):
+            worst = max(worst, np.abs(r["rows"][m][j, :, 0] - ref[j][0]).max(),
+                        np.abs(r["rows"][m][j, :, 1] - ref[j][1]).max())
+    assert worst < 1e-13
+    # the kick moves weight into the conduction band: sin(I)^2 of a filled valence state
+    nb1 = _obs(r, "n_band1")
+    assert nb1[kick_step - 1] < 1e-2 and abs(nb1[n] - nb1[kick_step - 1] - np.sin(0.7) ** 2 * (1 - 2 * nb1[0])) < 1e-12
+
+
+def test_paper_model_number_conservation():
+    """The paper's model (interband interaction with its -U n_c term, HF + second Born, dipole
+    kick): N(t) is conserved to rounding, before and after the kick."""
+    cfg = inputs.paper_chain(nk=8, nt=40)
+    r = O.run(cfg, 40)
+    N = _obs(r, "N")
+    assert abs(N[0] - 1.0) < 1e-12
+    assert np.abs(N - N[0]).max() < 1e-12
+    nb1 = _obs(r, "n_band1")
+    assert nb1[40] > 10 * nb1[0]
+
+
 def test_number_conservation_exact():
     """N(t) is conserved to rounding for any dt (conserving second Born + HF)."""
     for cfg in (inputs.c1().replace(nkx=8), inputs.c4().replace(nkx=4, nky=4)):

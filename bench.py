@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
 # (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
 # once that code changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0216,
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0215,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "1bda2ff22bdb501f1128bf7506ded375a0c5ca9d"}
+                    "source_sha1": "c92285d17a826b544d20b86505ac35799bbe54c8"}
 
 
 def _kernel_source_sha1():
@@ -98,6 +98,52 @@ def adjoint_leg(torch, inputs, kbe):
             "grad_amp_omega_U": [float(x) for x in g]}
 
 
+def paper_leg(torch, inputs, kbe, warmup: int, reps: int = 5):
+    """The paper's own workload (two-band chain, n_k = 1024, interband U, dipole kick, FP64):
+    steps 1..499 timed as a whole, then the step at n_t = 500 run stage by stage with its
+    self-energy slice and its collision integrals (history sums, end points, equal-time term)
+    timed on their own, as the paper reports its two components."""
+    cfg = inputs.paper_chain()
+    S = kbe.System(cfg)
+    if warmup:
+        S.step(min(warmup, cfg.nt - 1))
+        S.observables()
+    S.reset()
+    n = cfg.nt - 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(n)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m = cfg.nt
+    S.stage_propagators(m, 0)
+    S.stage_update(m, 0)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        best = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            fn(m)
+            torch.cuda.synchronize()
+            best.append(time.perf_counter() - a)
+        return 1e3 * float(np.median(best))
+    sig_ms = timed(S.stage_sigma)
+    ci_ms = timed(S.stage_collision)
+    obs = S.observables(0, n + 1)
+    S.close()
+    out = {"value": n / el, "unit": "steps/s", "steps": n,
+           "sigma_ms_at_nt500": sig_ms, "collision_ms_at_nt500": ci_ms,
+           "n_band1_final": float(obs[-1, 14]), "N_drift": float(np.abs(obs[:, 1] - obs[0, 1]).max()),
+           "paper_16_A100_s": {"sigma_cuda_fortran": 9.06, "collision_openacc": 7.83},
+           "workload": f"{cfg.name}: 1D two-band chain, n_k={cfg.nk}, interband U={cfg.U}, dipole kick "
+                       f"I={cfg.pulse.amp} at t={cfg.pulse.t0}, dt={cfg.dt}, K={cfg.n_corr}, FP64"}
+    print(f"[bench] paper workload: {n} steps in {el:.3f} s = {n / el:.1f} steps/s; at n_t = 500 the "
+          f"self-energy slice takes {sig_ms:.3f} ms and the collision integrals {ci_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def hbm_ceiling(torch, gib: float = 4.0, reps: int = 5):
     """Plain device-to-device copy (read + write) and a full-array sum (read) with torch's
     own kernels, as a measured ceiling beside the 8 TB/s peak."""
@@ -140,6 +186,8 @@ def main():
                     help="skip the run with the corrector's stopping rule (tolerance mode)")
     ap.add_argument("--no-gregory", action="store_true",
                     help="skip the run with Gregory end corrections of the collision-integral quadrature")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's own workload (two-band chain, n_k = 1024, 500 steps, per-phase times)")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the plain copy/read bandwidth probe")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="do not record HIP events around the history-sum launches (for counter-collection runs)")
@@ -278,6 +326,14 @@ def main():
         torch.cuda.empty_cache()
         S = kbe.System(cfg)
 
+    paper = None
+    if not args.no_paper and args.workload == "c2":
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        paper = paper_leg(torch, inputs, kbe, W)
+        S = kbe.System(cfg)
+
     adj = None
     if not args.no_adjoint:
         S.close()
@@ -337,6 +393,7 @@ def main():
         "fp32_form": fp32,
         "adaptive_corrector": adaptive,
         "gregory": gregory,
+        "paper_workload": paper,
         "adjoint": adj,
         "hbm_ceiling": ceiling,
         "checks": {"N_drift": n_drift, "energy_balance_max": e_bal, "finite": finite},

@@ -50,7 +50,10 @@ enum {
 /* Interaction presets (eq. (ham) and eq. (2BSE)). */
 enum {
   KBE_INT_HUBBARD = 0,   /* spin-degenerate, intra-orbital on-site U: Sigma_ab = U^2 G_ab G_ab G_ba */
-  KBE_INT_INTERBAND = 1  /* the paper's spinless two-band model (nb = 2): direct - exchange */
+  KBE_INT_INTERBAND = 1  /* the paper's spinless two-band model (nb = 2): direct - exchange, with the
+                            -U n_c one-body term of eq. (ham) and its Hartree-Fock field (U n_c on v,
+                            U n_v on c, -U rho_vc between them). The workspace then holds the
+                            real-space lines of the current row, (nt_max + 1) * 8 * N_k complex. */
 };
 
 enum { KBE_FP64 = 0, KBE_FP32 = 1 };
@@ -73,7 +76,8 @@ enum {
 
 /* Workload description (plain data; the caller keeps ownership). */
 typedef struct {
-  int32_t nkx, nky;     /* k grid; nky = 1 is a 1D chain. 1 <= nkx, nky <= 64, nkx*nky <= 1024 */
+  int32_t nkx, nky;     /* k grid; nky = 1 is a 1D chain of 1..1024 points, otherwise a 2D grid with
+                           nkx, nky <= 64 and nkx*nky <= 1024 */
   int32_t nb;           /* orbitals per spin, 1..4 (interband preset: 2) */
   int32_t spin_deg;     /* 1 or 2: prefactor s of the observables */
   int32_t interaction;  /* KBE_INT_* */
@@ -99,9 +103,20 @@ typedef struct {
                            passes taken. The adjoint needs corr_tol = 0. */
 } kbe_config;
 
-/* Peierls pulse A(t) = amp sin(omega t) exp(-((t - t0)/width)^2) along pol = (pol[0], pol[1]). */
+/* Pulse kinds. */
+enum {
+  KBE_PULSE_PEIERLS = 0,     /* A(t) = amp sin(omega t) exp(-((t - t0)/width)^2) along pol, entering the
+                                Bloch Hamiltonian as k -> k - A(t) pol */
+  KBE_PULSE_DIPOLE_KICK = 1  /* eq. (dipole): E(t) = amp delta(t - t0) coupling bands 0 and 1 with d_k = 1
+                                (nb = 2; omega, width, pol unused). Across the delta G(t0+, t') =
+                                K G(t0-, t'), K = cos(amp) 1 - i sin(amp) X (X: ones between bands 0 and
+                                1); the kick sits at the grid time t_{m0} nearest t0 (m0 = floor(t0/dt + 1/2)),
+                                so step m0 + 1 propagates with V K. No vector potential. */
+};
 typedef struct {
   double amp, omega, t0, width, pol[2];
+  int32_t kind;  /* KBE_PULSE_*; kbe_create returns KBE_ERR_INVALID_ARG for an unknown kind, or for a
+                    dipole kick with nb != 2, t0 < 0 or a non-finite amp / t0 */
 } kbe_pulse;
 
 typedef struct kbe_ctx kbe_ctx;
@@ -243,7 +258,8 @@ int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* 
  *   KBE_OBS_NBAND + b (band occupation in the eigenbasis of h0(k - A(T))).
  * Parameters theta = (pulse amp, pulse omega, U); the initial state does not depend on them.
  *
- * Requirements: precision KBE_FP64, n_corr = 1, nb <= 2, and T >= 1. The forward run keeps
+ * Requirements: precision KBE_FP64, n_corr = 1 with corr_tol = 0, quad_points <= 1, nb <= 2,
+ * the Hubbard preset, the Peierls pulse, nkx <= 64, and T >= 1 (KBE_ERR_SHAPE otherwise). The forward run keeps
  * nothing for the adjoint beyond its own history: every committed time slice is a checkpoint.
  * Reversing step m reads rho_{m-1} back from the history diagonal (G^< = i rho exactly) and
  * recomputes I(t_{m-1}, .) with D_{m-1}, the predictor row and the corrector's collision row

@@ -21,7 +21,7 @@ namespace {
 
 enum {
   B_SIGMA = 0, B_IA, B_IB, B_RHOA, B_RHOB, B_DA, B_DB, B_PROP, B_COL0, B_DIAG, B_COLSUM, B_ROWPART,
-  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_CHG, B_CHGMAX, B_COUNT
+  B_HF, B_HOP, B_EIGW, B_EIGU, B_MU, B_ROW64, B_CHG, B_CHGMAX, B_GR, B_COUNT
 };
 
 struct Layout {
@@ -34,19 +34,18 @@ struct Layout {
 int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   if (!c) { *why = "null config"; return KBE_ERR_INVALID_ARG; }
   if (c->nb < 1 || c->nb > 4) { *why = "nb must be 1..4"; return KBE_ERR_SHAPE; }
-  if (c->nkx < 1 || c->nky < 1 || c->nkx > 64 || c->nky > 64 || c->nkx * c->nky > 1024) {
-    *why = "k grid must satisfy 1 <= nkx, nky <= 64 and nkx * nky <= 1024";
-    return KBE_ERR_SHAPE;
-  }
-  if (4 * c->nkx * c->nky * 16 > 65536) {
-    *why = "k grid too large for the self-energy kernel's LDS tile (nkx * nky <= 1024)";
+  // a 1D chain (nky = 1) up to 1024 k-points, a 2D grid up to 64 per axis; N_k <= 1024 keeps the
+  // self-energy kernels' LDS tile (four lines and the roots of unity) within 82 KB
+  if (c->nkx < 1 || c->nky < 1 || c->nkx * c->nky > 1024 || (c->nky > 1 && (c->nkx > 64 || c->nky > 64))) {
+    *why = "k grid must be a chain of 1..1024 points (nky = 1) or a 2D grid with nkx, nky <= 64 and nkx * nky <= 1024";
     return KBE_ERR_SHAPE;
   }
   if (c->nt_max < 1 || c->nt_max > 8192) { *why = "nt_max must be 1..8192"; return KBE_ERR_SHAPE; }
-  if (c->interaction != KBE_INT_HUBBARD) {
-    *why = "only the Hubbard interaction preset is implemented on the GPU";
-    return KBE_ERR_SHAPE;
+  if (c->interaction != KBE_INT_HUBBARD && c->interaction != KBE_INT_INTERBAND) {
+    *why = "interaction must be KBE_INT_HUBBARD or KBE_INT_INTERBAND";
+    return KBE_ERR_INVALID_ARG;
   }
+  if (c->interaction == KBE_INT_INTERBAND && c->nb != 2) { *why = "the interband preset needs nb = 2"; return KBE_ERR_SHAPE; }
   if (c->precision != KBE_FP64 && c->precision != KBE_FP32) { *why = "precision must be KBE_FP64 or KBE_FP32"; return KBE_ERR_INVALID_ARG; }
   if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
   if (!(c->corr_tol >= 0.0) || !std::isfinite(c->corr_tol)) { *why = "corr_tol must be finite and >= 0"; return KBE_ERR_INVALID_ARG; }
@@ -91,6 +90,8 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   // corrector change per (k, t') and its maximum, only when the corrector stops on a tolerance
   sz[B_CHG] = c->corr_tol > 0.0 ? nk * d.Tp * sizeof(double) : 0;
   sz[B_CHGMAX] = c->corr_tol > 0.0 ? sizeof(double) : 0;
+  // interband self-energy: real-space lines of the current row, [t_j][comp][ab][R]
+  sz[B_GR] = c->interaction == KBE_INT_INTERBAND ? (size_t)d.Tp * 2 * d.nbb * nk * cz : 0;
   size_t off = 0;
   for (int i = 0; i < B_COUNT; ++i) {
     L->off[i] = off;
@@ -152,14 +153,14 @@ kbe::QuadW quad_corrections(int qp) {
 }
 
 double pulse_A(const kbe_pulse& p, double t) {
-  if (p.width <= 0.0) return 0.0;
+  if (p.kind != KBE_PULSE_PEIERLS || p.width <= 0.0) return 0.0;
   double x = (t - p.t0) / p.width;
   return p.amp * std::sin(p.omega * t) * std::exp(-x * x);
 }
 // dA/d(amp) and dA/d(omega) at t
 void pulse_dA(const kbe_pulse& p, double t, double* damp, double* domega) {
   *damp = *domega = 0.0;
-  if (p.width <= 0.0) return;
+  if (p.kind != KBE_PULSE_PEIERLS || p.width <= 0.0) return;
   double x = (t - p.t0) / p.width;
   double g = std::exp(-x * x);
   *damp = std::sin(p.omega * t) * g;
@@ -254,6 +255,10 @@ struct kbe_ctx {
     a.obs = obs;
     a.commit = 1;
     a.chg = nullptr;
+    a.gR = L.bytes[B_GR] ? buf<cplx>(B_GR) : nullptr;
+    a.kick = 0;
+    a.kick_c = 1.0;
+    a.kick_s = 0.0;
     a.quad = quad;
     a.Ax = a.Ay = 0.0;
     a.polx = pulse.pol[0];
@@ -308,8 +313,16 @@ struct kbe_ctx {
     if (!rc) rc = bulk_timed(a, m);
     return rc;
   }
+  // The dipole pulse E(t) = I delta(t - t0) of eq. (dipole) acts as the kick K = exp(-i I X) at the
+  // grid time t_{m0} nearest t0 (m0 = floor(t0 / dt + 1/2)): step m0 + 1 propagates with V K.
+  int kick_step() const { return (int)std::floor(pulse.t0 / cfg.dt + 0.5) + 1; }
   int props(LaunchArgs& a, int m, int mode) {
     set_A(a, (m - 0.5) * cfg.dt);
+    if (pulse.kind == KBE_PULSE_DIPOLE_KICK && m == kick_step()) {
+      a.kick = 1;
+      a.kick_c = std::cos(pulse.amp);
+      a.kick_s = std::sin(pulse.amp);
+    }
     int rc = check(kbe::launch_hf(L.d, a, mode == 0 ? 0.0 : 0.5, st), "mean-field launch");
     if (!rc) rc = check(kbe::launch_props(L.d, a, st), "propagator launch");
     return rc;
@@ -533,6 +546,13 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   c->cfg = *cfg;
   if (pulse) c->pulse = *pulse;
   else std::memset(&c->pulse, 0, sizeof(c->pulse));
+  const kbe_pulse& pu = c->pulse;
+  if ((pu.kind != KBE_PULSE_PEIERLS && pu.kind != KBE_PULSE_DIPOLE_KICK) ||
+      (pu.kind == KBE_PULSE_DIPOLE_KICK && (cfg->nb != 2 || !(pu.t0 >= 0.0) || !std::isfinite(pu.amp) ||
+                                            !std::isfinite(pu.t0)))) {
+    delete c;
+    return KBE_ERR_INVALID_ARG;
+  }
   std::string why;
   int rc = make_layout(cfg, &c->L, &why);
   if (rc) {
@@ -753,7 +773,8 @@ int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
   std::string why;
   int rc = make_layout(cfg, &L, &why);
   if (rc) return rc;
-  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->corr_tol != 0.0 || cfg->quad_points > 1 || cfg->nb > 2)
+  if (cfg->precision != KBE_FP64 || cfg->n_corr != 1 || cfg->corr_tol != 0.0 || cfg->quad_points > 1 || cfg->nb > 2 ||
+      cfg->interaction != KBE_INT_HUBBARD || cfg->nkx > 64)
     return KBE_ERR_SHAPE;
   *adjoint_bytes = adj_layout(L, nullptr);
   return KBE_OK;
@@ -762,10 +783,11 @@ int kbe_adjoint_query(const kbe_config* cfg, size_t* adjoint_bytes) {
 int kbe_adjoint_attach(kbe_ctx* ctx, void* d_adjoint, size_t bytes) {
   if (!ctx || !d_adjoint) return KBE_ERR_INVALID_ARG;
   if (ctx->cfg.precision != KBE_FP64 || ctx->cfg.n_corr != 1 || ctx->cfg.corr_tol != 0.0 || ctx->L.d.qp > 1 ||
-      ctx->L.d.nb > 2)
+      ctx->L.d.nb > 2 || ctx->cfg.interaction != KBE_INT_HUBBARD || ctx->pulse.kind != KBE_PULSE_PEIERLS ||
+      ctx->cfg.nkx > 64)
     return ctx->fail(KBE_ERR_SHAPE,
                      "the adjoint needs precision KBE_FP64, a fixed n_corr = 1 (corr_tol = 0), the trapezoid rule "
-                     "(quad_points <= 1) and nb <= 2");
+                     "(quad_points <= 1), nb <= 2, the Hubbard preset, the Peierls pulse and nkx <= 64");
   if (ctx->adj_obs >= 0) return ctx->fail(KBE_ERR_STATE, "a reverse sweep is in progress");
   size_t need = adj_layout(ctx->L, ctx->adj_off);
   if (bytes < need) return ctx->fail(KBE_ERR_INVALID_ARG, "adjoint workspace smaller than kbe_adjoint_query");

@@ -378,7 +378,8 @@ __host__ __device__ __forceinline__ int fft_split(int n) {
 // For n = n1 n2 (n1 = fft_split(n) > 1) in two Cooley-Tukey stages with p = n2 p1 + p2,
 // q = q1 + n1 q2: first the n1-point transforms over p1 with the twiddle w^{p2 q1} into the
 // scratch, then the n2-point transforms over p2 back into x; each output costs n1 + n2
-// multiply-adds instead of n. Horner chains in registers, roots from the LDS table tw.
+// multiply-adds instead of n. Horner chains in registers (8 outputs per item), roots from the
+// LDS table tw (n entries, fill_roots).
 // Every stage ends with a block barrier; the caller synchronises before the first.
 __device__ __forceinline__ void axis_dft(cplx* __restrict__ x0, cplx* __restrict__ x1, cplx* __restrict__ t0,
                                          cplx* __restrict__ t1, int n, int nlines, int line_mul, int stride,
@@ -407,28 +408,38 @@ __device__ __forceinline__ void axis_dft(cplx* __restrict__ x0, cplx* __restrict
     return;
   }
   const int n2 = n / n1;
-  // stage A: item = (array, line, p2), n1 outputs q1
-  int itemsA = 2 * nlines * n2;
+  constexpr int Q = 8;
+  // stage A: item = (array, line, p2, group of 8 q1): Horner chains over p1 read from LDS
+  const int groupsA = (n1 + Q - 1) / Q;
+  int itemsA = 2 * nlines * n2 * groupsA;
   for (int it = threadIdx.x; it < itemsA; it += blockDim.x) {
-    int arr = it / (nlines * n2);
-    int rem = it - arr * nlines * n2;
-    int line = rem / n2, p2 = rem - (rem / n2) * n2;
+    int arr = it / (nlines * n2 * groupsA);
+    int rem = it - arr * nlines * n2 * groupsA;
+    int line = rem / (n2 * groupsA);
+    rem -= line * n2 * groupsA;
+    int p2 = rem / groupsA, g = rem - (rem / groupsA) * groupsA;
     const cplx* x = (arr ? x1 : x0) + line * line_mul;
     cplx* t = (arr ? t1 : t0) + line * line_mul;
-    cplx v[8];
+    cplx z[Q], acc[Q];
 #pragma unroll
-    for (int p1 = 0; p1 < 8; ++p1) v[p1] = p1 < n1 ? x[(p1 * n2 + p2) * stride] : czero();
-    for (int q1 = 0; q1 < n1; ++q1) {
-      cplx r = root(tw, (n2 * q1) % n, sgn), acc = czero();
+    for (int r = 0; r < Q; ++r) {
+      int q1 = g * Q + r;
+      z[r] = root(tw, ((q1 < n1 ? q1 : 0) * n2) % n, sgn);
+      acc[r] = czero();
+    }
+    for (int p1 = n1 - 1; p1 >= 0; --p1) {
+      cplx v = x[(p1 * n2 + p2) * stride];
 #pragma unroll
-      for (int p1 = 7; p1 >= 0; --p1)
-        if (p1 < n1) acc = cadd(cmul(acc, r), v[p1]);
-      t[(q1 * n2 + p2) * stride] = cmul(acc, root(tw, (p2 * q1) % n, sgn));
+      for (int r = 0; r < Q; ++r) acc[r] = cadd(cmul(acc[r], z[r]), v);
+    }
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      int q1 = g * Q + r;
+      if (q1 < n1) t[(q1 * n2 + p2) * stride] = cmul(acc[r], root(tw, (p2 * q1) % n, sgn));
     }
   }
   __syncthreads();
   // stage B: item = (array, line, q1, group of 8 q2)
-  constexpr int Q = 8;
   const int groups = (n2 + Q - 1) / Q;
   int itemsB = 2 * nlines * n1 * groups;
   for (int it = threadIdx.x; it < itemsB; it += blockDim.x) {
@@ -532,7 +543,7 @@ __device__ __forceinline__ void axis_dft_ct(cplx* __restrict__ x0, cplx* __restr
 //   x(R) <- scale * sum_k e^{sgn 2 pi i (ix Rx / nx + iy Ry / ny)} x(k); y lines, then x lines.
 __device__ __forceinline__ void grid_dft(cplx* x0, cplx* x1, cplx* t0, cplx* t1, int nx, int ny, const cplx* twx,
                                          const cplx* twy, int sgn, double scale) {
-  axis_dft(x0, x1, t0, t1, ny, nx, ny, 1, twy, sgn, 1.0);
+  if (ny > 1) axis_dft(x0, x1, t0, t1, ny, nx, ny, 1, twy, sgn, 1.0);
   axis_dft(x0, x1, t0, t1, nx, ny, 1, ny, twx, sgn, scale);
 }
 // grid_dft for grid sizes fixed at compile time (NY = 1: a chain, only the x lines)

@@ -187,9 +187,11 @@ __global__ __launch_bounds__(256) void k_hf(Dims d, const cplx* __restrict__ rho
 // has exp(M) = [[V, dt phi1(-i hbar dt)], [0, 1]], so Phi = -i * (top-right block).
 // exp(M / 2^s) by a degree-16 Taylor polynomial (Horner), ||M / 2^s||_F <= 1/4, then s
 // squarings; the square before the last is exp(M/2), whose top-left block is Vh.
+// With kick = 1 (the step after a dipole kick, eq. (dipole)) V is returned as V K.
 template <int NB>
 __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ hop, const cplx* __restrict__ hf,
-                                               double Ax, double Ay, double dt, cplx* __restrict__ props) {
+                                               double Ax, double Ay, double dt, int kick, double kc, double ks,
+                                               cplx* __restrict__ props) {
   constexpr int N2 = 2 * NB, NN = N2 * N2, NBB = NB * NB;
   __shared__ cplx sX[4][NN], sE[4][NN];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -244,7 +246,12 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
   if (act && r < NB) {
     cplx* P = props + (int64_t)k * 3 * NBB;
     if (c < NB) {
-      P[r * NB + c] = e;              // V
+      cplx v = e;
+      if constexpr (NB == 2) {
+        if (kick)  // V K, K = kc 1 - i ks X: (V K)_rc = kc V_rc - i ks V_r,1-c
+          v = csub(cscal(e, kc), cmuli(cscal(sE[wv][r * N2 + (1 - c)], ks)));
+      }
+      P[r * NB + c] = v;              // V
       P[NBB + r * NB + c] = half;     // Vh
     } else {
       P[2 * NBB + r * NB + (c - NB)] = cneg(cmuli(e));  // Phi = -i * top-right
@@ -261,24 +268,26 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
 // Block-to-work mapping gives each XCD a contiguous range of t_j, so the cache lines of
 // row m that several t_j share stay in one L2. NX, NY > 0: the grid size is fixed at compile
 // time (unrolled transforms, 1.8x faster on 24 x 24); NX = NY = 0: any grid, sizes from d.
+// Dynamic LDS: four lines of N_k points and the nx + ny roots of unity.
 template <int NB, int NX, int NY>
 __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ row64, cplx* __restrict__ sig,
                                                int m, double UU, int corr) {
   constexpr int NBB = NB * NB;
   extern __shared__ cplx lds[];
-  __shared__ cplx twx[64], twy[64];
   const int nk = NX > 0 ? NX * NY : d.nk;
+  const int nx = NX > 0 ? NX : d.nkx, ny = NX > 0 ? NY : d.nky;
   cplx* gl = lds;
   cplx* gg = lds + nk;
   cplx* tl = lds + 2 * nk;
   cplx* tg = lds + 3 * nk;
+  cplx* twx = lds + 4 * nk;  // roots of unity, nx and ny entries
+  cplx* twy = twx + nx;
   int total = (m + 1) * NBB;
   int per = (total + 7) >> 3;
   int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (item >= total) return;
   int j = item / NBB, ab = item - (item / NBB) * NBB;
   int t = threadIdx.x;
-  const int nx = NX > 0 ? NX : d.nkx, ny = NX > 0 ? NY : d.nky;
   fill_roots(twx, nx);
   fill_roots(twy, ny);
   for (int k = t; k < nk; k += 256) {
@@ -312,6 +321,98 @@ __global__ __launch_bounds__(256) void k_sigma(Dims d, const cplx* __restrict__ 
     sig[sig_idx(d, o, 0, ab, j)] = al;
     sig[sig_idx(d, o, 1, ab, j)] = ag;
     sig[sig_idx(d, o, 2, ab, j)] = csub(ag, al);
+  }
+}
+
+// Interband preset (nb = 2, the paper's eq. (2BSE)): with jbar the other band,
+//   Sigma^<_ab(R) = -U^2 (-1)^(a+b) det g^<(R) conj(g^>_{abar bbar}(R)),  Sigma^> with < and > swapped,
+// (the direct minus the exchange term of eq. (2BSE): g_{abar bbar} g_ab - g_{a bbar} g_{abar b} is
+// (-1)^(a+b) det g; the backward line is -conj of the forward one, as for the Hubbard preset).
+// Each output needs all four orbital pairs of both components at R, so the transforms are split
+// around a real-space buffer gR[t_j][comp][ab][R]: k_sigma_fwd takes the lines of row m to R,
+// k_sigma_ib forms the products and takes them back to k. Both: one block per (t_j, ab), the
+// same XCD-aware mapping and LDS tile as k_sigma.
+__device__ __forceinline__ int64_t gr_idx(const Dims& d, int j, int comp, int ab, int R) {
+  return (((int64_t)j * 2 + comp) * 4 + ab) * d.nk + R;
+}
+template <int NX, int NY>
+__global__ __launch_bounds__(256) void k_sigma_fwd(Dims d, const cplx* __restrict__ row64, cplx* __restrict__ gR,
+                                                   int m) {
+  extern __shared__ cplx lds[];
+  const int nk = NX > 0 ? NX * NY : d.nk;
+  const int nx = NX > 0 ? NX : d.nkx, ny = NX > 0 ? NY : d.nky;
+  cplx* gl = lds;
+  cplx* gg = lds + nk;
+  cplx* tl = lds + 2 * nk;
+  cplx* tg = lds + 3 * nk;
+  cplx* twx = lds + 4 * nk;
+  cplx* twy = twx + nx;
+  int total = (m + 1) * 4;
+  int per = (total + 7) >> 3;
+  int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= total) return;
+  int j = item >> 2, ab = item & 3;
+  int t = threadIdx.x;
+  fill_roots(twx, nx);
+  fill_roots(twy, ny);
+  for (int k = t; k < nk; k += 256) {
+    gl[k] = row64[row64_idx(d, m, k, ab, j)];
+    gg[k] = row64[row64_idx(d, m, k, 4 + ab, j)];
+  }
+  __syncthreads();
+  if constexpr (NX > 0)
+    grid_dft_ct<NX, NY>(gl, gg, tl, tg, twx, twy, +1, 1.0 / nk);
+  else
+    grid_dft(gl, gg, tl, tg, nx, ny, twx, twy, +1, 1.0 / nk);
+  for (int o = t; o < nk; o += 256) {
+    gR[gr_idx(d, j, 0, ab, o)] = gl[o];
+    gR[gr_idx(d, j, 1, ab, o)] = gg[o];
+  }
+}
+template <int NX, int NY>
+__global__ __launch_bounds__(256) void k_sigma_ib(Dims d, const cplx* __restrict__ gR, cplx* __restrict__ sig,
+                                                  int m, double UU, int corr) {
+  extern __shared__ cplx lds[];
+  const int nk = NX > 0 ? NX * NY : d.nk;
+  const int nx = NX > 0 ? NX : d.nkx, ny = NX > 0 ? NY : d.nky;
+  cplx* sl = lds;
+  cplx* sg = lds + nk;
+  cplx* tl = lds + 2 * nk;
+  cplx* tg = lds + 3 * nk;
+  cplx* twx = lds + 4 * nk;
+  cplx* twy = twx + nx;
+  int total = (m + 1) * 4;
+  int per = (total + 7) >> 3;
+  int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= total) return;
+  int j = item >> 2, ab = item & 3;
+  int a = ab >> 1, b = ab & 1;
+  int cross = (1 - a) * 2 + (1 - b);                 // orbital pair (abar, bbar)
+  double pre = ((a + b) & 1) ? UU : -UU;             // -U^2 (-1)^(a+b)
+  int t = threadIdx.x;
+  fill_roots(twx, nx);
+  fill_roots(twy, ny);
+  for (int o = t; o < nk; o += 256) {
+    cplx l00 = gR[gr_idx(d, j, 0, 0, o)], l01 = gR[gr_idx(d, j, 0, 1, o)];
+    cplx l10 = gR[gr_idx(d, j, 0, 2, o)], l11 = gR[gr_idx(d, j, 0, 3, o)];
+    cplx g00 = gR[gr_idx(d, j, 1, 0, o)], g01 = gR[gr_idx(d, j, 1, 1, o)];
+    cplx g10 = gR[gr_idx(d, j, 1, 2, o)], g11 = gR[gr_idx(d, j, 1, 3, o)];
+    cplx dl = csub(cmul(l00, l11), cmul(l01, l10));
+    cplx dg = csub(cmul(g00, g11), cmul(g01, g10));
+    cplx lx = gR[gr_idx(d, j, 0, cross, o)], gx = gR[gr_idx(d, j, 1, cross, o)];
+    sl[o] = corr ? cscal(cmul(dl, cconj(gx)), pre) : czero();
+    sg[o] = corr ? cscal(cmul(dg, cconj(lx)), pre) : czero();
+  }
+  __syncthreads();
+  if constexpr (NX > 0)
+    grid_dft_ct<NX, NY>(sl, sg, tl, tg, twx, twy, -1, 1.0);
+  else
+    grid_dft(sl, sg, tl, tg, nx, ny, twx, twy, -1, 1.0);
+  for (int o = t; o < nk; o += 256) {
+    cplx vl = sl[o], vg = sg[o];
+    sig[sig_idx(d, o, 0, ab, j)] = vl;
+    sig[sig_idx(d, o, 1, ab, j)] = vg;
+    sig[sig_idx(d, o, 2, ab, j)] = csub(vg, vl);
   }
 }
 
@@ -1653,6 +1754,13 @@ __global__ void k_aux(Dims d, const void* __restrict__ hist, cplx* __restrict__ 
 }
 
 // ------------------------------------------------------------------ launchers
+// Dynamic LDS above 64 KB (the self-energy tile of a long chain: 82 KB at N_k = 1024) is asked
+// for explicitly; gfx950 gives a workgroup up to 160 KB.
+static hipError_t allow_lds(const void* kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int NB>
 struct Launch {
   static hipError_t init(const Dims& d, const LaunchArgs& a, hipStream_t st) {
@@ -1672,19 +1780,37 @@ struct Launch {
   }
   static hipError_t props(const Dims& d, const LaunchArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_props<NB>, dim3((d.nk + 3) / 4), dim3(256), 0, st, d, a.hop, (const cplx*)a.hfbuf,
-                       a.Ax, a.Ay, a.dt, a.props);
+                       a.Ax, a.Ay, a.dt, a.kick, a.kick_c, a.kick_s, a.props);
     return hipGetLastError();
   }
   static hipError_t sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     int total = (m + 1) * NB * NB;
     int per = (total + 7) / 8;
-    size_t shm = (size_t)(4 * d.nk) * sizeof(cplx);
+    size_t shm = (size_t)(4 * d.nk + d.nkx + d.nky) * sizeof(cplx);
+    if constexpr (NB == 2) {
+      if (a.interaction == KBE_DEV_INT_INTERBAND) {
+        auto fwd = k_sigma_fwd<0, 0>;
+        auto ib = k_sigma_ib<0, 0>;
+        if (d.nkx == 16 && d.nky == 1) {
+          fwd = k_sigma_fwd<16, 1>;
+          ib = k_sigma_ib<16, 1>;
+        }
+        hipError_t e = allow_lds((const void*)fwd, shm);
+        if (e == hipSuccess) e = allow_lds((const void*)ib, shm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fwd, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.row64, a.gR, m);
+        hipLaunchKernelGGL(ib, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.gR, a.sig, m, a.UU, a.corr);
+        return hipGetLastError();
+      }
+    }
     // grids of the standard workloads with compile-time transforms, any other grid at run time
     auto kern = k_sigma<NB, 0, 0>;
     if (d.nkx == 24 && d.nky == 24) kern = k_sigma<NB, 24, 24>;
     else if (d.nkx == 16 && d.nky == 16) kern = k_sigma<NB, 16, 16>;
     else if (d.nkx == 12 && d.nky == 12) kern = k_sigma<NB, 12, 12>;
     else if (d.nkx == 16 && d.nky == 1) kern = k_sigma<NB, 16, 1>;
+    hipError_t e = allow_lds((const void*)kern, shm);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(per * 8), dim3(256), shm, st, d, (const cplx*)a.row64, a.sig, m, a.UU, a.corr);
     return hipGetLastError();
   }

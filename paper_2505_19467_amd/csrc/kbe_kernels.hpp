@@ -42,8 +42,11 @@ struct LaunchArgs {
   double* obs;
   int commit;      // 0: the row kernel writes only the FP64 working row (recomputation)
   double* chg;     // if set, the corrector row kernel writes max |G_new - G_old| per (k, t') here ([k][Tp])
+  cplx* gR;        // interband self-energy: real-space lines of row m, [t_j][comp][ab][R] (else null)
   QuadW quad;      // quadrature weights of eq. (CI)
   double Ax, Ay;  // A(t) * pol for the launch at hand
+  int kick;       // 1: the propagators of this step carry the dipole kick, V -> V K
+  double kick_c, kick_s;  // K = kick_c 1 - i kick_s X (X: ones between bands 0 and 1)
   double polx, poly;  // pulse polarisation
   double dt, U, UU, temp, target, spin;
   int interaction, hf, corr;

@@ -45,7 +45,7 @@ class KbeConfig(ctypes.Structure):
 
 class KbePulse(ctypes.Structure):
     _fields_ = [("amp", ctypes.c_double), ("omega", ctypes.c_double), ("t0", ctypes.c_double),
-                ("width", ctypes.c_double), ("pol", ctypes.c_double * 2)]
+                ("width", ctypes.c_double), ("pol", ctypes.c_double * 2), ("kind", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -163,7 +163,7 @@ class System:
         hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
         pu = cfg.pulse
         p = KbePulse(amp=pu.amp, omega=pu.omega, t0=pu.t0, width=pu.width,
-                     pol=(ctypes.c_double * 2)(pu.pol[0], pu.pol[1]))
+                     pol=(ctypes.c_double * 2)(pu.pol[0], pu.pol[1]), kind=pu.kind)
         ctx = _vp()
         nbytes = lambda t: t.numel() * t.element_size()  # noqa: E731
         rc = _lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(p),

@@ -143,3 +143,39 @@ def test_corrector_tolerance_sizes_and_errors():
     tol = inputs.c4().replace(n_corr=1, corr_tol=1e-8)
     assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(tol, None)), ctypes.byref(n)) == -2
     assert kbe._lib.kbe_corrector_log(None, 0, 1, None, None) == -1
+
+
+def test_interband_chain_and_pulse_validation():
+    """The interband preset needs nb = 2 and adds the real-space lines of the current row to the
+    workspace; chains of up to 1024 points are accepted, 2D grids up to 64 per axis; an unknown
+    pulse kind, or a dipole kick with nb != 2 or t0 < 0, is refused before anything touches the
+    device; the adjoint refuses the interband preset and chains longer than 64."""
+    from paper_2505_19467_amd import kbe
+    import numpy as np
+    p1 = inputs.paper_chain()
+    _, wb, _ = kbe.workspace_query(p1)
+    _, wb_h, _ = kbe.workspace_query(p1.replace(interaction=inputs.INTERACTION_HUBBARD))
+    Tp = ((p1.nt + 1 + 7) // 8) * 8
+    need = Tp * 8 * p1.nk * 16
+    assert need <= wb - wb_h <= need + 1024
+    for bad in (p1.replace(nkx=1025), inputs.c2().replace(nkx=65), inputs.c2().replace(nkx=40, nky=40),
+                inputs.c5().replace(interaction=inputs.INTERACTION_INTERBAND)):
+        with pytest.raises(kbe.KbeError):
+            kbe.workspace_query(bad)
+    n = ctypes.c_size_t()
+    for bad in (p1.replace(nkx=16, pulse=inputs.Pulse()), inputs.c1().replace(nkx=128)):
+        assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(bad, None)), ctypes.byref(n)) == -2
+    assert kbe._lib.kbe_adjoint_query(ctypes.byref(kbe._c_config(inputs.c1().replace(nkx=64), None)),
+                                      ctypes.byref(n)) == 0
+    # pulse checks come before any buffer is used: fake device pointers are never dereferenced
+    fake = ctypes.c_void_p(0x100000)
+    for cfg, kind, t0 in ((p1.replace(nkx=16, nt=20), 2, 0.5), (p1.replace(nkx=16, nt=20), 1, -0.1),
+                          (inputs.c5().replace(nkx=2, nky=2, nt=8), 1, 0.5)):
+        c = kbe._c_config(cfg, None)
+        hb, wb, ob = kbe._query(c)
+        hop = np.ascontiguousarray(cfg.hop, np.complex128).view(np.float64)
+        pu = kbe.KbePulse(amp=0.3, omega=0.0, t0=t0, width=1.0, pol=(ctypes.c_double * 2)(1.0, 0.0), kind=kind)
+        ctx = ctypes.c_void_p()
+        rc = kbe._lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 ctypes.byref(pu), fake, hb, fake, wb, fake, ob, None, ctypes.byref(ctx))
+        assert rc == -1 and not ctx.value

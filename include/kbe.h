@@ -218,6 +218,13 @@ int kbe_stage_propagators(kbe_ctx* ctx, int32_t m, int32_t mode);
  * batched k <-> R transforms and pointwise products, into KBE_BUF_SIGMA. */
 int kbe_stage_sigma(kbe_ctx* ctx, int32_t m);
 
+/* Self-energy as the paper evaluates it (eq. (2BSE) with eq. (polarizability)/(kernel2) for the
+ * direct term, O(n_k^2), and the nested momentum sums of Alg. "contraction2" for the exchange
+ * term, O(n_k^3) per time pair): the same output as kbe_stage_sigma, into KBE_BUF_SIGMA, for
+ * timing the paper's algorithm. Interband preset on a chain with nkx divisible by 8
+ * (KBE_ERR_SHAPE otherwise). At n_k = 1024 one call takes about a second per 500 time pairs. */
+int kbe_stage_sigma_direct(kbe_ctx* ctx, int32_t m);
+
 /* Collision integrals: I^{<,>}(t_m, t'), t' = 0..m (eq. (CI), Langreth left form,
  * trapezoid weights) from history rows 0..m, KBE_BUF_SIGMA, COL0 and DIAG, into
  * KBE_BUF_I_CUR; D_m into KBE_BUF_D_CUR. */

@@ -699,6 +699,16 @@ int kbe_stage_sigma(kbe_ctx* ctx, int32_t m) {
   return ctx->check(kbe::launch_sigma(ctx->L.d, a, m, ctx->st), "self-energy launch");
 }
 
+int kbe_stage_sigma_direct(kbe_ctx* ctx, int32_t m) {
+  int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  const kbe_config& c = ctx->cfg;
+  if (c.interaction != KBE_INT_INTERBAND || c.nky != 1 || c.nkx % 8 != 0)
+    return ctx->fail(KBE_ERR_SHAPE, "the direct-sum self-energy needs the interband preset on a chain of 8j points");
+  LaunchArgs a = ctx->args();
+  return ctx->check(kbe::launch_sigma_direct(ctx->L.d, a, m, ctx->st), "direct self-energy launch");
+}
+
 int kbe_stage_collision(kbe_ctx* ctx, int32_t m) {
   int rc = check_m(ctx, m, 0);
   if (rc) return rc;

@@ -416,6 +416,136 @@ __global__ __launch_bounds__(256) void k_sigma_ib(Dims d, const cplx* __restrict
   }
 }
 
+// The paper's own evaluation of eq. (2BSE) for the interband preset on a chain (n divisible by
+// 8): the direct term through the polarizability of eq. (polarizability)/(kernel2), O(n^2) per
+// (t_j, jm), and the exchange term by the nested momentum sums of Alg. "contraction2",
+// O(n^3) per (t_j, jm); kept beside the transform route to time the paper's algorithm on this
+// hardware (same output). Momenta on the -pi-offset grid of eq. (kj): k_a + k_b has index
+// a + b - n/2 and k_a - k_b index a - b + n/2 (mod n), so k' + q - k has index k' + q - k.
+// One block per (t_j, jm) of row m, both components in turn; 512 threads in 4 groups that split
+// the q range (8 waves per CU: the 96 KB of LDS leave room for one block). In a group thread i
+// owns the KD = 8 outputs k = 8i .. 8i+7 (n <= 1024) and slides a window of KD backward-line
+// values along k', so one LDS read feeds KD complex multiply-adds; neighbouring lanes then read
+// the backward line 8 elements apart, so it is stored with one pad element after every 8 (lane
+// stride 36 banks). The groups' partial sums are added in LDS in a fixed order.
+// Dynamic LDS: the four forward lines of the component, P, the padded backward line:
+// 6n + n/8 complex.
+constexpr int KD = 8, DG = 4;
+__device__ __forceinline__ int wrap_n(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+__device__ __forceinline__ int padded(int x) { return x + (x >> 3); }
+__global__ __launch_bounds__(512) void k_sigma_direct(Dims d, const cplx* __restrict__ row64, cplx* __restrict__ sig,
+                                                      int m, double UU, int corr) {
+  extern __shared__ cplx lds[];
+  const int n = d.nk, h = n / 2;
+  cplx* Ajm = lds;           // G^s_{j m}     (t_m, t_j)
+  cplx* Abb = lds + n;       // G^s_{jb mb}
+  cplx* Ajb = lds + 2 * n;   // G^s_{j mb}
+  cplx* Abm = lds + 3 * n;   // G^s_{jb m}
+  cplx* P = lds + 4 * n;
+  cplx* Bk = lds + 5 * n;    // G^{s'}_{mb jb}(k; t_j, t_m) = -conj(G^{s'}_{jb mb}(k; t_m, t_j)), padded
+  int item = blockIdx.x;     // (t_j, jm)
+  int j = item >> 2, ab = item & 3;
+  int a = ab >> 1, b = ab & 1, ja = 1 - a, mb = 1 - b;
+  int t = threadIdx.x;
+  int g = t >> 7, k0 = (t & 127) * KD;
+  int q0 = g * (n / DG), q1 = q0 + n / DG;
+  cplx outv[2][KD];
+  const double pre = UU / ((double)n * (double)n);
+  for (int s = 0; s < 2; ++s) {
+    __syncthreads();
+    for (int k = t; k < n; k += 512) {
+      Ajm[k] = row64[row64_idx(d, m, k, s * 4 + a * 2 + b, j)];
+      Abb[k] = row64[row64_idx(d, m, k, s * 4 + ja * 2 + mb, j)];
+      Ajb[k] = row64[row64_idx(d, m, k, s * 4 + a * 2 + mb, j)];
+      Abm[k] = row64[row64_idx(d, m, k, s * 4 + ja * 2 + b, j)];
+      Bk[padded(k)] = cneg(cconj(row64[row64_idx(d, m, k, (1 - s) * 4 + ja * 2 + mb, j)]));
+    }
+    __syncthreads();
+    // polarizability P(q) = sum_k' G_{jb mb}(k' + q) G_{mb jb}(k'; t_j, t_m)
+    for (int q = t; q < n; q += 512) {
+      cplx acc = czero();
+      int idx = wrap_n(q - h, n);
+      for (int kp = 0; kp < n; ++kp) {
+        cmac(acc, Abb[idx], Bk[padded(kp)]);
+        idx = idx + 1 == n ? 0 : idx + 1;
+      }
+      P[q] = acc;
+    }
+    __syncthreads();
+    cplx part[KD];
+#pragma unroll
+    for (int r = 0; r < KD; ++r) part[r] = czero();
+    if (k0 < n) {
+      cplx dir[KD], ex[KD];
+#pragma unroll
+      for (int r = 0; r < KD; ++r) dir[r] = ex[r] = czero();
+      // direct: sum_q G_{jm}(k - q) P(q), this group's q
+      for (int q = q0; q < q1; ++q) {
+        cplx pq = P[q];
+#pragma unroll
+        for (int r = 0; r < KD; ++r)
+          if (k0 + r < n) cmac(dir[r], Ajm[wrap_n(k0 + r - q + h, n)], pq);
+      }
+      // exchange: sum_q G_{jb m}(q) sum_k' G_{j mb}(k') G_{mb jb}(k' + q - k; t_j, t_m)
+      for (int q = q0; q < q1; ++q) {
+        cplx acc[KD], w[KD];
+        int base = q - k0;  // window element r at k' is Bk[k' + base - r]
+#pragma unroll
+        for (int r = 0; r < KD; ++r) {
+          acc[r] = czero();
+          w[r] = Bk[padded(wrap_n(base - r, n))];
+        }
+        int idx = wrap_n(base, n);
+        for (int kp = 0; kp < n; kp += KD) {  // unrolled by the window length: the shifts are renames
+#pragma unroll
+          for (int u = 0; u < KD; ++u) {
+            cplx av = Ajb[kp + u];
+#pragma unroll
+            for (int r = 0; r < KD; ++r) cmac(acc[r], av, w[r]);
+#pragma unroll
+            for (int r = KD - 1; r > 0; --r) w[r] = w[r - 1];
+            idx = idx + 1 == n ? 0 : idx + 1;
+            w[0] = Bk[padded(idx)];
+          }
+        }
+        cplx cq = Abm[q];
+#pragma unroll
+        for (int r = 0; r < KD; ++r) cmac(ex[r], cq, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < KD; ++r) part[r] = csub(dir[r], ex[r]);
+    }
+    // add the 4 groups' partial sums (in the forward-line area, no longer read)
+    __syncthreads();
+    if (k0 < n) {
+#pragma unroll
+      for (int r = 0; r < KD; ++r)
+        if (k0 + r < n) lds[g * n + k0 + r] = part[r];
+    }
+    __syncthreads();
+    if (g == 0 && k0 < n) {
+#pragma unroll
+      for (int r = 0; r < KD; ++r) {
+        int k = k0 + r;
+        cplx v = czero();
+        if (k < n) v = cadd(cadd(lds[k], lds[n + k]), cadd(lds[2 * n + k], lds[3 * n + k]));
+        outv[s][r] = corr ? cscal(v, pre) : czero();
+      }
+    }
+  }
+  if (g == 0 && k0 < n) {
+#pragma unroll
+    for (int r = 0; r < KD; ++r) {
+      int k = k0 + r;
+      if (k < n) {
+        sig[sig_idx(d, k, 0, ab, j)] = outv[0][r];
+        sig[sig_idx(d, k, 1, ab, j)] = outv[1][r];
+        sig[sig_idx(d, k, 2, ab, j)] = csub(outv[1][r], outv[0][r]);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ equal-time collision
 // I^<(t_m, t_m) = dt sum_j a_j [Sigma^>_mj G^<_jm - Sigma^<_mj G^>_jm],  G_jm = -(G_mj)^dag
 // for j < m, a_j the quadrature weights on [0, t_m] (trapezoid, or with Gregory end
@@ -1908,6 +2038,14 @@ hipError_t launch_hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t 
 hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st) { KBE_DISPATCH(d.nb, props(d, a, st)); }
 hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
   KBE_DISPATCH(d.nb, sigma(d, a, m, st));
+}
+hipError_t launch_sigma_direct(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  size_t shm = (size_t)(6 * d.nk + d.nk / 8) * sizeof(cplx);
+  hipError_t e = allow_lds((const void*)k_sigma_direct, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sigma_direct, dim3((m + 1) * 4), dim3(512), shm, st, d, (const cplx*)a.row64, a.sig, m, a.UU,
+                     a.corr);
+  return hipGetLastError();
 }
 hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
   KBE_DISPATCH(d.nb, diag_I(d, a, m, st));

@@ -57,6 +57,8 @@ hipError_t launch_init(const Dims& d, const LaunchArgs& a, hipStream_t st);
 hipError_t launch_hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t st);
 hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st);
 hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+// the paper's direct-sum self-energy (interband preset, chain with even n <= 1024)
+hipError_t launch_sigma_direct(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st);

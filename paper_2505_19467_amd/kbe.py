@@ -67,7 +67,7 @@ _lib.kbe_last_error.restype = ctypes.c_char_p
 _lib.kbe_buffer.argtypes = [_vp, _i32, ctypes.POINTER(_vp), _szp]
 for _n in ("kbe_stage_propagators", "kbe_stage_update"):
     getattr(_lib, _n).argtypes = [_vp, _i32, _i32]
-for _n in ("kbe_stage_sigma", "kbe_stage_collision", "kbe_stage_observables", "kbe_stage_commit",
+for _n in ("kbe_stage_sigma", "kbe_stage_sigma_direct", "kbe_stage_collision", "kbe_stage_observables", "kbe_stage_commit",
            "kbe_rebuild_aux", "kbe_timing"):
     getattr(_lib, _n).argtypes = [_vp, _i32]
 _lib.kbe_timing_query.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -77,7 +77,7 @@ _lib.kbe_adjoint_attach.argtypes = [_vp, _vp, ctypes.c_size_t]
 _lib.kbe_adjoint_step.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 
 EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_corrector_log", "kbe_observables",
-           "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma",
+           "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma", "kbe_stage_sigma_direct",
            "kbe_stage_collision", "kbe_stage_update", "kbe_stage_observables", "kbe_stage_commit",
            "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query", "kbe_adjoint_query", "kbe_adjoint_attach",
            "kbe_adjoint_step"]
@@ -257,6 +257,10 @@ class System:
 
     def stage_sigma(self, m):
         self._check(_lib.kbe_stage_sigma(self._ctx, m), "kbe_stage_sigma")
+
+    def stage_sigma_direct(self, m):
+        """The self-energy row by the paper's direct momentum sums (interband preset, chains)."""
+        self._check(_lib.kbe_stage_sigma_direct(self._ctx, m), "kbe_stage_sigma_direct")
 
     def stage_collision(self, m):
         self._check(_lib.kbe_stage_collision(self._ctx, m), "kbe_stage_collision")

@@ -131,3 +131,49 @@ def test_adjoint_refuses_paper_model(K):
     with pytest.raises(K.KbeError):
         S.adjoint_gradient("n_band1")
     S.close()
+
+
+# ---------------------------------------------------------------- the paper's direct sums
+@pytest.mark.parametrize("nkx,m", [(16, 3), (64, 5), (104, 2), (1024, 1)])
+def test_sigma_direct_parity(K, nkx, m):
+    """kbe_stage_sigma_direct (eq. (polarizability)/(kernel2) and Alg. "contraction2") gives the
+    oracle's self-energy, and the transform route's to rounding."""
+    _say(f"direct-sum sigma chain {nkx} m={m}")
+    cfg = _interband(nkx, 1, m + 2)
+    S, row = _sigma_case(K, cfg, m, 500 + m + nkx)
+    fft = S.sigma_row(m).cpu().numpy()
+    S.stage_sigma_direct(m)
+    got = S.sigma_row(m).cpu().numpy()
+    assert relerr(got, O.sigma_row(cfg, m, row)) < KERNEL_TOL
+    assert relerr(got, fft) < KERNEL_TOL
+    sp = S.sigma_planes()[:, :, :, :m + 1].cpu().numpy()
+    assert np.abs(sp[:, 2] - (sp[:, 1] - sp[:, 0])).max() <= 1e-15 * max(1.0, np.abs(sp).max())
+
+
+def test_sigma_direct_full_size(K):
+    """The direct sums at the paper's size (n_k = 1024, the slice at m = 500: the call the
+    benchmark times) against the transform route on every output, and against the oracle on
+    sampled t_j."""
+    cfg = inputs.paper_chain()
+    m = cfg.nt
+    _say(f"full-size direct-sum sigma nk={cfg.nk} m={m}")
+    S, row = _sigma_case(K, cfg, m, 2029)
+    fft = S.sigma_row(m).cpu().numpy()
+    S.stage_sigma_direct(m)
+    got = S.sigma_row(m).cpu().numpy()
+    err = relerr(got, fft)
+    _say(f"  direct vs transforms, all outputs: rel err {err:.2e}")
+    assert err < KERNEL_TOL
+    for j in (0, 333, m):
+        e = relerr(got[j:j + 1], O.sigma_row(cfg, 0, row[j:j + 1]))
+        _say(f"  t_j={j} vs oracle: rel err {e:.2e}")
+        assert e < KERNEL_TOL
+    S.close()
+
+
+def test_sigma_direct_refuses_other_shapes(K):
+    for cfg in (_interband(20, 1, 4), inputs.c1(), _interband(4, 4, 4)):
+        S = K.System(cfg, nt_max=3)
+        with pytest.raises(K.KbeError):
+            S.stage_sigma_direct(0)
+        S.close()

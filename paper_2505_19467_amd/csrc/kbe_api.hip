@@ -65,7 +65,6 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
   d.Smax = (c->nt_max + 63) / 64;
   d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
-  d.rps = c->nb == 4 ? 2 : 1;
   d.spb = c->nb <= 2 ? 2 : 1;
   d.qp = c->quad_points > 1 ? c->quad_points : 1;
   d.rring = d.qp > 2 ? d.qp : 2;
@@ -80,7 +79,7 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   sz[B_PROP] = nk * 3 * d.nbb * cz;
   sz[B_COLSUM] = nk * d.C * d.Tp * cz;
   sz[B_COL0] = sz[B_DIAG] = nk * d.C * (size_t)d.qp * d.Tp * cz;  // qp columns / band offsets
-  sz[B_ROWPART] = nk * (size_t)d.Smax * d.rps * d.nbb * d.Tp * cz;
+  sz[B_ROWPART] = nk * (size_t)d.Smax * d.nbb * d.Tp * cz;
   sz[B_HF] = d.nbb * cz;
   sz[B_HOP] = 3 * d.nbb * cz;
   sz[B_EIGW] = nk * d.nb * sizeof(double);

@@ -84,8 +84,6 @@ struct Dims {
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
   int fp32;        // 1: the packed history is stored in FP32 (complex64)
-  int rps;         // row-partial slots per strip group: 2 when the history sums split a block's
-                   // components between two wavefronts (nb = 4), else 1
   int spb;         // 64-column strips per row-partial slot group: 2 when one history-sum block
                    // covers a pair of strips (nb <= 2), else 1
   int qp;          // quadrature nodes per end carrying end corrections (1: trapezoid)
@@ -121,9 +119,9 @@ __host__ __device__ __forceinline__ int64_t colq_idx(const Dims& d, int k, int c
 __host__ __device__ __forceinline__ int64_t band_idx(const Dims& d, int k, int c, int row, int off) {
   return (((int64_t)k * d.C + c) * d.qp + off) * d.Tp + row;
 }
-// Row-partial sums of the history sums: [k][slot][nb^2][Tp], slot = (strip / spb) * rps + half.
+// Row-partial sums of the history sums: [k][slot][nb^2][Tp], slot = strip / spb.
 __host__ __device__ __forceinline__ const cplx* rowpart_slot(const Dims& d, const cplx* rowpart, int k, int slot) {
-  return rowpart + ((int64_t)k * d.Smax * d.rps + slot) * d.nbb * d.Tp;
+  return rowpart + ((int64_t)k * d.Smax + slot) * d.nbb * d.Tp;
 }
 __host__ __device__ __forceinline__ int64_t rowbuf_idx(const Dims& d, int k, int c, int t) {
   return ((int64_t)k * d.C + c) * d.Tp + t;

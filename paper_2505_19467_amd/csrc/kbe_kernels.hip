@@ -729,6 +729,20 @@ __device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int
   wave_sync();
 }
 
+// The nb = 4 kernels' two component halves stage the row partials of the same 16 rows; after a
+// block barrier each of the two wavefronts stores half of the nb^2 components of their sum
+// (st0 + st1, a fixed order) to rows rb .. rb + 15 of the strip's slot, 256-byte runs.
+template <int NBB>
+__device__ __forceinline__ void flush_rows_fold(const cplx* st0, const cplx* st1, cplx* rp, int Tp, int rb, int m,
+                                                int lane, int h) {
+#pragma unroll
+  for (int q = lane; q < NBB * 8; q += 64) {
+    int e = h * (NBB / 2) + (q >> 4), r = q & 15;
+    int row = rb + r;
+    if (row < m) store_stream(rp + (int64_t)e * Tp + row, cadd(st0[e * 16 + r], st1[e * 16 + r]));
+  }
+}
+
 // Bulk of the collision integrals at row m over the stored blocks (j, t'), t' <= j <= m-1,
 // each with weight 1 (end-point weights are corrected in k_row):
 //   column term -> output t':  SR_j G^{<,>}_{j t'}                    (SR = Sigma^> - Sigma^<)
@@ -1264,12 +1278,12 @@ __global__ __launch_bounds__(256) void k_hist_bulk32(Dims d, const cplx32* __res
 // stream G^< (components 0..15), waves 1 and 3 stream G^> (16..31); the row pair (0, 1) takes
 // rows 0-15 of every 32-row chunk of the strip, the pair (2, 3) rows 16-31 (16 contiguous 1 KB
 // segments in flight per wavefront). Half 0 contributes -Sigma^>_{t'} (G^<_{j t'})^dag to the
-// row term, half 1 +Sigma^<_{t'} (G^>_{j t'})^dag, each to its own row-partial slot
-// (strip * 2 + half), summed by k_row. The four block rows of a row term go through one
-// 64-lane reduce-scatter together (4 quantities for the instructions of one), and a
-// wavefront's 16 row partials are staged in LDS and stored as 256-byte runs with streaming
-// stores. The per-column Sigma of the row term is read from LDS. FP64 storage; 2 waves per
-// SIMD.
+// row term, half 1 +Sigma^<_{t'} (G^>_{j t'})^dag. The four block rows of a row term go through
+// one 64-lane reduce-scatter together (4 quantities for the instructions of one); a
+// wavefront's 16 row partials are staged in LDS (two buffers, alternating by chunk), and after
+// one block barrier per 32-row chunk the two halves' partials are added and stored as 256-byte
+// runs with streaming stores, one row-partial slot per strip. The per-column Sigma of the row
+// term is read from LDS. FP64 storage; 2 waves per SIMD.
 template <int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_bulk_split(
     Dims d, const cplx* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
@@ -1278,7 +1292,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(NB == 4, "the four block rows share one reduce-scatter");
   __shared__ cplx sS[2][NBB][64];  // [half][e][lane]: half 0 needs Sigma^>, half 1 Sigma^<;
                                    // reused for the column-sum combine after the row loop
-  __shared__ cplx stg[2][2][NBB * 16];  // [row pair][half][e * 16 + row]
+  __shared__ cplx stg[2][2][2][NBB * 16];  // [buffer][row pair][half][e * 16 + row]
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63;
@@ -1297,11 +1311,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
   for (int e = 0; e < NBB; ++e) acc[e] = czero();
   const cplx* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
-  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
-  cplx* st = stg[rg][h];
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
   const double sgn = h ? 1.0 : -1.0;
-  for (int cb = 64 * s; cb < m; cb += 32) {
+  int buf = 0;
+  for (int cb = 64 * s; cb < m; cb += 32) {  // the same chunks in every wavefront
     const int rb = cb + 16 * rg;
+    cplx* st = stg[buf][rg][h];
     for (int i = 0; i < 16; ++i) {
       const int j = rb + i;
       if (j >= m) break;
@@ -1339,7 +1354,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk(x[0][2 * b], x[0][2 * b + 1]);
       }
     }
-    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+    __syncthreads();  // both halves of the chunk staged; the other buffer is free again
+    flush_rows_fold<NBB>(stg[buf][rg][0], stg[buf][rg][1], rp, d.Tp, rb, m, lane, h);
+    buf ^= 1;
   }
   __syncthreads();  // every wavefront is done with sS
   cplx (*red)[NBB][64] = sS;
@@ -1365,8 +1382,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(NB == 4, "the four block rows share one reduce-scatter");
   static_assert(NBB % 2 == 0, "component pairs must not straddle the halves");
   __shared__ cplx32 sS[2][NBB][64];
-  __shared__ cplx red[2][NBB][64];
-  __shared__ cplx stg[2][2][NBB * 16];
+  __shared__ cplx stg[2][2][2][NBB * 16];  // [buffer][row pair][half][e * 16 + row]; column-sum
+                                           // combine after the row loop
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63;
@@ -1389,11 +1406,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     acc32[e] = make_float2(0.f, 0.f);
   }
   const cplx32* hk = hist + strip_lane_base(d, k, s, lane) + 64 * NBB * h;
-  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, 2 * s + h));
-  cplx* st = stg[rg][h];
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
   const float sgn = h ? 1.f : -1.f;
-  for (int cb = 64 * s; cb < m; cb += 32) {
+  int buf = 0;
+  for (int cb = 64 * s; cb < m; cb += 32) {  // the same chunks in every wavefront
     const int rb = cb + 16 * rg;
+    cplx* st = stg[buf][rg][h];
     for (int i = 0; i < 16; ++i) {
       const int j = rb + i;
       if (j >= m) break;
@@ -1442,8 +1460,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       acc[e].y += (double)acc32[e].y;
       acc32[e] = make_float2(0.f, 0.f);
     }
-    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+    __syncthreads();  // both halves of the chunk staged; the other buffer is free again
+    flush_rows_fold<NBB>(stg[buf][rg][0], stg[buf][rg][1], rp, d.Tp, rb, m, lane, h);
+    buf ^= 1;
   }
+  __syncthreads();  // every wavefront is done with stg
+  cplx (*red)[NBB][64] = reinterpret_cast<cplx (*)[NBB][64]>(&stg[0][0][0][0]);
   if (rg == 1) {
 #pragma unroll
     for (int e = 0; e < NBB; ++e) red[h][e][lane] = acc[e];
@@ -1520,7 +1542,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
       for (int c = 0; c < C; ++c) In[c] = colsum[rowbuf_idx(d, k, c, tp)];
       cplx rs[NBB];
       mat_zero<NB>(rs);
-      int nslot = ((tp >> 6) / d.spb + 1) * d.rps;
+      int nslot = (tp >> 6) / d.spb + 1;
       for (int q = 0; q < nslot; ++q) {
         const cplx* rp = rowpart_slot(d, rowpart, k, q);
 #pragma unroll

@@ -62,16 +62,34 @@ def _energy_balance(obs, cfg):
     return obs[:, 5] - obs[0, 5] + W
 
 
-def cpu_baseline(cfg, sample_steps: int):
-    """The CPU oracle (plain FP64 C++, OpenMP over k) on the first ``sample_steps``
-    steps of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, sample_steps: int, one_core_steps: int):
+    """The CPU oracle (plain FP64 C++, OpenMP over k) on the first ``sample_steps`` steps of the
+    same workload with all its threads, and on the first ``one_core_steps`` with one thread."""
     from oracle import oracle as O
     O.build()
+    threads = O.max_threads()
     t0 = time.perf_counter()
     O.run(cfg, sample_steps)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dt, threads
+    dt1 = None
+    if one_core_steps > 0:
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        O.run(cfg, one_core_steps)
+        dt1 = time.perf_counter() - t0
+        O.set_threads(threads)
+    return dt, threads, dt1
 
 
 def adjoint_leg(torch, inputs, kbe):
@@ -183,7 +201,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--cpu-sample", type=int, default=60, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-adaptive", action="store_true",
@@ -354,7 +372,8 @@ def main():
     if args.cpu_sample > 0:
         ns = min(args.cpu_sample, K)
         print(f"[bench] CPU oracle on steps 1..{ns} ...", file=sys.stderr, flush=True)
-        tcpu, threads = cpu_baseline(cfg, ns)
+        n1 = min(30, ns)
+        tcpu, threads, tcpu1 = cpu_baseline(cfg, ns, n1)
         # GPU time for the same steps, for a like-for-like ratio
         S.reset()
         Sg = S
@@ -366,7 +385,9 @@ def main():
         cpu = {"value": ns / tcpu, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{cfg.name} steps 1..{ns} of {cfg.nt} (FP64 C++ oracle, OpenMP over k); "
                          f"{tcpu:.2f} s; the GPU path takes {tgpu:.3f} s on the same steps",
-               "gpu_same_sample_steps_per_s": ns / tgpu}
+               "gpu_same_sample_steps_per_s": ns / tgpu, "cpu_model": cpu_model(),
+               "one_core_steps_per_s": (n1 / tcpu1) if tcpu1 else None,
+               "one_core_sample": f"steps 1..{n1}, one OpenMP thread"}
 
     traffic = None
     if args.workload == "c2" and K == cfg.nt and _kernel_source_sha1() == MEASURED_TRAFFIC["source_sha1"]:

@@ -64,6 +64,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 // ---------------------------------------------------------------- real types
@@ -1127,6 +1129,13 @@ extern "C" {
 int oracle_nobs() { return NOBS; }
 
 // Quadrature weights of eq. (CI) on [0, N]: out[j] = weight of node j, j = 0..N.
+// Threads of the OpenMP loops over k: the count the next run uses, and a way to change it (for
+// a one-core timing).
+int oracle_max_threads() { return omp_get_max_threads(); }
+void oracle_set_threads(int32_t n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
 int oracle_quad_weights(int32_t quad_points, int32_t N, double* out) {
   if (quad_points < 1 || quad_points > QUAD_MAX || N < 0 || !out) return -1;
   Params p{};

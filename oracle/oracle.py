@@ -66,6 +66,8 @@ def lib():
         _lib.oracle_run_log.argtypes = [P, dp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int32), dp]
         _lib.oracle_quad_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, dp]
         _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
+        _lib.oracle_max_threads.restype = ctypes.c_int
+        _lib.oracle_set_threads.argtypes = [ctypes.c_int32]
     return _lib
 
 
@@ -219,3 +221,13 @@ def h0(cfg, A: float) -> np.ndarray:
     p = params(cfg)
     lib().oracle_h0(ctypes.byref(p), _ptr(_hop(cfg)), float(A), _ptr(out))
     return out
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops over k-points use."""
+    return int(lib().oracle_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the oracle's OpenMP thread count (for a one-core timing)."""
+    lib().oracle_set_threads(int(n))

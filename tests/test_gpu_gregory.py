@@ -21,7 +21,7 @@ def K():
     return kbe
 
 
-@pytest.mark.parametrize("q,nkx,nky,nb,m", [(3, 3, 2, 2, 1), (3, 3, 2, 2, 2), (3, 2, 2, 2, 3), (4, 2, 1, 2, 5),
+@pytest.mark.parametrize("q,nkx,nky,nb,m", [(3, 3, 2, 2, 0), (3, 3, 2, 2, 1), (3, 3, 2, 2, 2), (3, 2, 2, 2, 3), (4, 2, 1, 2, 5),
                                             (6, 2, 2, 1, 4), (6, 2, 1, 2, 11), (2, 3, 2, 2, 64), (3, 2, 2, 2, 65),
                                             (4, 2, 1, 1, 130), (5, 1, 2, 4, 70), (4, 2, 1, 3, 66), (6, 3, 1, 2, 200)])
 def test_gregory_collision_row_parity(K, q, nkx, nky, nb, m):

@@ -94,7 +94,7 @@ def test_sigma_row_parity(K, nkx, nky, nb, m):
 @pytest.mark.parametrize("nkx,nky,nb,m", [(3, 2, 2, 130), (4, 1, 1, 64), (2, 2, 3, 65), (2, 1, 4, 70),
                                           (2, 2, 2, 1), (2, 2, 2, 2), (1, 3, 2, 63), (2, 1, 2, 200),
                                           (2, 2, 2, 128), (2, 1, 1, 129), (1, 2, 2, 192), (2, 1, 2, 257),
-                                          (1, 2, 1, 65), (1, 1, 4, 129)])
+                                          (1, 2, 1, 65), (1, 1, 4, 129), (2, 2, 2, 0)])
 def test_collision_row_parity(K, nkx, nky, nb, m):
     import torch
     _say(f"collision parity nk={nkx}x{nky} nb={nb} m={m}")
@@ -234,6 +234,38 @@ def test_errors_are_reported(K):
         S.step(1)
     with pytest.raises(K.KbeError):
         S.stage_sigma(99)
+
+
+def test_largest_history_length(K):
+    """nt_max = 8192, the largest history length the library accepts, on a 2-point chain with
+    nb = 1: 40 propagated steps against the oracle, then the history sums of the last row
+    (m = 8192: 129 strips in 65 strip pairs) on a seeded random history, both k-points
+    recomputed by the oracle."""
+    from tests.sampled import collision_reference
+    cfg = _cfg(2, 1, 1, 8192, pulse=inputs.Pulse(amp=0.6, omega=1.2, t0=0.3, width=0.7))
+    _say("largest history length: nt_max = 8192")
+    S = K.System(cfg)
+    n = 40
+    S.step(n)
+    obs = S.observables(0, n + 1)
+    ref = O.run(cfg, n)["obs"]
+    for name in ("N", "Ekin", "EHF", "Ecorr", "Etot", "Jx", "n_band0"):
+        i = O.OBS[name]
+        assert relerr(obs[:, i], ref[:, i]) < RUN_TOL, name
+    m = cfg.nt
+    inputs.fill_normal_(S.history, seed=2030, scale=0.3)
+    inputs.fill_normal_(S.sigma_planes(), seed=2031, scale=0.3)
+    sp = S.sigma_planes()
+    sp[:, 2].copy_(sp[:, 1] - sp[:, 0])
+    S.rebuild_aux(m)
+    S.stage_collision(m)
+    got_all = S.collision_row(m).cpu().numpy()
+    sig_all = S.sigma_row(m).cpu().numpy()
+    for k in range(cfg.nk):
+        err = relerr(got_all[:, k:k + 1], collision_reference(K, S, cfg, m, k, sig_all))
+        _say(f"  m = {m}, k = {k}: rel err {err:.2e}")
+        assert err < KERNEL_TOL
+    S.close()
 
 
 # ---------------------------------------------------------------- full size, sampled

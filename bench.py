@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # once that code changes.
 MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0216,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "a39ce85f3a3c7bd8e6b3b5ee2abaa7be0d00e607"}
+                    "source_sha1": "10c2bea7c3ad57daf85d2b4d4a9f1c2aa4116c3d"}
 
 
 def _kernel_source_sha1():

@@ -16,6 +16,11 @@
 
 namespace kbe {
 
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
 // ------------------------------------------------------------------ utility
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -803,69 +808,77 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
     for (int i = 0; i < 16 / R; ++i) {
       const int jb = rb + R * i;
       if (jb >= m) break;
-      cplx G[R][2][C];
+      // rows past the pair's first 128 (and below m) need no masks (as in k_hist_pair32)
+      auto iteration = [&](auto tag) {
+        constexpr bool MASKED = decltype(tag)::value;
+        cplx G[R][2][C];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < 2; ++h) {
+            int j = jb + r;
+            bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
+            const cplx* row = hk[h] + 64 * (int64_t)C * j;
+#pragma unroll
+            for (int c = 0; c < C; ++c) G[r][h][c] = v ? load_stream(row + 64 * c) : czero();
+          }
+        double rt[R][2 * NBB];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
           int j = jb + r;
-          bool v = colv[h] && tp[h] <= j && j < m;
-          const cplx* row = hk[h] + 64 * (int64_t)C * j;
+          int jc = MASKED ? (j < m ? j : m - 1) : j;
+          cplx SR[NBB];
 #pragma unroll
-          for (int c = 0; c < C; ++c) G[r][h][c] = v ? load_stream(row + 64 * c) : czero();
-        }
-      double rt[R][2 * NBB];
+          for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int j = jb + r;
-        int jc = j < m ? j : m - 1;
-        cplx SR[NBB];
+          for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.0;
 #pragma unroll
-        for (int e = 0; e < NBB; ++e) SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
+          for (int h = 0; h < 2; ++h) {
+            mm_acc<NB>(acc[h], SR, G[r][h]);
+            mm_acc<NB>(acc[h] + NBB, SR, G[r][h] + NBB);
+            cplx Sl[NBB], Sg[NBB], a[NBB], u[NBB];
 #pragma unroll
-        for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.0;
+            for (int e = 0; e < NBB; ++e) {
+              Sl[e] = sS[h][0][e][lane];
+              Sg[e] = sS[h][1][e][lane];
+            }
+            mat_zero<NB>(a);
+            mat_zero<NB>(u);
+            mm_acc_bdag<NB>(a, Sl, G[r][h] + NBB);
+            mm_acc_bdag<NB>(u, Sg, G[r][h]);
+            bool rv = MASKED ? tp[h] < j : true;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          mm_acc<NB>(acc[h], SR, G[r][h]);
-          mm_acc<NB>(acc[h] + NBB, SR, G[r][h] + NBB);
-          cplx Sl[NBB], Sg[NBB], a[NBB], u[NBB];
-#pragma unroll
-          for (int e = 0; e < NBB; ++e) {
-            Sl[e] = sS[h][0][e][lane];
-            Sg[e] = sS[h][1][e][lane];
-          }
-          mat_zero<NB>(a);
-          mat_zero<NB>(u);
-          mm_acc_bdag<NB>(a, Sl, G[r][h] + NBB);
-          mm_acc_bdag<NB>(u, Sg, G[r][h]);
-          bool rv = tp[h] < j;
-#pragma unroll
-          for (int e = 0; e < NBB; ++e) {
-            rt[r][2 * e] += rv ? a[e].x - u[e].x : 0.0;
-            rt[r][2 * e + 1] += rv ? a[e].y - u[e].y : 0.0;
+            for (int e = 0; e < NBB; ++e) {
+              rt[r][2 * e] += rv ? a[e].x - u[e].x : 0.0;
+              rt[r][2 * e + 1] += rv ? a[e].y - u[e].y : 0.0;
+            }
           }
         }
-      }
-      if constexpr (R == 1 && NBB == 4) {
-        // one row, four components: each component's (re, im) is one group of a 4-group
-        // reduce-scatter (2 lane reductions instead of 8)
-        double xg[4][2];
+        if constexpr (R == 1 && NBB == 4) {
+          // one row, four components: each component's (re, im) is one group of a 4-group
+          // reduce-scatter (2 lane reductions instead of 8)
+          double xg[4][2];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          xg[e][0] = rt[0][2 * e];
-          xg[e][1] = rt[0][2 * e + 1];
-        }
-        reduce_rows<4>(xg);
-        int e = reduced_row<4>(lane);
-        if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
-      } else {
-        reduce_rows<R>(rt);
-        int rr = reduced_row<R>(lane);
-        if (rr >= 0) {
+          for (int e = 0; e < 4; ++e) {
+            xg[e][0] = rt[0][2 * e];
+            xg[e][1] = rt[0][2 * e + 1];
+          }
+          reduce_rows<4>(xg);
+          int e = reduced_row<4>(lane);
+          if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
+        } else {
+          reduce_rows<R>(rt);
+          int rr = reduced_row<R>(lane);
+          if (rr >= 0) {
 #pragma unroll
-          for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+          }
         }
-      }
+      };
+      if (jb >= 128 * sp + 128 && jb + R <= m)
+        iteration(BoolTag<false>{});
+      else
+        iteration(BoolTag<true>{});
     }
     flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
   }
@@ -945,89 +958,98 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
     for (int i = 0; i < 16 / R; ++i) {
       const int jb = rb + R * i;
       if (jb >= m) break;
-      cplx32 G[R][2][C];
+      // rows past the pair's first 128 (and below m) need no masks: every lane's columns lie
+      // below the row, so that common case runs without the bounds selects
+      auto iteration = [&](auto tag) {
+        constexpr bool MASKED = decltype(tag)::value;
+        cplx32 G[R][2][C];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          int j = jb + r;
-          bool v = colv[h] && tp[h] <= j && j < m;
-          const cplx32* row = hk[h] + 64 * (int64_t)C * j;
+          for (int h = 0; h < 2; ++h) {
+            int j = jb + r;
+            bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
+            const cplx32* row = hk[h] + 64 * (int64_t)C * j;
 #pragma unroll
-          for (int c2 = 0; c2 < C / 2; ++c2) {
-            if (v) {
-              load_stream32x2(row + 128 * c2, G[r][h][2 * c2], G[r][h][2 * c2 + 1]);
-            } else {
-              G[r][h][2 * c2] = make_float2(0.f, 0.f);
-              G[r][h][2 * c2 + 1] = make_float2(0.f, 0.f);
+            for (int c2 = 0; c2 < C / 2; ++c2) {
+              if (v) {
+                load_stream32x2(row + 128 * c2, G[r][h][2 * c2], G[r][h][2 * c2 + 1]);
+              } else {
+                G[r][h][2 * c2] = make_float2(0.f, 0.f);
+                G[r][h][2 * c2 + 1] = make_float2(0.f, 0.f);
+              }
             }
           }
-        }
-      float rt[R][2 * NBB];
+        float rt[R][2 * NBB];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int j = jb + r;
-        int jc = j < m ? j : m - 1;
-        cplx32 SR[NBB];
+        for (int r = 0; r < R; ++r) {
+          int j = jb + r;
+          int jc = MASKED ? (j < m ? j : m - 1) : j;
+          cplx32 SR[NBB];
 #pragma unroll
-        for (int e = 0; e < NBB; ++e) SR[e] = to32(sk[(2 * NBB + e) * d.Tp + jc]);
+          for (int e = 0; e < NBB; ++e) SR[e] = to32(sk[(2 * NBB + e) * d.Tp + jc]);
 #pragma unroll
-        for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.f;
+          for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.f;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < 2; ++h) {
 #pragma unroll
-          for (int sc = 0; sc < 2; ++sc)
+            for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+              for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                  for (int l = 0; l < NB; ++l)
+                    cmac32(acc32[h][sc * NBB + a * NB + b], SR[a * NB + l], G[r][h][sc * NBB + l * NB + b]);
+            bool rv = MASKED ? tp[h] < j : true;
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-              for (int b = 0; b < NB; ++b)
+              for (int b = 0; b < NB; ++b) {
+                cplx32 x = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int l = 0; l < NB; ++l)
-                  cmac32(acc32[h][sc * NBB + a * NB + b], SR[a * NB + l], G[r][h][sc * NBB + l * NB + b]);
-          bool rv = tp[h] < j;
-#pragma unroll
-          for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              cplx32 x = make_float2(0.f, 0.f), u = make_float2(0.f, 0.f);
-#pragma unroll
-              for (int l = 0; l < NB; ++l) {
-                cmacc32(x, sS[h][0][a * NB + l][lane], G[r][h][NBB + b * NB + l]);
-                cmacc32(u, sS[h][1][a * NB + l][lane], G[r][h][b * NB + l]);
+                for (int l = 0; l < NB; ++l) {
+                  cmacc32(x, sS[h][0][a * NB + l][lane], G[r][h][NBB + b * NB + l]);
+                  cmacc32(u, sS[h][1][a * NB + l][lane], G[r][h][b * NB + l]);
+                }
+                int e = a * NB + b;
+                rt[r][2 * e] += rv ? x.x - u.x : 0.f;
+                rt[r][2 * e + 1] += rv ? x.y - u.y : 0.f;
               }
-              int e = a * NB + b;
-              rt[r][2 * e] += rv ? x.x - u.x : 0.f;
-              rt[r][2 * e + 1] += rv ? x.y - u.y : 0.f;
-            }
+          }
         }
-      }
-      if constexpr (R == 2 && NBB == 4) {
-        // two rows, four components: groups (row, component pair) of a 4-group reduce-scatter
-        // (4 lane reductions instead of 8); group g = 2 r + p holds components 2 p, 2 p + 1
-        float xg[4][4];
+        if constexpr (R == 2 && NBB == 4) {
+          // two rows, four components: groups (row, component pair) of a 4-group reduce-scatter
+          // (4 lane reductions instead of 8); group g = 2 r + p holds components 2 p, 2 p + 1
+          float xg[4][4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+          for (int r = 0; r < 2; ++r)
 #pragma unroll
-          for (int p2 = 0; p2 < 2; ++p2)
+            for (int p2 = 0; p2 < 2; ++p2)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xg[2 * r + p2][q] = rt[r][4 * p2 + q];
-        reduce_rows32<4>(xg);
-        int g = reduced_row<4>(lane);
-        if (g >= 0) {
-          int r = g >> 1, p2 = g & 1;
+              for (int q = 0; q < 4; ++q) xg[2 * r + p2][q] = rt[r][4 * p2 + q];
+          reduce_rows32<4>(xg);
+          int g = reduced_row<4>(lane);
+          if (g >= 0) {
+            int r = g >> 1, p2 = g & 1;
 #pragma unroll
-          for (int c = 0; c < 2; ++c)
-            st[(2 * p2 + c) * 16 + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
+            for (int c = 0; c < 2; ++c)
+              st[(2 * p2 + c) * 16 + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
+          }
+        } else {
+          reduce_rows32<R>(rt);
+          int rr = reduced_row<R>(lane);
+          if (rr >= 0) {
+#pragma unroll
+            for (int e = 0; e < NBB; ++e)
+              st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+          }
         }
-      } else {
-        reduce_rows32<R>(rt);
-        int rr = reduced_row<R>(lane);
-        if (rr >= 0) {
-#pragma unroll
-          for (int e = 0; e < NBB; ++e)
-            st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
-        }
-      }
+      };
+      if (jb >= 128 * sp + 128 && jb + R <= m)
+        iteration(BoolTag<false>{});
+      else
+        iteration(BoolTag<true>{});
     }
     // the group's FP32 column sums into the FP64 accumulators
 #pragma unroll

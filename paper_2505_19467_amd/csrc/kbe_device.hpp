@@ -537,10 +537,79 @@ __device__ __forceinline__ void axis_dft_ct(cplx* __restrict__ x0, cplx* __restr
   __syncthreads();
 }
 
+// Power-of-two line length n (one line per array, contiguous): Stockham autosort FFT in
+// radix-4 stages (one radix-2 stage first when log2 n is odd), ping-ponging between x and the
+// scratch t. Stage with sub-length Ns (the product of the radices before it) and radix R:
+// butterfly j reads x[j + r n/R], r < R, multiplies by w^{sgn (j mod Ns) r n/(Ns R)}, takes the
+// R-point transform and writes y[(j / Ns) Ns R + (j mod Ns) + r Ns]; after the last stage the
+// output is in natural order (n log4 n work instead of n (n1 + n2)). The scale is applied by
+// the last stage; a result left in the scratch is copied back. Roots from the LDS table tw
+// (n entries). Every stage ends with a block barrier; the caller synchronises before the first.
+__device__ __forceinline__ void axis_fft_pow2(cplx* __restrict__ x0, cplx* __restrict__ x1, cplx* __restrict__ t0,
+                                              cplx* __restrict__ t1, int n, const cplx* __restrict__ tw, int sgn,
+                                              double scale) {
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  cplx *s0 = x0, *s1 = x1, *d0 = t0, *d1 = t1;
+  int Ns = 1;
+  int rem = lg;
+  while (rem > 0) {
+    const int R = (rem & 1) ? 2 : 4;  // the radix-2 stage first, then radix 4
+    rem -= (R == 2) ? 1 : 2;
+    const bool last = rem == 0;
+    const double sc = last ? scale : 1.0;
+    const int nb = n / R;           // butterflies per array
+    for (int it = threadIdx.x; it < 2 * nb; it += blockDim.x) {
+      const int arr = it >= nb;
+      const int j = it - arr * nb;
+      const cplx* src = arr ? s1 : s0;
+      cplx* dst = arr ? d1 : d0;
+      const int jm = j % Ns;
+      const int ustep = jm * (n / (Ns * R));
+      const int base = (j / Ns) * Ns * R + jm;
+      if (R == 2) {
+        cplx a = src[j], b = cmul(src[j + nb], root(tw, ustep, sgn));
+        dst[base] = cscal(cadd(a, b), sc);
+        dst[base + Ns] = cscal(csub(a, b), sc);
+      } else {
+        cplx v0 = src[j];
+        cplx v1 = cmul(src[j + nb], root(tw, ustep, sgn));
+        cplx v2 = cmul(src[j + 2 * nb], root(tw, (2 * ustep) % n, sgn));
+        cplx v3 = cmul(src[j + 3 * nb], root(tw, (3 * ustep) % n, sgn));
+        cplx s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = csub(v1, v3);
+        cplx id13 = sgn > 0 ? cmuli(d13) : cneg(cmuli(d13));  // (sgn i) (v1 - v3)
+        dst[base] = cscal(cadd(s02, s13), sc);
+        dst[base + Ns] = cscal(cadd(d02, id13), sc);
+        dst[base + 2 * Ns] = cscal(csub(s02, s13), sc);
+        dst[base + 3 * Ns] = cscal(csub(d02, id13), sc);
+      }
+    }
+    __syncthreads();
+    Ns *= R;
+    cplx* q0 = s0;
+    cplx* q1 = s1;
+    s0 = d0;
+    s1 = d1;
+    d0 = q0;
+    d1 = q1;
+  }
+  if (s0 != x0) {  // an odd number of stages left the result in the scratch
+    for (int it = threadIdx.x; it < 2 * n; it += blockDim.x) {
+      if (it < n) x0[it] = t0[it];
+      else x1[it - n] = t1[it - n];
+    }
+    __syncthreads();
+  }
+}
+
 // Index transform of an nx x ny grid (k = ix * ny + iy) for two arrays in place:
 //   x(R) <- scale * sum_k e^{sgn 2 pi i (ix Rx / nx + iy Ry / ny)} x(k); y lines, then x lines.
 __device__ __forceinline__ void grid_dft(cplx* x0, cplx* x1, cplx* t0, cplx* t1, int nx, int ny, const cplx* twx,
                                          const cplx* twy, int sgn, double scale) {
+  if (ny == 1 && nx >= 128 && (nx & (nx - 1)) == 0) {  // long power-of-two chains
+    axis_fft_pow2(x0, x1, t0, t1, nx, twx, sgn, scale);
+    return;
+  }
   if (ny > 1) axis_dft(x0, x1, t0, t1, ny, nx, ny, 1, twy, sgn, 1.0);
   axis_dft(x0, x1, t0, t1, nx, ny, 1, ny, twx, sgn, scale);
 }

@@ -42,8 +42,10 @@ def _sigma_case(K, cfg, m, seed):
 
 
 # chains: 16 (compile-time transform), 37 (prime: direct line sums), 96 (8 x 12 split), 200 (10 x 20:
-# more than 8 first-stage outputs per line), 1024 (32 x 32, the paper's n_k); 2D grids
-@pytest.mark.parametrize("nkx,nky,m", [(16, 1, 5), (37, 1, 4), (96, 1, 9), (200, 1, 3), (1024, 1, 2),
+# more than 8 first-stage outputs per line), 128 / 512 (power-of-two FFT with a radix-2 stage),
+# 256 / 1024 (radix-4 stages only; 1024 is the paper's n_k); 2D grids
+@pytest.mark.parametrize("nkx,nky,m", [(16, 1, 5), (37, 1, 4), (96, 1, 9), (200, 1, 3), (128, 1, 6),
+                                       (256, 1, 4), (512, 1, 3), (1024, 1, 2),
                                        (4, 3, 7), (6, 4, 70), (5, 5, 0)])
 def test_interband_sigma_row_parity(K, nkx, nky, m):
     _say(f"interband sigma nk={nkx}x{nky} m={m}")

@@ -810,33 +810,33 @@ __global__ __launch_bounds__(256) void k_adj_props(Dims d, const cplx* __restric
     if (lane < BB) sX[wv][lane] = x;
     cplx e = id;
     if (lane < BB) sE[wv][lane] = e;
-    __syncthreads();
+    wave_sync();  // every LDS array here is per wavefront
     for (int n = 18; n >= 1; --n) {
       cplx acc = czero();
       if (lane < BB)
 #pragma unroll
         for (int l = 0; l < B2; ++l) cmac(acc, sX[wv][r * B2 + l], sE[wv][l * B2 + c]);
-      __syncthreads();
+      wave_sync();  // every LDS array here is per wavefront
       e = cadd(id, cscal(acc, 1.0 / n));
       if (lane < BB) sE[wv][lane] = e;
-      __syncthreads();
+      wave_sync();  // every LDS array here is per wavefront
     }
     for (int q = 0; q < s; ++q) {
       cplx acc = czero();
       if (lane < BB)
 #pragma unroll
         for (int l = 0; l < B2; ++l) cmac(acc, sE[wv][r * B2 + l], sE[wv][l * B2 + c]);
-      __syncthreads();
+      wave_sync();  // every LDS array here is per wavefront
       e = acc;
       if (lane < BB) sE[wv][lane] = e;
-      __syncthreads();
+      wave_sync();  // every LDS array here is per wavefront
     }
     // top-right block, top-left (NB x NB) sub-block of L: (r, c - N2) with r, c - N2 < NB
     if (act && r < NB && c >= N2 && c - N2 < NB) mbar = cadd(mbar, cscal(e, ne * sc));
   }
   // hbarbar = i dt Mbar_tl
   if (act && r < NB && c >= N2 && c - N2 < NB) hb[wv][r * NB + (c - N2)] = cscal(cmuli(mbar), dt);
-  __syncthreads();
+  wave_sync();  // every LDS array here is per wavefront
   if (kval && lane == 0) {
     // dL/dhf_aa += Re hbarbar_aa ;  dL/dA += Re sum conj(hbarbar) dh0/dA, dh0/dA = -(pol . v)
     cplx vx[NBB], vy[NBB];

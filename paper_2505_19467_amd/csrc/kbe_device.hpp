@@ -350,7 +350,15 @@ __device__ __forceinline__ double row16_sum(double x) {
 
 
 // ------------------------------------------------------------------ factorised line transforms
-// Roots of unity tw[u] = e^{+2 pi i u / n}, u < n (n <= 64), for one block (one per thread).
+// Keep the compiler from moving LDS accesses of one wavefront across this point (the lanes of
+// a wavefront exchange values through LDS; the hardware executes them in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Roots of unity tw[u] = e^{+2 pi i u / n}, u < n, into an LDS table (the block's threads in turn).
 __device__ __forceinline__ void fill_roots(cplx* tw, int n) {
   for (int u = threadIdx.x; u < n; u += blockDim.x) {
     double sn, cs;

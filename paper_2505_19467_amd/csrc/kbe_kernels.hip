@@ -225,16 +225,16 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
   if (lane < NN) sX[wv][lane] = x;
   cplx e = id;
   if (lane < NN) sE[wv][lane] = e;
-  __syncthreads();
+  wave_sync();  // every LDS array here is per wavefront
   for (int n = 16; n >= 1; --n) {  // E <- 1 + X E / n
     cplx acc = czero();
     if (lane < NN)
 #pragma unroll
       for (int l = 0; l < N2; ++l) cmac(acc, sX[wv][r * N2 + l], sE[wv][l * N2 + c]);
-    __syncthreads();
+    wave_sync();  // every LDS array here is per wavefront
     e = cadd(id, cscal(acc, 1.0 / n));
     if (lane < NN) sE[wv][lane] = e;
-    __syncthreads();
+    wave_sync();  // every LDS array here is per wavefront
   }
   cplx half = czero();
   for (int q = 0; q < s; ++q) {  // E <- E E
@@ -243,10 +243,10 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
     if (lane < NN)
 #pragma unroll
       for (int l = 0; l < N2; ++l) cmac(acc, sE[wv][r * N2 + l], sE[wv][l * N2 + c]);
-    __syncthreads();
+    wave_sync();  // every LDS array here is per wavefront
     e = acc;
     if (lane < NN) sE[wv][lane] = e;
-    __syncthreads();
+    wave_sync();  // every LDS array here is per wavefront
   }
   if (act && r < NB) {
     cplx* P = props + (int64_t)k * 3 * NBB;
@@ -626,13 +626,6 @@ __device__ __forceinline__ void load_stream32x2(const float2* p, float2& a, floa
 __device__ __forceinline__ void store_stream(cplx* p, cplx v) {
   kbe_d2v w = {v.x, v.y};
   __builtin_nontemporal_store(w, reinterpret_cast<kbe_d2v*>(p));
-}
-// Keep the compiler from moving LDS accesses of one wavefront across this point (the lanes of
-// a wavefront exchange values through LDS; the hardware executes them in order).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 typedef float2 cplx32;

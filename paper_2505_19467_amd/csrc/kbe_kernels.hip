@@ -1,16 +1,24 @@
 // HIP kernels (gfx950) of the Kadanoff-Baym propagation step.
 //
-//   k_init_*      uncorrelated initial state (Fermi-Dirac density of h0, mu by bisection)
-//   k_hf          mean-field (first-order) self-energy from the local density matrix
-//   k_props       per-k propagators V, Vh, Phi of the midpoint Hamiltonian (scaling and
-//                 squaring of an augmented matrix exponential, one wavefront per k)
-//   k_sigma       second-Born self-energy of a time slice, eq. (2BSE), by k <-> R transforms
-//   k_diag_I      equal-time collision integral I^<(t_m, t_m) and D_m
-//   k_hist_bulk   the history sums of eq. (CI): streams the packed triangle of rows
-//                 0..m-1 once, every stored block feeding its column and its row
-//   k_row         end-point terms, collision row assembly, predictor/corrector update
-//   k_obs         observables of one time slice
-//   k_aux         refresh the column-0 / diagonal copies of the history
+//   k_init_*        uncorrelated initial state (Fermi-Dirac density of h0, mu by bisection)
+//   k_hf            mean-field (first-order) self-energy from the local density matrix
+//   k_props         per-k propagators V, Vh, Phi of the midpoint Hamiltonian (scaling and
+//                   squaring of an augmented matrix exponential, one wavefront per k), with
+//                   the dipole kick of eq. (dipole) in the step after it
+//   k_sigma         second-Born self-energy of a time slice, eq. (2BSE), by k <-> R transforms
+//                   (Hubbard preset)
+//   k_sigma_fwd/ib  the same for the interband preset: lines to real space, then products
+//                   and back
+//   k_sigma_direct  the paper's direct momentum sums for the interband preset (comparison)
+//   k_diag_I        equal-time collision integral I^<(t_m, t_m) and D_m
+//   k_hist_pair, k_hist_bulk(_split) and their FP32 forms
+//                   the history sums of eq. (CI): stream the packed triangle of rows 0..m-1
+//                   once, every stored block feeding its column and its row
+//   k_row           end-point terms (trapezoid or Gregory), collision row assembly,
+//                   predictor/corrector update
+//   k_change_max    the corrector's row change (stopping rule)
+//   k_obs           observables of one time slice
+//   k_aux           refresh the column / diagonal / recent-row copies of the history
 #include "kbe_device.hpp"
 #include "kbe_kernels.hpp"
 

@@ -46,7 +46,10 @@
 //   propagators ..... scipy expm of -i h dt and of the augmented phi_1 matrix
 //   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
 //   dipole kick ..... U = 0 closed form with the kick (the order of the kick and the band
-//                     propagation, its phase and its step), exact N conservation
+//                     propagation, its phase and its step), exact N conservation; first-order
+//                     convergence across the kick with a density-dependent mean field
+//   interband HF .... one electron in a pure state: no self-interaction, so TDHF converges at
+//                     second order to the exact one-electron evolution under h0 - U P_c
 //   time stepping ... U = 0 closed form, exact N conservation, energy balance O(dt^2),
 //                     dt-convergence ratio 4, TDHF limit vs RK4
 //   symmetry ........ full-square mode: the upper triangle propagated on its own with the

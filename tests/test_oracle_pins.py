@@ -330,6 +330,64 @@ def test_tdhf_limit_matches_rk4():
     assert errs[1] < 1e-4 and 3.5 < errs[0] / errs[1] < 4.6, errs
 
 
+def _one_electron_tdhf_errors(pulse, t0_offdiag):
+    """|rho(T) - exact| for the paper model at one k-point with one electron (valence band
+    filled), correlation off, against the exact one-electron evolution under h0 - U P_c (and
+    the kick exp(-i I X) at the grid time nearest t0), for dt = 0.02, 0.01, 0.005, T = 2."""
+    U = 1.3
+    base = inputs.paper_chain(nk=1, nt=400).replace(corr=0, U=U, pulse=pulse)
+    hop = base.hop.copy()
+    hop[0] = hop[0] + t0_offdiag * np.array([[0, 1], [1, 0]])
+    base = base.replace(hop=hop)
+    rho0, _ = O.initial_state(base)
+    assert np.abs(rho0[0] @ rho0[0] - rho0[0]).max() < 1e-12   # a pure one-electron state
+    assert abs(np.trace(rho0[0]) - 1.0) < 1e-12
+    h1 = brute.h0_numpy(base.hop, 1, 1, 0.0)[0] + np.diag([0.0, -U])
+    w, v = np.linalg.eigh(h1)
+
+    def evo(t):
+        return v @ np.diag(np.exp(-1j * w * t)) @ v.conj().T
+    I = pulse.amp
+    K = np.cos(I) * np.eye(2) - 1j * np.sin(I) * np.array([[0, 1], [1, 0]])
+    T = 2.0
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        cfg = base.replace(dt=dt)
+        if pulse.kind == inputs.PULSE_DIPOLE_KICK:
+            tk = int(np.floor(pulse.t0 / dt + 0.5)) * dt
+            Ut = evo(T - tk) @ K @ evo(tk)
+        else:
+            Ut = evo(T)
+        exact = Ut @ rho0[0] @ Ut.conj().T
+        r = O.run(cfg, int(round(T / dt)))
+        errs.append(np.abs(r["rho"][0] - exact).max())
+    return errs
+
+
+def test_interband_hf_is_free_of_self_interaction():
+    """The interband preset's mean field (Hartree U n_c on v and U n_v on c, Fock -U rho_vc)
+    and its -U n_c one-body term, pinned by a property of one electron: for a pure one-electron
+    state the Hartree and Fock fields cancel on the occupied orbital (Sigma^HF[rho] rho = 0), so
+    TDHF must follow the exact one-electron evolution under h0 - U P_c. Started off a stationary
+    state (an off-diagonal on-site block), the scheme's difference from it vanishes at second
+    order in dt; a wrong Fock sign, a misplaced Hartree term or a missing -U n_c term leaves a
+    finite difference."""
+    errs = _one_electron_tdhf_errors(inputs.Pulse(amp=0.0), 0.4)
+    assert errs[2] < 1e-5, errs
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2, errs
+
+
+def test_dipole_kick_step_is_first_order_with_a_mean_field():
+    """The kick's reading: in the step after the kick the mean field is taken at the average
+    of the densities before and after the kick, an O(dt) error confined to that step, so with
+    a density-dependent field the scheme converges at first order across the kick (the
+    one-electron TDHF of the previous test, now driven by the kick): the error halves with dt
+    and still goes to zero."""
+    errs = _one_electron_tdhf_errors(inputs.Pulse(amp=0.6, omega=0.0, t0=0.2, kind=inputs.PULSE_DIPOLE_KICK), 0.0)
+    assert 1.8 < errs[0] / errs[1] < 2.8 and 1.8 < errs[1] / errs[2] < 2.8, errs
+    assert errs[2] < 3e-3, errs
+
+
 def test_corrector_count_changes_at_higher_order():
     """K = 2 corrector passes differ from K = 1 by much less than the O(dt^2) error."""
     cfg = inputs.c1().replace(nkx=4)

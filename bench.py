@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # once that code changes.
 MEASURED_TRAFFIC = {"bytes_per_launch": 1.2684e10, "fetch_over_algorithmic": 1.0215,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "db60bf073be9eed1386378403037ad2c7382f3eb"}
+                    "source_sha1": "ebb743e160c43c45887632667da5464fcca4b8b1"}
 
 
 def _kernel_source_sha1():

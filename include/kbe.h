@@ -110,8 +110,13 @@ enum {
   KBE_PULSE_DIPOLE_KICK = 1  /* eq. (dipole): E(t) = amp delta(t - t0) coupling bands 0 and 1 with d_k = 1
                                 (nb = 2; omega, width, pol unused). Across the delta G(t0+, t') =
                                 K G(t0-, t'), K = cos(amp) 1 - i sin(amp) X (X: ones between bands 0 and
-                                1); the kick sits at the grid time t_{m0} nearest t0 (m0 = floor(t0/dt + 1/2)),
-                                so step m0 + 1 propagates with V K. No vector potential. */
+                                1). The kick acts on the slice at the grid time t_{m0} nearest t0
+                                (m0 = floor(t0/dt + 1/2)) when that slice is committed (kbe_step,
+                                kbe_stage_commit; at m0 = 0 in kbe_create): its observables are the
+                                values just before the kick, its row and density matrix are replaced
+                                by the kicked ones (K G for t' < t_m0, K G K^dag on the equal-time
+                                block), and its self-energy and collision integrals are evaluated
+                                again on the kicked row. No vector potential. */
 };
 typedef struct {
   double amp, omega, t0, width, pol[2];

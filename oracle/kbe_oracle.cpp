@@ -23,6 +23,7 @@
 //                       exponential-midpoint solve of eq. (Green)
 //   dipole pulse ...... eq. (dipole): E(t) = I delta(t - t0), d_k = 1, coupling bands 0 (v)
 //                       and 1 (c), integrated across the delta as the kick exp(-i I sigma_x)
+//                       applied to the completed slice nearest t0
 //
 // Conventions: G^<(t,t') = i<c^dag(t') c(t)>, G^>(t,t') = -i<c(t) c^dag(t')>;
 // G^{<,>}(t',t) = -[G^{<,>}(t,t')]^dag; rho(t) = -i G^<(t,t).
@@ -46,7 +47,7 @@
 //   propagators ..... scipy expm of -i h dt and of the augmented phi_1 matrix
 //   eigh, initial ... numpy eigh; Fermi-Dirac density; mu = 0 by particle-hole symmetry
 //   dipole kick ..... U = 0 closed form with the kick (the order of the kick and the band
-//                     propagation, its phase and its step), exact N conservation; first-order
+//                     propagation, its phase and its slice), exact N conservation; second-order
 //                     convergence across the kick with a density-dependent mean field
 //   interband HF .... one electron in a pure state: no self-interaction, so TDHF converges at
 //                     second order to the exact one-electron evolution under h0 - U P_c
@@ -346,10 +347,11 @@ void hf_field(const Params& p, const Theta<R>& th, const Grid& g, const std::vec
 // The dipole pulse of eq. (dipole), E(t) = I delta(t - t0) with d_k = 1: H_ext(t) = E(t) X,
 // X the matrix with ones between band 0 (v) and band 1 (c). Across the delta the equation of
 // motion reduces to i dG/dt = E(t) X G, so G(t0+, t') = exp(-i I X) G(t0-, t') with
-// exp(-i I X) = cos(I) 1 - i sin(I) X. On the time grid the kick sits at the grid time
-// t_{m0} nearest t0 (m0 = floor(t0 / dt + 1/2)): slice m0 is taken before it, and the step
-// m0 -> m0 + 1 starts from the kicked state, i.e. its homogeneous propagator becomes V K.
-inline int kick_step(const Params& p) { return (int)std::floor(p.t0 / p.dt + 0.5) + 1; }
+// exp(-i I X) = cos(I) 1 - i sin(I) X. On the time grid the kick sits at the grid time t_{m0}
+// nearest t0 (m0 = floor(t0 / dt + 1/2)): once slice m0 is complete (its observables are the
+// values just before the kick), it is replaced by the kicked slice and its self-energy and
+// collision integrals are evaluated again on it (dipole_kick below).
+inline int kick_slice(const Params& p) { return (int)std::floor(p.t0 / p.dt + 0.5); }
 template <class R>
 void kick_matrix(const Theta<R>& th, Cx<R>* K) {
   using std::cos;
@@ -850,12 +852,6 @@ void update_row(State<R>& st, int m, bool corrector) {
     h0(p, g, st.hop.data(), k, Amid, h.data());
     for (int i = 0; i < nbb; ++i) h[i] += hf[i];
     propagators(nb, p.dt, h.data(), V.data(), Vh.data(), Phi.data());
-    if (p.pulse_kind == PULSE_DIPOLE_KICK && m == kick_step(p)) {
-      std::vector<C> K(nbb);
-      kick_matrix(st.th, K.data());
-      mm(nb, V.data(), K.data(), t1.data());
-      V = t1;
-    }
     for (int tp = 0; tp < m; ++tp) {
       const C* Ip = &st.I_prev[((size_t)tp * nk + k) * blk];
       for (int i = 0; i < blk; ++i)
@@ -921,6 +917,40 @@ void step(State<R>& st, int m) {
   if ((int)st.passes.size() <= m) st.passes.resize(m + 1, 0);
   st.passes[m] = passes;
   sigma_and_collision(st, m);
+  st.I_prev = st.I_cur;
+  st.D_prev = st.D_cur;
+  st.rho_prev = st.rho_cur;
+}
+
+// The kick of the dipole pulse on the completed slice m = m0: G(t_m, t') <- K G(t_m, t') for
+// t' < m and K G K^dag on the equal-time block (both components), rho_m <- K rho_m K^dag, then
+// the self-energy and the collision integrals of the kicked slice (they feed the next step's
+// predictor; at m = 0 the integrals are empty).
+template <class R>
+void dipole_kick(State<R>& st, int m) {
+  typedef Cx<R> C;
+  if (st.p.pulse_kind != PULSE_DIPOLE_KICK || m != kick_slice(st.p)) return;
+  int nb = st.g.nb, nbb = st.nbb, nk = st.g.nk;
+  std::vector<C> K(nbb), Kd(nbb), t1(nbb), t2(nbb);
+  kick_matrix(st.th, K.data());
+  adjoint(nb, K.data(), Kd.data());
+  for (int tp = 0; tp <= m; ++tp)
+    for (int k = 0; k < nk; ++k)
+      for (int c = 0; c < 2; ++c) {
+        C* G = st.at(m, tp, k) + c * nbb;
+        mm(nb, K.data(), G, t1.data());
+        if (tp == m) {
+          mm(nb, t1.data(), Kd.data(), t2.data());
+          std::copy(t2.begin(), t2.end(), G);
+        } else {
+          std::copy(t1.begin(), t1.end(), G);
+        }
+      }
+  for (int k = 0; k < nk; ++k) {
+    mm(nb, K.data(), &st.rho_cur[k * nbb], t1.data());
+    mm(nb, t1.data(), Kd.data(), &st.rho_cur[k * nbb]);
+  }
+  if (m > 0) sigma_and_collision(st, m);
   st.I_prev = st.I_cur;
   st.D_prev = st.D_cur;
   st.rho_prev = st.rho_cur;
@@ -1161,9 +1191,11 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
   State<double> st(*p, th, hop);
   init(st);
   if (obs) observables(st, 0, obs);
+  dipole_kick(st, 0);
   for (int m = 1; m <= nsteps; ++m) {
     step(st, m);
     if (obs) observables(st, m, obs + (size_t)m * NOBS);
+    dipole_kick(st, m);
   }
   if (final_row) to_doubles(st.rows[nsteps].data(), st.rows[nsteps].size(), final_row);
   if (hist) {
@@ -1190,12 +1222,14 @@ int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* o
   State<double> st(*p, th, hop);
   init(st);
   if (obs) observables(st, 0, obs);
+  dipole_kick(st, 0);
   if (changes)
     for (int64_t i = 0; i < (int64_t)nsteps * p->n_corr; ++i) changes[i] = -1.0;
   for (int m = 1; m <= nsteps; ++m) {
     size_t c0 = st.changes.size();
     step(st, m);
     if (obs) observables(st, m, obs + (size_t)m * NOBS);
+    dipole_kick(st, m);
     if (changes)
       for (size_t i = c0; i < st.changes.size(); ++i) changes[(size_t)(m - 1) * p->n_corr + (i - c0)] = st.changes[i];
   }
@@ -1231,9 +1265,11 @@ int oracle_tlm_run(const Params* p, const double* hop, int32_t nsteps, double* o
     }
   };
   emit(0);
+  dipole_kick(st, 0);
   for (int m = 1; m <= nsteps; ++m) {
     step(st, m);
     emit(m);
+    dipole_kick(st, m);
   }
   return 0;
 }

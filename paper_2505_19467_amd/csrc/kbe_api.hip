@@ -255,9 +255,6 @@ struct kbe_ctx {
     a.commit = 1;
     a.chg = nullptr;
     a.gR = L.bytes[B_GR] ? buf<cplx>(B_GR) : nullptr;
-    a.kick = 0;
-    a.kick_c = 1.0;
-    a.kick_s = 0.0;
     a.quad = quad;
     a.Ax = a.Ay = 0.0;
     a.polx = pulse.pol[0];
@@ -312,16 +309,24 @@ struct kbe_ctx {
     if (!rc) rc = bulk_timed(a, m);
     return rc;
   }
-  // The dipole pulse E(t) = I delta(t - t0) of eq. (dipole) acts as the kick K = exp(-i I X) at the
-  // grid time t_{m0} nearest t0 (m0 = floor(t0 / dt + 1/2)): step m0 + 1 propagates with V K.
-  int kick_step() const { return (int)std::floor(pulse.t0 / cfg.dt + 0.5) + 1; }
+  // The dipole pulse E(t) = I delta(t - t0) of eq. (dipole) acts as the kick K = exp(-i I X) on the
+  // slice at the grid time t_{m0} nearest t0 (m0 = floor(t0 / dt + 1/2)): once the slice is
+  // complete (its observables are the values just before the kick) the row and rho_m0 are
+  // kicked and the slice's self-energy and collision integrals are evaluated again on the kicked
+  // row; they feed the next step's predictor (at m0 = 0 the integrals are empty).
+  int kick_slice() const { return (int)std::floor(pulse.t0 / cfg.dt + 0.5); }
+  int dipole_kick(int m) {
+    if (pulse.kind != KBE_PULSE_DIPOLE_KICK || m != kick_slice()) return KBE_OK;
+    LaunchArgs a = args();
+    int rc = check(kbe::launch_kick(L.d, a, m, std::cos(pulse.amp), std::sin(pulse.amp),
+                                    m == 0 ? a.rho_prev : a.rho_cur, st),
+                   "dipole-kick launch");
+    if (!rc && m > 0) rc = collision_parts(a, m);
+    if (!rc && m > 0) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_EVAL, st), "collision-row launch");
+    return rc;
+  }
   int props(LaunchArgs& a, int m, int mode) {
     set_A(a, (m - 0.5) * cfg.dt);
-    if (pulse.kind == KBE_PULSE_DIPOLE_KICK && m == kick_step()) {
-      a.kick = 1;
-      a.kick_c = std::cos(pulse.amp);
-      a.kick_s = std::sin(pulse.amp);
-    }
     int rc = check(kbe::launch_hf(L.d, a, mode == 0 ? 0.0 : 0.5, st), "mean-field launch");
     if (!rc) rc = check(kbe::launch_props(L.d, a, st), "propagator launch");
     return rc;
@@ -372,6 +377,7 @@ struct kbe_ctx {
     if (!rc) rc = collision_parts(a, m);
     if (!rc) rc = check(kbe::launch_row(L.d, a, m, KBE_ROW_EVAL, st), "collision-row launch");
     if (!rc) rc = observe(m);
+    if (!rc) rc = dipole_kick(m);
     if (rc) return rc;
     cur ^= 1;
     step = m;
@@ -596,6 +602,7 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
     rc = c->check(kbe::launch_init(d, a, c->st), "initial-state launch");
   }
   if (!rc) rc = c->observe(0);
+  if (!rc) rc = c->dipole_kick(0);
   if (!rc) rc = c->check(hipStreamSynchronize(c->st), "initial state");
   if (rc) {
     delete c;
@@ -735,6 +742,8 @@ int kbe_stage_observables(kbe_ctx* ctx, int32_t m) {
 
 int kbe_stage_commit(kbe_ctx* ctx, int32_t m) {
   int rc = check_m(ctx, m, 0);
+  if (rc) return rc;
+  rc = ctx->dipole_kick(m);
   if (rc) return rc;
   ctx->cur ^= 1;
   ctx->step = m;

@@ -3,8 +3,8 @@
 //   k_init_*        uncorrelated initial state (Fermi-Dirac density of h0, mu by bisection)
 //   k_hf            mean-field (first-order) self-energy from the local density matrix
 //   k_props         per-k propagators V, Vh, Phi of the midpoint Hamiltonian (scaling and
-//                   squaring of an augmented matrix exponential, one wavefront per k), with
-//                   the dipole kick of eq. (dipole) in the step after it
+//                   squaring of an augmented matrix exponential, one wavefront per k)
+//   k_kick_row      the dipole kick of eq. (dipole) on the completed slice nearest t0
 //   k_sigma         second-Born self-energy of a time slice, eq. (2BSE), by k <-> R transforms
 //                   (Hubbard preset)
 //   k_sigma_fwd/ib  the same for the interband preset: lines to real space, then products
@@ -200,11 +200,9 @@ __global__ __launch_bounds__(256) void k_hf(Dims d, const cplx* __restrict__ rho
 // has exp(M) = [[V, dt phi1(-i hbar dt)], [0, 1]], so Phi = -i * (top-right block).
 // exp(M / 2^s) by a degree-16 Taylor polynomial (Horner), ||M / 2^s||_F <= 1/4, then s
 // squarings; the square before the last is exp(M/2), whose top-left block is Vh.
-// With kick = 1 (the step after a dipole kick, eq. (dipole)) V is returned as V K.
 template <int NB>
 __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ hop, const cplx* __restrict__ hf,
-                                               double Ax, double Ay, double dt, int kick, double kc, double ks,
-                                               cplx* __restrict__ props) {
+                                               double Ax, double Ay, double dt, cplx* __restrict__ props) {
   constexpr int N2 = 2 * NB, NN = N2 * N2, NBB = NB * NB;
   __shared__ cplx sX[4][NN], sE[4][NN];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -259,12 +257,7 @@ __global__ __launch_bounds__(256) void k_props(Dims d, const cplx* __restrict__ 
   if (act && r < NB) {
     cplx* P = props + (int64_t)k * 3 * NBB;
     if (c < NB) {
-      cplx v = e;
-      if constexpr (NB == 2) {
-        if (kick)  // V K, K = kc 1 - i ks X: (V K)_rc = kc V_rc - i ks V_r,1-c
-          v = csub(cscal(e, kc), cmuli(cscal(sE[wv][r * N2 + (1 - c)], ks)));
-      }
-      P[r * NB + c] = v;              // V
+      P[r * NB + c] = e;              // V
       P[NBB + r * NB + c] = half;     // Vh
     } else {
       P[2 * NBB + r * NB + (c - NB)] = cneg(cmuli(e));  // Phi = -i * top-right
@@ -1796,6 +1789,62 @@ __global__ __launch_bounds__(1024) void k_change_max(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// ------------------------------------------------------------------ dipole kick
+// The kick of the dipole pulse of eq. (dipole) on the completed slice m: G(t_m, t') <- K G(t_m, t')
+// for t' < m and K G K^dag on the equal-time block (both components), rho_m <- K rho_m K^dag,
+// K = kc 1 - i ks X (X: ones between bands 0 and 1; nb = 2). Thread per (k, t'); the FP64
+// working copy of the row is the source, and every copy of the row is rewritten (packed
+// history, working copy, column and diagonal copies). rho goes to rhoX and rhoY (both density
+// buffers at t = 0).
+template <int NB>
+__global__ __launch_bounds__(256) void k_kick_row(Dims d, void* __restrict__ hist, cplx* __restrict__ row64,
+                                                  cplx* __restrict__ col0, cplx* __restrict__ diag, cplx* rhoX,
+                                                  cplx* rhoY, int m, double kc, double ks) {
+  static_assert(NB == 2, "the dipole kick couples the two bands of the paper's model");
+  int k = blockIdx.y;
+  int tp = blockIdx.x * 256 + threadIdx.x;
+  if (tp > m) return;
+  // (K G)_ab = kc G_ab - i ks G_{1-a, b};  (T K^dag)_ab = kc T_ab + i ks T_{a, 1-b}
+  auto kick = [&](const cplx* G, cplx* out, bool both_sides) {
+    cplx T[4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) T[a * 2 + b] = csub(cscal(G[a * 2 + b], kc), cmuli(cscal(G[(1 - a) * 2 + b], ks)));
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        out[a * 2 + b] = both_sides ? cadd(cscal(T[a * 2 + b], kc), cmuli(cscal(T[a * 2 + 1 - b], ks))) : T[a * 2 + b];
+  };
+#pragma unroll
+  for (int sc = 0; sc < 2; ++sc) {
+    cplx G[4], R[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) G[e] = row64[row64_idx(d, m, k, sc * 4 + e, tp)];
+    kick(G, R, tp == m);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int c = sc * 4 + e;
+      row64[row64_idx(d, m, k, c, tp)] = R[e];
+      commit_store(d, hist, k, c, m, tp, R[e]);
+      if (tp < d.qp) col0[colq_idx(d, k, c, m, tp)] = R[e];
+      if (m - tp < d.qp) diag[band_idx(d, k, c, m, m - tp)] = R[e];
+    }
+  }
+  if (tp == m) {
+    cplx r[4], R[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = rhoX[(int64_t)k * 4 + e];
+    kick(r, R, true);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      rhoX[(int64_t)k * 4 + e] = R[e];
+      rhoY[(int64_t)k * 4 + e] = R[e];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ observables
 template <int NB>
 __global__ __launch_bounds__(256) void k_obs(Dims d, const cplx* __restrict__ hop, const cplx* __restrict__ rho,
@@ -1955,7 +2004,7 @@ struct Launch {
   }
   static hipError_t props(const Dims& d, const LaunchArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_props<NB>, dim3((d.nk + 3) / 4), dim3(256), 0, st, d, a.hop, (const cplx*)a.hfbuf,
-                       a.Ax, a.Ay, a.dt, a.kick, a.kick_c, a.kick_s, a.props);
+                       a.Ax, a.Ay, a.dt, a.props);
     return hipGetLastError();
   }
   static hipError_t sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
@@ -2083,6 +2132,13 @@ hipError_t launch_hf(const Dims& d, const LaunchArgs& a, double wb, hipStream_t 
 hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st) { KBE_DISPATCH(d.nb, props(d, a, st)); }
 hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
   KBE_DISPATCH(d.nb, sigma(d, a, m, st));
+}
+hipError_t launch_kick(const Dims& d, const LaunchArgs& a, int m, double kc, double ks, cplx* rho_other,
+                       hipStream_t st) {
+  if (d.nb != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_kick_row<2>, dim3((m + 1 + 255) / 256, d.nk), dim3(256), 0, st, d, a.hist, a.row64, a.col0,
+                     a.diag, a.rho_cur, rho_other, m, kc, ks);
+  return hipGetLastError();
 }
 hipError_t launch_sigma_direct(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
   size_t shm = (size_t)(6 * d.nk + d.nk / 8) * sizeof(cplx);

@@ -45,8 +45,6 @@ struct LaunchArgs {
   cplx* gR;        // interband self-energy: real-space lines of row m, [t_j][comp][ab][R] (else null)
   QuadW quad;      // quadrature weights of eq. (CI)
   double Ax, Ay;  // A(t) * pol for the launch at hand
-  int kick;       // 1: the propagators of this step carry the dipole kick, V -> V K
-  double kick_c, kick_s;  // K = kick_c 1 - i kick_s X (X: ones between bands 0 and 1)
   double polx, poly;  // pulse polarisation
   double dt, U, UU, temp, target, spin;
   int interaction, hf, corr;
@@ -59,6 +57,9 @@ hipError_t launch_props(const Dims& d, const LaunchArgs& a, hipStream_t st);
 hipError_t launch_sigma(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 // the paper's direct-sum self-energy (interband preset, chain with even n <= 1024)
 hipError_t launch_sigma_direct(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+// the dipole kick on the completed slice m (nb = 2): the row's copies and rho_cur (and rho_other)
+hipError_t launch_kick(const Dims& d, const LaunchArgs& a, int m, double kc, double ks, cplx* rho_other,
+                       hipStream_t st);
 hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st);

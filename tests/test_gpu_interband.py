@@ -179,3 +179,28 @@ def test_sigma_direct_refuses_other_shapes(K):
         with pytest.raises(K.KbeError):
             S.stage_sigma_direct(0)
         S.close()
+
+
+def test_stage_api_with_kick_composes_to_step(K):
+    """With the dipole kick the stage entry points still reproduce kbe_step bit for bit: the
+    commit of the kick slice applies the kick and evaluates the slice again."""
+    cfg = _interband(16, 1, 12, pulse=inputs.Pulse(amp=0.4, omega=0.0, t0=0.1, kind=inputs.PULSE_DIPOLE_KICK))
+    n = 10
+    A = K.System(cfg, nt_max=n)
+    A.step(n)
+    B = K.System(cfg, nt_max=n)
+    for m in range(1, n + 1):
+        B.stage_propagators(m, 0)
+        B.stage_update(m, 0)
+        for _ in range(cfg.n_corr):
+            B.stage_sigma(m)
+            B.stage_collision(m)
+            B.stage_propagators(m, 1)
+            B.stage_update(m, 1)
+        B.stage_sigma(m)
+        B.stage_collision(m)
+        B.stage_observables(m)
+        B.stage_commit(m)
+    assert np.array_equal(A.observables(), B.observables())
+    assert np.array_equal(A.history_row(n).cpu().numpy(), B.history_row(n).cpu().numpy())
+    assert np.array_equal(A.history_row(5).cpu().numpy(), B.history_row(5).cpu().numpy())

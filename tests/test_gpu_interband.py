@@ -204,3 +204,14 @@ def test_stage_api_with_kick_composes_to_step(K):
     assert np.array_equal(A.observables(), B.observables())
     assert np.array_equal(A.history_row(n).cpu().numpy(), B.history_row(n).cpu().numpy())
     assert np.array_equal(A.history_row(5).cpu().numpy(), B.history_row(5).cpu().numpy())
+
+
+def test_adjoint_refuses_dipole_kick(K):
+    """The reverse sweep covers the Peierls pulse only: a Hubbard context driven by the dipole
+    kick is refused as well."""
+    cfg = inputs.c1().replace(pulse=inputs.Pulse(amp=0.3, omega=0.0, t0=0.04, kind=inputs.PULSE_DIPOLE_KICK))
+    S = K.System(cfg, nt_max=6)
+    S.step(4)
+    with pytest.raises(K.KbeError):
+        S.adjoint_gradient("n_band1")
+    S.close()

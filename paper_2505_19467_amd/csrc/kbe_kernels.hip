@@ -1428,48 +1428,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   for (int cb = 64 * s; cb < m; cb += 32) {  // the same chunks in every wavefront
     const int rb = cb + 16 * rg;
     cplx* st = stg[buf][rg][h];
-    for (int i = 0; i < 16; ++i) {
-      const int j = rb + i;
-      if (j >= m) break;
-      bool v = colv && tp <= j;
-      const cplx32* row = hk + 64 * (int64_t)C * j;
-      cplx32 G[NBB];
+    // groups of 16 rows past the strip's first 64 rows and below m need no masks (this
+    // kernel is bound by the vector ALU; the FP64 kernel keeps one path, a second one would
+    // not fit its registers)
+    auto rows16 = [&](auto tag) {
+      constexpr bool MASKED = decltype(tag)::value;
+      for (int i = 0; i < 16; ++i) {
+        const int j = rb + i;
+        if (MASKED && j >= m) break;
+        bool v = MASKED ? (colv && tp <= j) : true;
+        const cplx32* row = hk + 64 * (int64_t)C * j;
+        cplx32 G[NBB];
 #pragma unroll
-      for (int p = 0; p < NBB / 2; ++p) {
-        if (v) {
-          load_stream32x2(row + 128 * p, G[2 * p], G[2 * p + 1]);
-        } else {
-          G[2 * p] = make_float2(0.f, 0.f);
-          G[2 * p + 1] = make_float2(0.f, 0.f);
+        for (int p = 0; p < NBB / 2; ++p) {
+          if (v) {
+            load_stream32x2(row + 128 * p, G[2 * p], G[2 * p + 1]);
+          } else {
+            G[2 * p] = make_float2(0.f, 0.f);
+            G[2 * p + 1] = make_float2(0.f, 0.f);
+          }
+        }
+        bool rv = MASKED ? tp < j : true;
+        float x[NB][2 * NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          cplx32 SRa[NB];
+#pragma unroll
+          for (int l = 0; l < NB; ++l) SRa[l] = to32(sk[(2 * NBB + a * NB + l) * d.Tp + j]);
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) cmac32(acc32[a * NB + b], SRa[l], G[l * NB + b]);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            cplx32 t = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) cmacc32(t, sS[h][a * NB + l][lane], G[b * NB + l]);
+            x[a][2 * b] = rv ? sgn * t.x : 0.f;
+            x[a][2 * b + 1] = rv ? sgn * t.y : 0.f;
+          }
+        }
+        reduce_rows32<NB>(x);
+        int ra = reduced_row<NB>(lane);
+        if (ra >= 0) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk((double)x[0][2 * b], (double)x[0][2 * b + 1]);
         }
       }
-      bool rv = tp < j;
-      float x[NB][2 * NB];
-#pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        cplx32 SRa[NB];
-#pragma unroll
-        for (int l = 0; l < NB; ++l) SRa[l] = to32(sk[(2 * NBB + a * NB + l) * d.Tp + j]);
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-          for (int l = 0; l < NB; ++l) cmac32(acc32[a * NB + b], SRa[l], G[l * NB + b]);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          cplx32 t = make_float2(0.f, 0.f);
-#pragma unroll
-          for (int l = 0; l < NB; ++l) cmacc32(t, sS[h][a * NB + l][lane], G[b * NB + l]);
-          x[a][2 * b] = rv ? sgn * t.x : 0.f;
-          x[a][2 * b + 1] = rv ? sgn * t.y : 0.f;
-        }
-      }
-      reduce_rows32<NB>(x);
-      int ra = reduced_row<NB>(lane);
-      if (ra >= 0) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk((double)x[0][2 * b], (double)x[0][2 * b + 1]);
-      }
-    }
+    };
+    if (rb >= 64 * s + 64 && rb + 16 <= m)
+      rows16(BoolTag<false>{});
+    else
+      rows16(BoolTag<true>{});
 #pragma unroll
     for (int e = 0; e < NBB; ++e) {
       acc[e].x += (double)acc32[e].x;

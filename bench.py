@@ -242,7 +242,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 8}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the k-point sharding across GPUs is described in the design notes, not implemented.",
               file=sys.stderr)
         sys.exit(2)

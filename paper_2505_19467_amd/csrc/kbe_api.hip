@@ -615,7 +615,7 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
 int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0) return KBE_ERR_INVALID_ARG;
   if (ctx->frozen) return ctx->fail(KBE_ERR_STATE, "the context's buffers were used by a reverse sweep");
-  if (ctx->step + nsteps > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_STATE, "step index would pass nt_max");
+  if ((int64_t)ctx->step + nsteps > ctx->cfg.nt_max) return ctx->fail(KBE_ERR_STATE, "step index would pass nt_max");
   for (int i = 0; i < nsteps; ++i) {
     int rc = ctx->one_step();
     if (rc) return rc;
@@ -626,7 +626,7 @@ int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
 int32_t kbe_current_step(const kbe_ctx* ctx) { return ctx ? ctx->step : -1; }
 
 int kbe_corrector_log(const kbe_ctx* ctx, int32_t first, int32_t count, int32_t* passes, double* changes) {
-  if (!ctx || first < 0 || count < 0 || first + count > ctx->cfg.nt_max + 1) return KBE_ERR_INVALID_ARG;
+  if (!ctx || first < 0 || count < 0 || (int64_t)first + count > (int64_t)ctx->cfg.nt_max + 1) return KBE_ERR_INVALID_ARG;
   const int K = ctx->cfg.n_corr > 0 ? ctx->cfg.n_corr : 1;
   for (int i = 0; i < count; ++i) {
     int m = first + i;
@@ -638,7 +638,7 @@ int kbe_corrector_log(const kbe_ctx* ctx, int32_t first, int32_t count, int32_t*
 }
 
 int kbe_observables(kbe_ctx* ctx, int32_t first, int32_t count, double* host_out) {
-  if (!ctx || !host_out || first < 0 || count < 0 || first + count > ctx->cfg.nt_max + 1)
+  if (!ctx || !host_out || first < 0 || count < 0 || (int64_t)first + count > (int64_t)ctx->cfg.nt_max + 1)
     return KBE_ERR_INVALID_ARG;
   int rc = ctx->check(hipStreamSynchronize(ctx->st), "stream synchronisation");
   if (rc) return rc;

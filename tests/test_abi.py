@@ -179,3 +179,60 @@ def test_interband_chain_and_pulse_validation():
         rc = kbe._lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  ctypes.byref(pu), fake, hb, fake, wb, fake, ob, None, ctypes.byref(ctx))
         assert rc == -1 and not ctx.value
+
+
+def _header_enums():
+    """name -> value of every enumerator in include/kbe.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", text, flags=re.S):
+        for name, value in re.findall(r"\b(KBE_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            out[name] = int(value)
+    return out
+
+
+def _header_struct_fields(typedef):
+    """[(c type, field name)] of a typedef'd struct in include/kbe.h, in declaration order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + typedef + r"\s*;", text, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for n in names.split(","):
+            fields.append((ctype, n.strip()))
+    return fields
+
+
+def test_binding_constants_match_header():
+    from paper_2505_19467_amd import kbe
+    e = _header_enums()
+    assert kbe.KBE_OK == e["KBE_OK"]
+    assert {v: k for k, v in kbe.ERRORS.items()} == {k: v for k, v in e.items() if k.startswith("KBE_ERR_")}
+    assert kbe.NOBS == e["KBE_NOBS"]
+    for col, name in [("t", "KBE_OBS_T"), ("N", "KBE_OBS_N"), ("Ekin", "KBE_OBS_EKIN"), ("EHF", "KBE_OBS_EHF"),
+                      ("Ecorr", "KBE_OBS_ECORR"), ("Etot", "KBE_OBS_ETOT"), ("Jx", "KBE_OBS_JX"), ("Jy", "KBE_OBS_JY"),
+                      ("A", "KBE_OBS_A"), ("n_orb0", "KBE_OBS_NORB"), ("n_band0", "KBE_OBS_NBAND")]:
+        assert kbe.OBS[col] == e[name], col
+    for n in ("SIGMA", "I_PREV", "I_CUR", "RHO_PREV", "RHO_CUR", "D_PREV", "D_CUR", "PROP", "COL0", "DIAG", "ROWS"):
+        assert getattr(kbe, "BUF_" + n) == e["KBE_BUF_" + n], n
+    assert (inputs.PRECISION_FP64, inputs.PRECISION_FP32) == (e["KBE_FP64"], e["KBE_FP32"])
+    assert (inputs.INTERACTION_HUBBARD, inputs.INTERACTION_INTERBAND) == (e["KBE_INT_HUBBARD"], e["KBE_INT_INTERBAND"])
+    assert (inputs.PULSE_PEIERLS, inputs.PULSE_DIPOLE_KICK) == (e["KBE_PULSE_PEIERLS"], e["KBE_PULSE_DIPOLE_KICK"])
+
+
+@pytest.mark.parametrize("typedef,cls", [("kbe_config", "KbeConfig"), ("kbe_pulse", "KbePulse")])
+def test_binding_structs_match_header(typedef, cls):
+    """Field names, order and C types of the ctypes mirrors equal the header's structs."""
+    from paper_2505_19467_amd import kbe
+    ctypes_of = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    want = []
+    for ctype, name in _header_struct_fields(typedef):
+        m = re.fullmatch(r"(\w+)\[(\d+)\]", name)
+        want.append((m.group(1), ctypes_of[ctype] * int(m.group(2))) if m else (name, ctypes_of[ctype]))
+    got = getattr(kbe, cls)._fields_
+    assert [n for n, _ in got] == [n for n, _ in want]
+    for (n, t), (_, w) in zip(got, want):
+        assert ctypes.sizeof(t) == ctypes.sizeof(w) and getattr(t, "_type_", t) == getattr(w, "_type_", w), n

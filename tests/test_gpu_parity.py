@@ -236,6 +236,24 @@ def test_errors_are_reported(K):
         S.stage_sigma(99)
 
 
+def test_range_checks_take_the_largest_counts(K):
+    """Step and slice counts near INT32_MAX are refused before any work is queued (the range
+    checks add them to the current step or first slice in 64 bits)."""
+    import ctypes
+    big = 2**31 - 1
+    S = K.System(inputs.c1().replace(nkx=4), nt_max=3)
+    S.step(1)
+    assert K._lib.kbe_step(S._ctx, big) == -4
+    assert K._lib.kbe_current_step(S._ctx) == 1
+    out = np.zeros(4 * K.NOBS)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert K._lib.kbe_observables(S._ctx, 1, big, ptr) == -1
+    assert K._lib.kbe_corrector_log(S._ctx, 1, big, None, None) == -1
+    S.step(2)
+    assert np.all(np.isfinite(S.observables()))
+    S.close()
+
+
 def test_largest_history_length(K):
     """nt_max = 8192, the largest history length the library accepts, on a 2-point chain with
     nb = 1: 40 propagated steps against the oracle, then the history sums of the last row

@@ -192,8 +192,9 @@ const char* kbe_last_error(const kbe_ctx* ctx);
  * time slice t_m. kbe_step is the composition
  *   propagators(m, 0); update(m, PREDICT);
  *   K x { sigma(m); collision(m); propagators(m, 1); update(m, CORRECT) };
- *   sigma(m); collision(m); commit(m); observables(m)
- * (the corrector's collision and update are fused inside kbe_step).
+ *   sigma(m); collision(m); observables(m); commit(m)
+ * (the corrector's collision and update are fused inside kbe_step). The observables come
+ * before the commit, which applies the dipole kick on its slice.
  * ------------------------------------------------------------------------------------- */
 
 /* Sub-buffers of the workspace (kbe_buffer). */
@@ -245,7 +246,9 @@ int kbe_stage_update(kbe_ctx* ctx, int32_t m, int32_t mode);
 int kbe_stage_observables(kbe_ctx* ctx, int32_t m);
 
 /* Make step m the current step and swap the _PREV/_CUR roles as kbe_step does after
- * its evaluation pass. */
+ * its evaluation pass and observables. If m is the slice of a dipole kick
+ * (KBE_PULSE_DIPOLE_KICK), first apply the kick to row m and rho_m, and evaluate row m's
+ * self-energy and collision integrals again on the kicked row. */
 int kbe_stage_commit(kbe_ctx* ctx, int32_t m);
 
 /* Refresh the FP64 working copies (COL0, DIAG, ROWS for rows m-1 and m) from history rows

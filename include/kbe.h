@@ -246,7 +246,7 @@ int kbe_stage_update(kbe_ctx* ctx, int32_t m, int32_t mode);
 int kbe_stage_observables(kbe_ctx* ctx, int32_t m);
 
 /* Make step m the current step and swap the _PREV/_CUR roles as kbe_step does after
- * its evaluation pass and observables. If m is the slice of a dipole kick
+ * its evaluation pass and observables; m must be the current step + 1 (KBE_ERR_STATE). If m is the slice of a dipole kick
  * (KBE_PULSE_DIPOLE_KICK), first apply the kick to row m and rho_m, and evaluate row m's
  * self-energy and collision integrals again on the kicked row. */
 int kbe_stage_commit(kbe_ctx* ctx, int32_t m);

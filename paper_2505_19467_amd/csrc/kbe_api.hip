@@ -741,8 +741,9 @@ int kbe_stage_observables(kbe_ctx* ctx, int32_t m) {
 }
 
 int kbe_stage_commit(kbe_ctx* ctx, int32_t m) {
-  int rc = check_m(ctx, m, 0);
+  int rc = check_m(ctx, m, 1);
   if (rc) return rc;
+  if (m != ctx->step + 1) return ctx->fail(KBE_ERR_STATE, "commit(m) must follow step m - 1");
   rc = ctx->dipole_kick(m);
   if (rc) return rc;
   ctx->cur ^= 1;

@@ -234,6 +234,16 @@ def test_errors_are_reported(K):
         S.step(1)
     with pytest.raises(K.KbeError):
         S.stage_sigma(99)
+    S.close()
+    S = K.System(cfg, nt_max=4)
+    S.step(1)
+    for bad in (1, 3):                # commits follow the last completed step
+        with pytest.raises(K.KbeError):
+            S.stage_commit(bad)
+    assert S.current_step == 1
+    S.step(3)
+    assert np.all(np.isfinite(S.observables()))
+    S.close()
 
 
 def test_range_checks_take_the_largest_counts(K):

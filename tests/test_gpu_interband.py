@@ -136,7 +136,7 @@ def test_adjoint_refuses_paper_model(K):
 
 
 # ---------------------------------------------------------------- the paper's direct sums
-@pytest.mark.parametrize("nkx,m", [(16, 3), (64, 5), (104, 2), (1024, 1)])
+@pytest.mark.parametrize("nkx,m", [(8, 0), (16, 3), (24, 4), (64, 5), (104, 2), (1024, 1)])
 def test_sigma_direct_parity(K, nkx, m):
     """kbe_stage_sigma_direct (eq. (polarizability)/(kernel2) and Alg. "contraction2") gives the
     oracle's self-energy, and the transform route's to rounding."""

@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
 # (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
 # once that code changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2685e10, "fetch_over_algorithmic": 1.0215,
+MEASURED_TRAFFIC = {"bytes_per_launch": 1.2684e10, "fetch_over_algorithmic": 1.0215,
                     "write_over_algorithmic": 0.0077,
-                    "source_sha1": "a5310f87503ce3e42cf5313a65dfbda25717033c"}
+                    "source_sha1": "217d5f8b3496bdd2b4b7f7bb7ba9f39116b03ba6"}
 
 
 def _kernel_source_sha1():

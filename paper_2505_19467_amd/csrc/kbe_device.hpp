@@ -559,22 +559,25 @@ __device__ __forceinline__ void axis_fft_pow2(cplx* __restrict__ x0, cplx* __res
   int lg = 0;
   while ((1 << lg) < n) ++lg;
   cplx *s0 = x0, *s1 = x1, *d0 = t0, *d1 = t1;
-  int Ns = 1;
+  // Ns, R and n are powers of two: the index arithmetic below is shifts and masks
+  int lgNs = 0;
   int rem = lg;
   while (rem > 0) {
-    const int R = (rem & 1) ? 2 : 4;  // the radix-2 stage first, then radix 4
-    rem -= (R == 2) ? 1 : 2;
+    const int lgR = (rem & 1) ? 1 : 2;  // the radix-2 stage first, then radix 4
+    const int R = 1 << lgR, Ns = 1 << lgNs;
+    rem -= lgR;
     const bool last = rem == 0;
     const double sc = last ? scale : 1.0;
-    const int nb = n / R;           // butterflies per array
+    const int nb = n >> lgR;                // butterflies per array
+    const int lgu = lg - lgNs - lgR;        // root step of a butterfly: n / (Ns R) per unit of j mod Ns
     for (int it = threadIdx.x; it < 2 * nb; it += blockDim.x) {
       const int arr = it >= nb;
       const int j = it - arr * nb;
       const cplx* src = arr ? s1 : s0;
       cplx* dst = arr ? d1 : d0;
-      const int jm = j % Ns;
-      const int ustep = jm * (n / (Ns * R));
-      const int base = (j / Ns) * Ns * R + jm;
+      const int jm = j & (Ns - 1);
+      const int ustep = jm << lgu;
+      const int base = ((j >> lgNs) << (lgNs + lgR)) + jm;
       if (R == 2) {
         cplx a = src[j], b = cmul(src[j + nb], root(tw, ustep, sgn));
         dst[base] = cscal(cadd(a, b), sc);
@@ -582,8 +585,8 @@ __device__ __forceinline__ void axis_fft_pow2(cplx* __restrict__ x0, cplx* __res
       } else {
         cplx v0 = src[j];
         cplx v1 = cmul(src[j + nb], root(tw, ustep, sgn));
-        cplx v2 = cmul(src[j + 2 * nb], root(tw, (2 * ustep) % n, sgn));
-        cplx v3 = cmul(src[j + 3 * nb], root(tw, (3 * ustep) % n, sgn));
+        cplx v2 = cmul(src[j + 2 * nb], root(tw, (2 * ustep) & (n - 1), sgn));
+        cplx v3 = cmul(src[j + 3 * nb], root(tw, (3 * ustep) & (n - 1), sgn));
         cplx s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = csub(v1, v3);
         cplx id13 = sgn > 0 ? cmuli(d13) : cneg(cmuli(d13));  // (sgn i) (v1 - v3)
         dst[base] = cscal(cadd(s02, s13), sc);
@@ -593,7 +596,7 @@ __device__ __forceinline__ void axis_fft_pow2(cplx* __restrict__ x0, cplx* __res
       }
     }
     __syncthreads();
-    Ns *= R;
+    lgNs += lgR;
     cplx* q0 = s0;
     cplx* q1 = s1;
     s0 = d0;

@@ -8,10 +8,12 @@ Synthetic, seeded input; no dataset.
 A "step" is one KBE time step: self-energy slice, history sums, end points and the
 predictor-corrector update of G(t_m, .) and rho_m, and the observables.
 
-Prints one JSON line. ``--steps K`` times K consecutive steps starting at t = 0 (the
-default K = nt is the whole trajectory, the configuration the metric is quoted on);
-``--warmup W`` steps are run first on the same buffers and then discarded (the context
-is re-created at t = 0 before the timed region).
+Prints one JSON line. Every run propagates the whole trajectory (nt steps from t = 0).
+``--steps K`` times its LAST K steps, nt - K + 1 .. nt, which run against the full-length
+history (steps 1 .. nt - K run first, untimed for ``value``); the default K = nt times the
+whole trajectory. The whole trajectory's steps/s and history-sum bandwidth are reported
+beside the timed window in every case. ``--warmup W`` steps are run first on the same
+buffers and then discarded (the context is re-created at t = 0 before the trajectory).
 """
 from __future__ import annotations
 
@@ -28,14 +30,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
-# HBM traffic of the FP64 history-sum kernel per launch, averaged over the 2000 launches of
-# this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by what the same counters
-# read for a plain 1 GiB device copy (x2.000 and x1.000); summary and commands in
-# profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured on
-# (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
-# once that code changes.
-MEASURED_TRAFFIC = {"bytes_per_launch": 1.2684e10, "fetch_over_algorithmic": 1.0215,
-                    "write_over_algorithmic": 0.0077,
+# HBM traffic of the FP64 history-sum kernel per launch: rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# scaled by what the same counters read for a plain 1 GiB device copy (x2.000 and x1.000), averaged
+# over the launches of one timed window, keyed by (workload, nt, timed steps K); summary and
+# commands in profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured
+# on (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
+# once that code changes, or for a window that was not measured.
+MEASURED_TRAFFIC = {"bytes_per_launch": {("c2", 1000, 1000): 1.2684e10},
                     "source_sha1": "217d5f8b3496bdd2b4b7f7bb7ba9f39116b03ba6"}
 
 
@@ -88,23 +89,27 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(cfg, sample_steps: int, one_core_steps: int):
+def cpu_baseline(cfg, sample_steps: int, same_steps: int):
     """The CPU oracle (plain FP64 C++, OpenMP over k) on the first ``sample_steps`` steps of the
-    same workload with all its threads, and on the first ``one_core_steps`` with one thread."""
+    same workload with all its threads; then the first ``same_steps`` steps with all threads and
+    with one thread (one sample for both rates)."""
     from oracle import oracle as O
     O.build()
     threads = O.max_threads()
     t0 = time.perf_counter()
     O.run(cfg, sample_steps)
     dt = time.perf_counter() - t0
-    dt1 = None
-    if one_core_steps > 0:
+    dt_same = dt1 = None
+    if same_steps > 0:
+        t0 = time.perf_counter()
+        O.run(cfg, same_steps)
+        dt_same = time.perf_counter() - t0
         O.set_threads(1)
         t0 = time.perf_counter()
-        O.run(cfg, one_core_steps)
+        O.run(cfg, same_steps)
         dt1 = time.perf_counter() - t0
         O.set_threads(threads)
-    return dt, threads, dt1
+    return dt, threads, dt_same, dt1
 
 
 def adjoint_leg(torch, inputs, kbe):
@@ -217,6 +222,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=120, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-sample-one-core", type=int, default=40,
+                    help="oracle steps timed with all threads and with one (the core-scaling sample)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
     ap.add_argument("--no-adaptive", action="store_true",
@@ -260,22 +267,40 @@ def main():
     print(f"[bench] workload {cfg.name}: nk={cfg.nk} nb={cfg.nb} nt={cfg.nt} dt={cfg.dt} K={cfg.n_corr}; "
           f"timing {K} steps after {W} warm-up steps", file=sys.stderr, flush=True)
 
+    kt = not args.no_kernel_timing
+
     def run(c):
+        """The whole trajectory of ``c``; steps nt - K + 1 .. nt are the timed window."""
         S = kbe.System(c)
         gb = S.history.numel() * S.history.element_size() / 1e9
         if W:
             S.step(W)
             S.observables()
         S.reset()   # fresh context on the same buffers: t = 0 again
-        S.timing(not args.no_kernel_timing)
+        pre = c.nt - K
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if pre:
+            S.timing(kt)
+            S.step(pre)
+            torch.cuda.synchronize()
+        t_pre = time.perf_counter() - t0
+        pl, pms, pbytes = S.timing_query() if (pre and kt) else (0, 0.0, 0.0)
+        S.timing(kt)   # the window's history-sum launches only
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         S.step(K)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         launches, kms, kbytes = S.timing_query()
-        obs = S.observables(0, K + 1)
-        return S, dict(elapsed=el, launches=launches, kms=kms, kbytes=kbytes, obs=obs, hist_gb=gb)
+        obs = S.observables(0, c.nt + 1)
+        whole = t_pre + el
+        wl, wms, wbytes = launches + pl, kms + pms, kbytes + pbytes
+        traj = {"steps": c.nt, "steps_per_s": c.nt / whole,
+                "history_sums_GBs": wbytes / (wms * 1e-3) / 1e9 if wms > 0 else None,
+                "history_sums_launches": wl}
+        return S, dict(elapsed=el, launches=launches, kms=kms, kbytes=kbytes, obs=obs, hist_gb=gb,
+                       whole_s=whole, traj=traj)
 
     S, r64 = run(cfg)
     elapsed, obs, hist_gb = r64["elapsed"], r64["obs"], r64["hist_gb"]
@@ -286,16 +311,22 @@ def main():
     eb = _energy_balance(obs, cfg)
     e_bal = float(np.abs(eb).max()) if eb is not None else None
     finite = bool(np.isfinite(obs).all())
-    print(f"[bench] FP64: {K} steps in {elapsed:.3f} s = {steps_per_s:.1f} steps/s; history sums: {launches} launches, "
-          f"{kms:.1f} ms, {kbytes / 1e12:.3f} TB algorithmic -> {achieved or 0:.0f} GB/s; "
+    first = cfg.nt - K + 1
+    traj = r64["traj"]
+    print(f"[bench] FP64: steps {first}..{cfg.nt} in {elapsed:.3f} s = {steps_per_s:.1f} steps/s; history sums: "
+          f"{launches} launches, {kms:.1f} ms, {kbytes / 1e12:.3f} TB algorithmic -> {achieved or 0:.0f} GB/s; "
+          f"whole trajectory {traj['steps_per_s']:.1f} steps/s, {traj['history_sums_GBs'] or 0:.0f} GB/s; "
           f"N drift {n_drift:.1e}, energy balance " + (f"{e_bal:.1e}" if e_bal is not None else "n/a (dipole kick)"),
           file=sys.stderr, flush=True)
 
-    fp32 = None
-    if not args.no_fp32:
+    def fresh(S):
         S.close()
         del S
         torch.cuda.empty_cache()
+
+    fp32 = None
+    if not args.no_fp32:
+        fresh(S)
         c32 = cfg.replace(precision=inputs.PRECISION_FP32)
         S, r32 = run(c32)
         o32 = r32["obs"]
@@ -304,78 +335,70 @@ def main():
         ach32 = r32["kbytes"] / (r32["kms"] * 1e-3) / 1e9 if r32["kms"] > 0 else None
         fp32 = {"value": K / r32["elapsed"], "unit": "steps/s", "speedup_vs_fp64": elapsed / r32["elapsed"],
                 "history_sums_GBs": ach32, "history_sums_frac": ach32 / HBM_PEAK_GBS if ach32 else None,
+                "trajectory": r32["traj"], "trajectory_speedup_vs_fp64": r64["whole_s"] / r32["whole_s"],
                 "history_GB": round(r32["hist_gb"], 2),
-                "max_rel_err_vs_fp64": err, "workload": f"{c32.name}: history stored and summed in FP32"}
-        print(f"[bench] FP32 form: {K} steps in {r32['elapsed']:.3f} s = {K / r32['elapsed']:.1f} steps/s "
-              f"({elapsed / r32['elapsed']:.2f}x); history sums {ach32 or 0:.0f} GB/s; max rel err vs FP64 "
-              f"{max(err.values()):.1e}", file=sys.stderr, flush=True)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+                "max_rel_err_vs_fp64": err, "error_over_steps": f"0..{cfg.nt}",
+                "workload": f"{c32.name}: history stored and summed in FP32"}
+        print(f"[bench] FP32 form: steps {first}..{cfg.nt} in {r32['elapsed']:.3f} s = {K / r32['elapsed']:.1f} "
+              f"steps/s ({elapsed / r32['elapsed']:.2f}x); history sums {ach32 or 0:.0f} GB/s; whole trajectory "
+              f"{r32['traj']['steps_per_s']:.1f} steps/s ({r64['whole_s'] / r32['whole_s']:.2f}x); max rel err vs "
+              f"FP64 over {cfg.nt} steps {max(err.values()):.1e}", file=sys.stderr, flush=True)
+        fresh(S)
         S = kbe.System(cfg)
 
     adaptive = None
     if not args.no_adaptive and args.workload == "c2":
         # Algorithm "prop"'s stopping rule on the same workload: at most 4 corrector passes, stop
         # once the row changes by <= 6e-9 (a wide gap of the changes: 3 passes on every step)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        fresh(S)
         ca = cfg.replace(n_corr=4, corr_tol=6e-9)
         S, ra = run(ca)
-        passes, _ = S.corrector_log(1, K)
+        passes, _ = S.corrector_log(1, cfg.nt)
         oa = ra["obs"]
         dev = _rel_devs(oa, obs, {"n_band1": 14, "Jx": 6, "Etot": 5})
-        adaptive = {"value": K / ra["elapsed"], "unit": "steps/s", "corr_tol": ca.corr_tol, "max_passes": ca.n_corr,
+        adaptive = {"value": K / ra["elapsed"], "unit": "steps/s", "trajectory": ra["traj"],
+                    "corr_tol": ca.corr_tol, "max_passes": ca.n_corr,
                     "mean_passes": float(passes.mean()), "pass_histogram": np.bincount(passes).tolist(),
                     "history_passes_per_step": 1.0 + float(passes.mean()),
                     "max_rel_dev_vs_one_pass": dev,
                     "workload": f"{ca.name}: corrector passes until the row changes by <= {ca.corr_tol:g} "
                                 f"(at most {ca.n_corr}), FP64"}
-        print(f"[bench] stopping rule: {K} steps in {ra['elapsed']:.3f} s = {K / ra['elapsed']:.1f} steps/s; "
-              f"{passes.mean():.2f} corrector passes per step; deviation from one pass "
+        print(f"[bench] stopping rule: steps {first}..{cfg.nt} in {ra['elapsed']:.3f} s = {K / ra['elapsed']:.1f} "
+              f"steps/s; {passes.mean():.2f} corrector passes per step; deviation from one pass "
               f"{max(dev.values()):.1e}", file=sys.stderr, flush=True)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        fresh(S)
         S = kbe.System(cfg)
 
     gregory = None
     if not args.no_gregory and args.workload == "c2":
         # the same workload with the quadrature's higher-order end corrections (5 nodes per end)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        fresh(S)
         cq = cfg.replace(quad_points=5)
         S, rq = run(cq)
         oq = rq["obs"]
         dev = _rel_devs(oq, obs, {"n_band1": 14, "Jx": 6, "Etot": 5, "Ecorr": 3})
         achq = rq["kbytes"] / (rq["kms"] * 1e-3) / 1e9 if rq["kms"] > 0 else None
-        gregory = {"value": K / rq["elapsed"], "unit": "steps/s", "quad_points": cq.quad_points,
+        gregory = {"value": K / rq["elapsed"], "unit": "steps/s", "trajectory": rq["traj"],
+                   "quad_points": cq.quad_points,
                    "history_sums_GBs": achq, "max_rel_dev_vs_trapezoid": dev,
                    "N_drift": float(np.abs(oq[:, 1] - oq[0, 1]).max()),
                    "energy_balance_max": float(np.abs(_energy_balance(oq, cq)).max()),  # Peierls pulse
                    "workload": f"{cq.name}: Gregory end corrections, {cq.quad_points} nodes per end, FP64"}
-        print(f"[bench] Gregory q={cq.quad_points}: {K} steps in {rq['elapsed']:.3f} s = {K / rq['elapsed']:.1f} "
-              f"steps/s; deviation from the trapezoid {max(dev.values()):.1e}", file=sys.stderr, flush=True)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        print(f"[bench] Gregory q={cq.quad_points}: steps {first}..{cfg.nt} in {rq['elapsed']:.3f} s = "
+              f"{K / rq['elapsed']:.1f} steps/s; deviation from the trapezoid {max(dev.values()):.1e}",
+              file=sys.stderr, flush=True)
+        fresh(S)
         S = kbe.System(cfg)
 
     paper = None
     if not args.no_paper and args.workload == "c2":
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        fresh(S)
         paper = paper_leg(torch, inputs, kbe, W)
         S = kbe.System(cfg)
 
     adj = None
     if not args.no_adjoint:
-        S.close()
-        del S
-        torch.cuda.empty_cache()
+        fresh(S)
         adj = adjoint_leg(torch, inputs, kbe)
         S = kbe.System(cfg)
 
@@ -385,28 +408,29 @@ def main():
 
     cpu = None
     if args.cpu_sample > 0:
-        ns = min(args.cpu_sample, K)
-        print(f"[bench] CPU oracle on steps 1..{ns} ...", file=sys.stderr, flush=True)
-        n1 = min(30, ns)
-        tcpu, threads, tcpu1 = cpu_baseline(cfg, ns, n1)
+        ns = min(args.cpu_sample, cfg.nt)
+        n1 = min(args.cpu_sample_one_core, ns)
+        print(f"[bench] CPU oracle on steps 1..{ns}, and on steps 1..{n1} with all threads and with one ...",
+              file=sys.stderr, flush=True)
+        tcpu, threads, tcpu_same, tcpu1 = cpu_baseline(cfg, ns, n1)
         # GPU time for the same steps, for a like-for-like ratio
         S.reset()
-        Sg = S
         torch.cuda.synchronize()
         tg0 = time.perf_counter()
-        Sg.step(ns)
+        S.step(ns)
         torch.cuda.synchronize()
         tgpu = time.perf_counter() - tg0
         cpu = {"value": ns / tcpu, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{cfg.name} steps 1..{ns} of {cfg.nt} (FP64 C++ oracle, OpenMP over k); "
                          f"{tcpu:.2f} s; the GPU path takes {tgpu:.3f} s on the same steps",
                "gpu_same_sample_steps_per_s": ns / tgpu, "cpu_model": cpu_model(),
+               "same_sample_all_threads_steps_per_s": (n1 / tcpu_same) if tcpu_same else None,
                "one_core_steps_per_s": (n1 / tcpu1) if tcpu1 else None,
-               "one_core_sample": f"steps 1..{n1}, one OpenMP thread"}
+               "one_core_sample": f"steps 1..{n1}, timed with all {threads} threads and with one"}
 
     traffic = None
-    if args.workload == "c2" and K == cfg.nt and _kernel_source_sha1() == MEASURED_TRAFFIC["source_sha1"]:
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    if _kernel_source_sha1() == MEASURED_TRAFFIC["source_sha1"]:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"].get((args.workload, cfg.nt, K))
     line = {
         "metric": "KBE steps/s (history sums: achieved HBM GB/s)",
         "value": steps_per_s,
@@ -422,13 +446,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: 2D {cfg.nkx}x{cfg.nky} k-grid, nb={cfg.nb}, nt={cfg.nt}, dt={cfg.dt}, "
                                f"second Born + HF, K={cfg.n_corr} corrector pass, FP64",
-                   "nk": cfg.nk, "nb": cfg.nb, "nt": cfg.nt, "steps_timed_from_t0": K,
+                   "nk": cfg.nk, "nb": cfg.nb, "nt": cfg.nt, "timed_steps": [first, cfg.nt],
+                   "history_rows_in_timed_steps": [first, cfg.nt + 1],
                    "history_passes_per_step": cfg.n_corr + 1, "history_GB": round(hist_gb, 2)},
+        "trajectory": traj,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM fetch + write)",
                      "kernel": "k_hist_pair" if cfg.nb <= 2 else ("k_hist_bulk_split" if cfg.nb == 4 else "k_hist_bulk"),
-                     "launches": launches, "kernel_ms": kms},
+                     "launches": launches, "kernel_ms": kms,
+                     "algorithmic_bytes_per_launch": kbytes / launches if launches else None},
         "cpu_baseline": cpu,
         "fp32_form": fp32,
         "adaptive_corrector": adaptive,

@@ -44,7 +44,8 @@ enum {
   KBE_ERR_HIP = -3,          /* a HIP runtime call failed */
   KBE_ERR_STATE = -4,        /* call out of order (e.g. stepping past nt_max) */
   KBE_ERR_NONFINITE = -5,    /* a NaN/Inf appeared in the propagated state */
-  KBE_ERR_NOT_CONVERGED = -6
+  KBE_ERR_NOT_CONVERGED = -6 /* kbe_step: the corrector's stopping rule (corr_tol > 0) ran all n_corr
+                                passes with the row still changing by more than corr_tol */
 };
 
 /* Interaction presets (eq. (ham) and eq. (2BSE)). */
@@ -168,7 +169,11 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
                void* hip_stream, kbe_ctx** out);
 
 /* Advance nsteps time steps (Algorithm "prop" with K = cfg->n_corr fixed corrector passes),
- * asynchronously. KBE_ERR_STATE if the step index would pass nt_max. */
+ * asynchronously. KBE_ERR_STATE if the step index would pass nt_max. With corr_tol > 0, a step
+ * whose n_corr passes all end with the row changing by more than corr_tol is committed as the
+ * algorithm commits it, and the call then returns KBE_ERR_NOT_CONVERGED without taking the
+ * remaining steps: kbe_current_step is that step, kbe_corrector_log holds its changes, and a
+ * further kbe_step call continues from it. */
 int kbe_step(kbe_ctx* ctx, int32_t nsteps);
 
 /* Index of the last completed step (0 after kbe_create). */
@@ -256,9 +261,12 @@ int kbe_stage_commit(kbe_ctx* ctx, int32_t m);
 int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m);
 
 /* Per-launch timing of the history-sum kernel with HIP events on the context's stream.
- * kbe_timing(ctx, 1) starts recording (clearing earlier records); kbe_timing_query
- * synchronises and returns the number of launches, their summed duration (ms) and the
- * algorithmic bytes they move (each stored history block read once). */
+ * kbe_timing(ctx, 1) synchronises the stream, clears earlier records and creates the whole
+ * event pool up front (two events per history pass of every step up to nt_max), so that no
+ * event is created while work is queued; history-sum launches beyond the pool run untimed.
+ * kbe_timing(ctx, 0) synchronises and stops recording. kbe_timing_query synchronises and
+ * returns the number of timed launches, their summed duration (ms) and the algorithmic bytes
+ * they move (each stored history block read once). */
 int kbe_timing(kbe_ctx* ctx, int32_t enable);
 int kbe_timing_query(kbe_ctx* ctx, int64_t* launches, double* total_ms, double* algo_bytes);
 

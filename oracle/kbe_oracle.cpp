@@ -385,6 +385,7 @@ struct State {
   std::vector<C> sig;              // [j][k][comp][a][b], j = 0..m
   std::vector<int> passes;         // corrector passes taken at each step (index m)
   std::vector<double> changes;     // after each pass: max |G_new - G_old| over row m
+  std::vector<int> unconverged;    // 1 at step m if all n_corr passes ended above corr_tol
   State(const Params& pp, const Theta<R>& t, const double* hopd) : p(pp), th(t), g(pp) {
     nbb = g.nb * g.nb;
     blk = 2 * nbb;
@@ -895,13 +896,16 @@ double row_change(const std::vector<Cx<R>>& a, const std::vector<Cx<R>>& b) {
 
 // One step of Algorithm "prop": predictor, then at most n_corr corrector passes; with
 // corr_tol > 0 the passes stop at the first whose change of the row is <= corr_tol (the
-// algorithm's max and epsilon), otherwise all n_corr passes run.
+// algorithm's max and epsilon), otherwise all n_corr passes run. When the loop ends on its
+// pass limit with the last change still above corr_tol (the algorithm leaves its loop without
+// reaching epsilon), the step is kept and marked as not converged.
 template <class R>
 void step(State<R>& st, int m) {
   int nk = st.g.nk, blk = st.blk;
   st.rows.emplace_back((size_t)(m + 1) * nk * blk);
   update_row(st, m, false);
   int passes = 0;
+  bool reached = st.p.corr_tol <= 0.0;
   for (int it = 0; it < st.p.n_corr; ++it) {
     std::vector<Cx<R>> before;
     if (st.p.corr_tol > 0.0) before = st.rows[m];
@@ -911,11 +915,16 @@ void step(State<R>& st, int m) {
     if (st.p.corr_tol > 0.0) {
       double ch = row_change(st.rows[m], before);
       st.changes.push_back(ch);
-      if (ch <= st.p.corr_tol) break;
+      if (ch <= st.p.corr_tol) {
+        reached = true;
+        break;
+      }
     }
   }
   if ((int)st.passes.size() <= m) st.passes.resize(m + 1, 0);
   st.passes[m] = passes;
+  if ((int)st.unconverged.size() <= m) st.unconverged.resize(m + 1, 0);
+  st.unconverged[m] = (st.p.corr_tol > 0.0 && st.p.n_corr > 0 && !reached) ? 1 : 0;
   sigma_and_collision(st, m);
   st.I_prev = st.I_cur;
   st.D_prev = st.D_cur;
@@ -1211,9 +1220,10 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
 
 // oracle_run with the corrector log: passes[m] = corrector passes of step m (passes[0] = 0);
 // changes[(m - 1) * n_corr + i] = row change after pass i of step m (-1 where no pass ran;
-// only filled when corr_tol > 0).
+// only filled when corr_tol > 0); unconverged[m] = 1 where step m ran all n_corr passes and
+// its last change was still above corr_tol.
 int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* obs, int32_t* passes,
-                   double* changes) {
+                   double* changes, int32_t* unconverged) {
   if (!p || !hop || nsteps < 0 || p->nb < 1 || p->nb > 4) return -1;
   if (p->interaction == INT_INTERBAND && p->nb != 2) return -1;
   if (p->pulse_kind != PULSE_PEIERLS && (p->pulse_kind != PULSE_DIPOLE_KICK || p->nb != 2 || !(p->t0 >= 0.0)))
@@ -1235,6 +1245,8 @@ int oracle_run_log(const Params* p, const double* hop, int32_t nsteps, double* o
   }
   if (passes)
     for (int m = 0; m <= nsteps; ++m) passes[m] = m < (int)st.passes.size() ? st.passes[m] : 0;
+  if (unconverged)
+    for (int m = 0; m <= nsteps; ++m) unconverged[m] = m < (int)st.unconverged.size() ? st.unconverged[m] : 0;
   return 0;
 }
 

@@ -33,8 +33,12 @@ OBS = {n: i for i, n in enumerate(OBS_NAMES)}
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (plain -O2, OpenMP over k-points)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", _LIB, _SRC]
+        # link to a private file and rename it into place, so that a process that has the
+        # library loaded (a long reference run) keeps its own copy
+        tmp = f"{_LIB}.{os.getpid()}.tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
     return _LIB
 
 
@@ -63,7 +67,8 @@ def lib():
         _lib.oracle_initial_state.argtypes = [P, dp, dp, dp]
         _lib.oracle_h0.argtypes = [P, dp, ctypes.c_double, dp]
         _lib.oracle_tlm_run.argtypes = [P, dp, ctypes.c_int32, dp, dp]
-        _lib.oracle_run_log.argtypes = [P, dp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int32), dp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        _lib.oracle_run_log.argtypes = [P, dp, ctypes.c_int32, dp, ip, dp, ip]
         _lib.oracle_quad_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, dp]
         _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
         _lib.oracle_max_threads.restype = ctypes.c_int
@@ -129,19 +134,25 @@ def quad_weights(quad_points: int, N: int) -> np.ndarray:
     return out
 
 
-def run_log(cfg, nsteps: int | None = None):
+def run_log(cfg, nsteps: int | None = None, with_unconverged: bool = False):
     """Propagation with the corrector log (Algorithm "prop"'s max / epsilon loop).
     Returns (obs, passes, changes): passes[m] corrector passes of step m, changes[m - 1, i] the
-    row change after pass i of step m (-1: no such pass; only with cfg.corr_tol > 0)."""
+    row change after pass i of step m (-1: no such pass; only with cfg.corr_tol > 0); with
+    ``with_unconverged`` also unconverged[m] = 1 where step m ran all n_corr passes with its
+    last change still above cfg.corr_tol."""
     n = cfg.nt if nsteps is None else nsteps
     obs = np.zeros((n + 1, NOBS))
     passes = np.zeros(n + 1, np.int32)
+    unconv = np.zeros(n + 1, np.int32)
     changes = np.zeros((max(n, 1), max(cfg.n_corr, 1)))
     p = params(cfg)
-    rc = lib().oracle_run_log(ctypes.byref(p), _ptr(_hop(cfg)), n, _ptr(obs),
-                              passes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(changes))
+    ip = ctypes.POINTER(ctypes.c_int32)
+    rc = lib().oracle_run_log(ctypes.byref(p), _ptr(_hop(cfg)), n, _ptr(obs), passes.ctypes.data_as(ip),
+                              _ptr(changes), unconv.ctypes.data_as(ip))
     if rc != 0:
         raise ValueError(f"oracle_run_log rejected the configuration (rc={rc})")
+    if with_unconverged:
+        return obs, passes, changes[:n, :cfg.n_corr], unconv
     return obs, passes, changes[:n, :cfg.n_corr]
 
 

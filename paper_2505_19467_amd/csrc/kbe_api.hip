@@ -284,14 +284,9 @@ struct kbe_ctx {
     return KBE_OK;
   }
   int bulk_timed(const LaunchArgs& a, int m) {
-    if (timing && m >= 1) {
-      if (ev_used + 2 > ev.size()) {
-        for (int i = 0; i < 256; ++i) {
-          hipEvent_t e;
-          if (hipEventCreate(&e) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventCreate failed");
-          ev.push_back(e);
-        }
-      }
+    // the event pool is created whole by kbe_timing before any launch is queued; launches past
+    // its end (more passes than it was sized for) run untimed
+    if (timing && m >= 1 && ev_used + 2 <= ev.size()) {
       if (hipEventRecord(ev[ev_used], st) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventRecord failed");
       int rc = check(kbe::launch_bulk(L.d, a, m, st), "history-sum launch");
       if (rc) return rc;
@@ -347,6 +342,8 @@ struct kbe_ctx {
     // largest change of row m is <= corr_tol, which needs the change on the host after each
     // pass (one stream synchronisation per pass in that mode).
     const bool tol = cfg.corr_tol > 0.0;
+    bool reached = !tol;
+    double last_change = 0.0;
     int taken = 0;
     for (int it = 0; it < cfg.n_corr && !rc; ++it) {
       rc = collision_parts(a, m);
@@ -370,7 +367,11 @@ struct kbe_ctx {
           break;
         }
         changes[(size_t)m * cfg.n_corr + it] = ch;
-        if (ch <= cfg.corr_tol) break;
+        last_change = ch;
+        if (ch <= cfg.corr_tol) {
+          reached = true;
+          break;
+        }
       }
     }
     if (!rc) passes[m] = taken;
@@ -381,6 +382,12 @@ struct kbe_ctx {
     if (rc) return rc;
     cur ^= 1;
     step = m;
+    // Algorithm "prop" left its corrector loop on the pass limit without reaching epsilon: the
+    // step is committed (as the algorithm proceeds) and reported to the caller
+    if (!reached && cfg.n_corr > 0)
+      return fail(KBE_ERR_NOT_CONVERGED, "step " + std::to_string(m) + ": the row still changed by " +
+                                             std::to_string(last_change) + " after " + std::to_string(taken) +
+                                             " corrector passes (corr_tol " + std::to_string(cfg.corr_tol) + ")");
     return KBE_OK;
   }
 
@@ -760,9 +767,25 @@ int kbe_rebuild_aux(kbe_ctx* ctx, int32_t m) {
 
 int kbe_timing(kbe_ctx* ctx, int32_t enable) {
   if (!ctx) return KBE_ERR_INVALID_ARG;
+  // events of an earlier window may still be pending on the stream: let them complete before
+  // they are recorded again
+  int rc = ctx->check(hipStreamSynchronize(ctx->st), "stream synchronisation");
+  if (rc) return rc;
   ctx->timing = enable != 0;
   ctx->ev_used = 0;
   ctx->ev_m.clear();
+  if (ctx->timing) {
+    // two events per history-sum launch: at most n_corr + 1 passes per step, one more on the
+    // dipole-kick slice, for every step up to nt_max
+    size_t need = 2 * ((size_t)ctx->cfg.nt_max * (ctx->cfg.n_corr + 1) + 1);
+    ctx->ev_m.reserve(need / 2);
+    while (ctx->ev.size() < need) {
+      hipEvent_t e;
+      rc = ctx->check(hipEventCreate(&e), "hipEventCreate");
+      if (rc) return rc;
+      ctx->ev.push_back(e);
+    }
+  }
   return KBE_OK;
 }
 

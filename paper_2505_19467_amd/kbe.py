@@ -25,6 +25,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 KBE_OK = 0
+KBE_ERR_NOT_CONVERGED = -6
 ERRORS = {-1: "KBE_ERR_INVALID_ARG", -2: "KBE_ERR_SHAPE", -3: "KBE_ERR_HIP", -4: "KBE_ERR_STATE",
           -5: "KBE_ERR_NONFINITE", -6: "KBE_ERR_NOT_CONVERGED"}
 NOBS = 17
@@ -85,6 +86,15 @@ EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", 
 
 class KbeError(RuntimeError):
     pass
+
+
+class KbeNotConverged(KbeError):
+    """kbe_step committed a step whose corrector passes all ended above corr_tol; ``step`` is
+    that step (the context can be stepped on from it)."""
+
+    def __init__(self, msg, step):
+        super().__init__(msg)
+        self.step = step
 
 
 def _c_config(cfg: _inputs.Config, nt_max: int | None = None) -> KbeConfig:
@@ -225,7 +235,10 @@ class System:
 
     # ------------------------------------------------------------------ propagation
     def step(self, n: int = 1):
-        self._check(_lib.kbe_step(self._ctx, n), "kbe_step")
+        rc = _lib.kbe_step(self._ctx, n)
+        if rc == KBE_ERR_NOT_CONVERGED:
+            raise KbeNotConverged(f"kbe_step: {_lib.kbe_last_error(self._ctx).decode()}", self.current_step)
+        self._check(rc, "kbe_step")
 
     @property
     def current_step(self) -> int:

@@ -97,3 +97,33 @@ def test_adjoint_refuses_tolerance_mode(K):
     with pytest.raises(K.KbeError):
         S.adjoint_gradient("n_band1")
     S.close()
+
+
+@pytest.mark.parametrize("tol,nsteps", [(1e-30, 12), (1e-7, 40)])
+def test_unmet_tolerance_reports_not_converged(K, tol, nsteps):
+    """A step whose n_corr passes all end above corr_tol is committed and reported
+    (KBE_ERR_NOT_CONVERGED): kbe_step stops on it, and stepping on continues the run. The
+    flagged steps are the oracle's, the run matches the oracle's run with the same rule."""
+    _say(f"unmet tolerance: c1 n_corr=2 tol={tol:g} steps={nsteps}")
+    cfg = inputs.c1().replace(n_corr=2, corr_tol=tol)
+    ref_obs, ref_passes, ref_ch, ref_unconv = O.run_log(cfg, nsteps, with_unconverged=True)
+    # every logged change sits far (in absolute terms) from the tolerance compared with the
+    # 1e-13 the two sides' changes agree to, so both take the same decisions
+    assert np.min(np.abs(ref_ch[ref_ch > 0] - tol)) > 1e-11
+    S = K.System(cfg, nt_max=nsteps)
+    flagged, calls = [], 0
+    while S.current_step < nsteps:
+        calls += 1
+        try:
+            S.step(nsteps - S.current_step)
+        except K.KbeNotConverged as e:
+            assert e.step == S.current_step
+            flagged.append(e.step)
+    obs = S.observables()
+    passes, _ = S.corrector_log()
+    want = [int(m) for m in np.nonzero(ref_unconv)[0]]
+    _say(f"  flagged {len(flagged)} of {nsteps} steps in {calls} calls; oracle {len(want)}")
+    assert flagged == want and len(want) > 0
+    assert np.array_equal(passes, ref_passes)
+    assert _series_err(obs, ref_obs) < RUN_TOL
+    S.close()

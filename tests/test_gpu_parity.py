@@ -159,20 +159,24 @@ def _compare_run(K, cfg, nsteps):
     obs = S.observables()
     final = S.history_row(nsteps).cpu().numpy()
     ref = O.run(cfg, nsteps)
-    worst = {}
+    worst, vanish = {}, {}
     for name in SERIES:
         i = O.OBS[name]
         x, r = obs[:, i], ref["obs"][:, i]
         if np.abs(r).max() < 1e-12:
-            # identically zero by symmetry (e.g. J_y for a pulse along x, unused orbitals):
-            # both sides must stay at rounding level
-            assert np.abs(x).max() < 1e-12, name
+            # zero by symmetry (e.g. J_y for a pulse along x, unused orbitals): the cancelling
+            # terms are O(1) per k-point, so what remains is rounding of O(1) numbers summed over
+            # the grid and carried through the run; the bound is a hundredth of the FP64 target
+            # at the scale of those terms
+            vanish[name] = float(np.abs(x).max())
+            assert vanish[name] < 1e-12, name
             continue
         worst[name] = relerr(x, r)
     assert np.abs(obs[:, 0] - ref["obs"][:, 0]).max() < 1e-12
     worst["final_row"] = relerr(final, ref["final_row"])
     _say(f"  worst relative errors: {max(worst.values()):.2e} " +
-         " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
+         " ".join(f"{k}={v:.1e}" for k, v in worst.items()) +
+         "; vanishing series " + " ".join(f"{k}={v:.1e}" for k, v in vanish.items()))
     bad = {k: v for k, v in worst.items() if not v < RUN_TOL}
     assert not bad, bad
     return obs

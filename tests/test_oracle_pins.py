@@ -61,6 +61,31 @@ def test_sigma_hubbard_matches_momentum_convolution(nkx, nky, nb):
             assert np.abs(sig[j, :, comp] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("nk,seed", [(8, 41), (6, 42)])
+def test_sigma_hubbard_is_eq_2bse_with_spins_as_bands(nk, seed):
+    """The Hubbard preset's sign and U^2/n_k^2 prefactor tied to the paper's eq. (2BSE): with
+    the two bands of the paper's model read as the two spins of one orbital, its interaction
+    U n_v n_c is the on-site U n_up n_down. For a spin-diagonal G = diag(g, g) the exchange term
+    of eq. (2BSE) vanishes (it needs G between the spins), and its direct term must equal the
+    nb = 1 Hubbard self-energy of g on both diagonal entries, with no spin-flip entries."""
+    U = 1.3
+    cfg = inputs.Config(name="t", nkx=nk, nky=1, nb=1, hop=np.zeros((3, 1, 1), complex), U=U,
+                        dt=0.02, nt=4, interaction=inputs.INTERACTION_HUBBARD)
+    m = 2
+    row = inputs.random_complex((m + 1, nk, 2, 1, 1), seed)
+    sig = O.sigma_row(cfg, m, row)
+    for j in range(m + 1):
+        G2 = np.zeros((nk, 2, 2, 2), complex)   # [k][</>][spin][spin]
+        G2[:, :, 0, 0] = row[j, :, :, 0, 0]
+        G2[:, :, 1, 1] = row[j, :, :, 0, 0]
+        for comp, lesser in ((0, True), (1, False)):
+            ref = brute.paper_sigma_direct(G2[:, 0], G2[:, 1], U, lesser)
+            scale = np.abs(ref).max()
+            assert np.abs(ref[:, 0, 1]).max() <= 1e-15 * scale and np.abs(ref[:, 1, 0]).max() <= 1e-15 * scale
+            for s in range(2):
+                assert np.abs(sig[j, :, comp, 0, 0] - ref[:, s, s]).max() <= 1e-13 * scale
+
+
 @pytest.mark.parametrize("interaction", [inputs.INTERACTION_HUBBARD, inputs.INTERACTION_INTERBAND])
 def test_sigma_conserving_pairing(interaction):
     """sum_k tr[Sigma^>(t,tb) G^<(tb,t) - Sigma^<(t,tb) G^>(tb,t)] is purely imaginary
@@ -503,6 +528,28 @@ def test_corrector_tolerance_approaches_the_fixed_point():
         errs.append(np.max(np.abs(obs - ref) / scale))
         assert errs[-1] < 1e3 * tol
     assert errs[0] > errs[1] > errs[2]
+
+
+def test_corrector_reports_unmet_tolerance():
+    """Algorithm "prop" leaves its loop after `max` passes even when the change is still above
+    epsilon: with an epsilon no pass can reach, every step runs all passes (so the run equals
+    the fixed-count run bit for bit) and every step is flagged; with a reachable epsilon a step
+    is flagged exactly when it used every pass and its last change stayed above epsilon."""
+    cfg = inputs.c1()
+    n = 30
+    fixed2 = O.run(cfg.replace(n_corr=2), n)["obs"]
+    obs, passes, ch, unconv = O.run_log(cfg.replace(n_corr=2, corr_tol=1e-30), n, with_unconverged=True)
+    assert np.array_equal(obs, fixed2)
+    assert np.all(passes[1:] == 2) and np.all(unconv[1:] == 1) and unconv[0] == 0
+    assert np.all(ch > 1e-30)
+    c3 = cfg.replace(n_corr=2, corr_tol=1e-7)
+    _, passes, ch, unconv = O.run_log(c3, 40, with_unconverged=True)
+    for m in range(1, 41):
+        last = ch[m - 1, passes[m] - 1]
+        assert unconv[m] == int(passes[m] == c3.n_corr and last > c3.corr_tol), m
+    assert unconv[1:].any() and not unconv[1:].all()   # both outcomes occur on this run
+    _, _, _, unconv0 = O.run_log(cfg.replace(n_corr=2), n, with_unconverged=True)
+    assert not unconv0.any()   # the fixed-count mode has no stopping rule to miss
 
 
 # ---------------------------------------------------------------- Gregory end corrections

@@ -168,6 +168,28 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
                size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
                void* hip_stream, kbe_ctx** out);
 
+/* Allocation-free variant of kbe_create, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation): the same context,
+ * except that its workspace is not passed in but lives in a static device array of the library,
+ * one array of KBE_NOALLOC_WORKSPACE_MAX bytes per device, held from the library's first use
+ * on that device until the process ends. The caller passes the history and the observables as
+ * for kbe_create. The call allocates no device memory.
+ *   - The device is the one current at the call; hip_stream must belong to it.
+ *   - KBE_ERR_SHAPE if the workspace of cfg (kbe_workspace_query) exceeds
+ *     KBE_NOALLOC_WORKSPACE_MAX (e.g. the 12x12, nb = 2, nt_max = 400 workload needs 86 MiB and
+ *     fits; the 24x24, nt_max = 1000 one needs 1.1 GiB and does not); other argument errors as
+ *     for kbe_create. Nothing is launched on an error.
+ *   - One such context per device at a time: the array is the context's whole state, so a
+ *     second kbe_create_noalloc on the device returns KBE_ERR_STATE until kbe_destroy of the
+ *     first (which waits for its work to complete) has returned.
+ *   - The array keeps the previous context's contents; creation clears the part it uses (a
+ *     fill kernel on hip_stream) before it computes the initial state.
+ *   - Every other entry point works on the context as on one from kbe_create; kbe_adjoint_attach
+ *     still takes a caller-owned adjoint workspace. */
+#define KBE_NOALLOC_WORKSPACE_MAX ((size_t)128 << 20)
+int kbe_create_noalloc(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+                       size_t history_bytes, void* d_obs, size_t obs_bytes, void* hip_stream, kbe_ctx** out);
+
 /* Advance nsteps time steps (Algorithm "prop" with K = cfg->n_corr fixed corrector passes),
  * asynchronously. KBE_ERR_STATE if the step index would pass nt_max. With corr_tol > 0, a step
  * whose n_corr passes all end with the row changing by more than corr_tol is committed as the

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -226,6 +227,7 @@ struct kbe_ctx {
   // corrector log (host): passes taken per step, and the row change after each pass
   std::vector<int32_t> passes;
   std::vector<double> changes;
+  int noalloc_dev = -1;  // device whose static workspace this context holds (kbe_create_noalloc)
 
   template <class T>
   T* buf(int b) const { return reinterpret_cast<T*>(ws + L.off[b]); }
@@ -534,23 +536,13 @@ struct kbe_ctx {
   }
 };
 
-extern "C" {
+namespace {
 
-int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* workspace_bytes,
-                        size_t* obs_bytes) {
-  Layout L;
-  std::string why;
-  int rc = make_layout(cfg, &L, &why);
-  if (rc) return rc;
-  if (history_bytes) *history_bytes = L.hist_bytes;
-  if (workspace_bytes) *workspace_bytes = L.ws_bytes;
-  if (obs_bytes) *obs_bytes = L.obs_bytes;
-  return KBE_OK;
-}
-
-int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
-               size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
-               void* hip_stream, kbe_ctx** out) {
+// kbe_create on the given workspace; clear_workspace zeroes all of it first (a workspace that
+// keeps an earlier context's contents).
+int create_context(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+                   size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
+                   void* hip_stream, kbe_ctx** out, bool clear_workspace) {
   if (!out) return KBE_ERR_INVALID_ARG;
   *out = nullptr;
   if (!cfg || !hop || !d_history || !d_workspace || !d_obs) return KBE_ERR_INVALID_ARG;
@@ -597,8 +589,11 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   if (d.nky == 1)
     for (int i = 0; i < d.nbb; ++i) c->hop_host[2 * d.nbb + i] = make_double2(0.0, 0.0);
   LaunchArgs a = c->args();
-  rc = c->check(hipMemcpyAsync(a.hop, c->hop_host.data(), 3 * d.nbb * sizeof(cplx), hipMemcpyHostToDevice, c->st),
-                "copy of the hopping blocks");
+  if (clear_workspace)
+    rc = c->check(kbe::launch_fill_zero((double*)c->ws, c->L.ws_bytes / sizeof(double), c->st), "zero");
+  if (!rc)
+    rc = c->check(hipMemcpyAsync(a.hop, c->hop_host.data(), 3 * d.nbb * sizeof(cplx), hipMemcpyHostToDevice, c->st),
+                  "copy of the hopping blocks");
   if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_IA), 2 * c->L.bytes[B_IA] / sizeof(cplx), c->st), "zero");
   if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_IB), 2 * c->L.bytes[B_IB] / sizeof(cplx), c->st), "zero");
   if (!rc) rc = c->check(kbe::launch_fill_zero((double*)c->buf<cplx>(B_DA), 2 * c->L.bytes[B_DA] / sizeof(cplx), c->st), "zero");
@@ -617,6 +612,75 @@ int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse,
   }
   *out = c;
   return KBE_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free contexts
+// The workspace of a context made by kbe_create_noalloc: one array per device, loaded with the
+// library's code and kept until the process ends. Host code never passes the array's name to a
+// kernel or a copy (on the host it only stands for the symbol): it uses the device address
+// that hipGetSymbolAddress returns for the current device, kept per device below.
+constexpr size_t NOALLOC_BYTES = KBE_NOALLOC_WORKSPACE_MAX;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[NOALLOC_DEVICES];   // device address of scratch on each device (null: not yet looked up)
+bool noalloc_busy[NOALLOC_DEVICES];   // a live context holds that device's array
+
+}  // namespace
+
+extern "C" {
+
+int kbe_workspace_query(const kbe_config* cfg, size_t* history_bytes, size_t* workspace_bytes,
+                        size_t* obs_bytes) {
+  Layout L;
+  std::string why;
+  int rc = make_layout(cfg, &L, &why);
+  if (rc) return rc;
+  if (history_bytes) *history_bytes = L.hist_bytes;
+  if (workspace_bytes) *workspace_bytes = L.ws_bytes;
+  if (obs_bytes) *obs_bytes = L.obs_bytes;
+  return KBE_OK;
+}
+
+
+int kbe_create(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+               size_t history_bytes, void* d_workspace, size_t workspace_bytes, void* d_obs, size_t obs_bytes,
+               void* hip_stream, kbe_ctx** out) {
+  return create_context(cfg, hop, pulse, d_history, history_bytes, d_workspace, workspace_bytes, d_obs, obs_bytes,
+                        hip_stream, out, false);
+}
+
+int kbe_create_noalloc(const kbe_config* cfg, const double* hop, const kbe_pulse* pulse, void* d_history,
+                       size_t history_bytes, void* d_obs, size_t obs_bytes, void* hip_stream, kbe_ctx** out) {
+  if (!out) return KBE_ERR_INVALID_ARG;
+  *out = nullptr;
+  Layout L;
+  std::string why;
+  int rc = make_layout(cfg, &L, &why);
+  if (rc) return rc;
+  if (L.ws_bytes > NOALLOC_BYTES) return KBE_ERR_SHAPE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return KBE_ERR_HIP;
+  if (dev < 0 || dev >= NOALLOC_DEVICES) return KBE_ERR_SHAPE;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KBE_ERR_HIP;
+      noalloc_ptr[dev] = p;
+    }
+    if (noalloc_busy[dev]) return KBE_ERR_STATE;
+    noalloc_busy[dev] = true;
+    ws = noalloc_ptr[dev];
+  }
+  rc = create_context(cfg, hop, pulse, d_history, history_bytes, ws, NOALLOC_BYTES, d_obs, obs_bytes, hip_stream,
+                      out, true);
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (rc) noalloc_busy[dev] = false;
+  else (*out)->noalloc_dev = dev;
+  return rc;
 }
 
 int kbe_step(kbe_ctx* ctx, int32_t nsteps) {
@@ -662,6 +726,11 @@ void kbe_destroy(kbe_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->st);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->noalloc_dev >= 0) {
+    // the context's work has completed: the device's static workspace is free again
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    noalloc_busy[ctx->noalloc_dev] = false;
+  }
   delete ctx;
 }
 

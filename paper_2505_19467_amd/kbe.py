@@ -56,6 +56,9 @@ _lib.kbe_workspace_query.argtypes = [ctypes.POINTER(KbeConfig), _szp, _szp, _szp
 _lib.kbe_create.argtypes = [ctypes.POINTER(KbeConfig), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(KbePulse),
                             _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
                             ctypes.POINTER(_vp)]
+_lib.kbe_create_noalloc.argtypes = [ctypes.POINTER(KbeConfig), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(KbePulse), _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp,
+                                    ctypes.POINTER(_vp)]
 _lib.kbe_step.argtypes = [_vp, _i32]
 _lib.kbe_current_step.argtypes = [_vp]
 _lib.kbe_current_step.restype = _i32
@@ -77,7 +80,8 @@ _lib.kbe_adjoint_query.argtypes = [ctypes.POINTER(KbeConfig), _szp]
 _lib.kbe_adjoint_attach.argtypes = [_vp, _vp, ctypes.c_size_t]
 _lib.kbe_adjoint_step.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 
-EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_step", "kbe_current_step", "kbe_corrector_log", "kbe_observables",
+NOALLOC_WORKSPACE_MAX = 128 << 20   # KBE_NOALLOC_WORKSPACE_MAX
+EXPORTS = ["kbe_workspace_query", "kbe_create", "kbe_create_noalloc", "kbe_step", "kbe_current_step", "kbe_corrector_log", "kbe_observables",
            "kbe_destroy", "kbe_last_error", "kbe_buffer", "kbe_stage_propagators", "kbe_stage_sigma", "kbe_stage_sigma_direct",
            "kbe_stage_collision", "kbe_stage_update", "kbe_stage_observables", "kbe_stage_commit",
            "kbe_rebuild_aux", "kbe_timing", "kbe_timing_query", "kbe_adjoint_query", "kbe_adjoint_attach",
@@ -146,8 +150,11 @@ class System:
     """One propagation context: caller-owned (torch) device buffers + the library context."""
 
     def __init__(self, cfg: _inputs.Config, nt_max: int | None = None, device: str = "cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, noalloc: bool = False):
+        """``noalloc``: create the context with kbe_create_noalloc (its workspace is the library's
+        static per-device array; no workspace tensor is allocated)."""
         self.cfg = cfg
+        self.noalloc = noalloc
         self.nt_max = cfg.nt if nt_max is None else nt_max
         self.adj_workspace = None
         # one KbeConfig for both the sizing and the creation of the context
@@ -157,7 +164,7 @@ class System:
         self.fp32 = cfg.precision == _inputs.PRECISION_FP32
         hdt = torch.complex64 if self.fp32 else torch.complex128
         self.history = torch.empty(hb // (8 if self.fp32 else 16), dtype=hdt, device=dev)
-        self.workspace = torch.empty(wb, dtype=torch.uint8, device=dev)
+        self.workspace = None if noalloc else torch.empty(wb, dtype=torch.uint8, device=dev)
         self.obs = torch.empty(ob // 8, dtype=torch.float64, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.nk, self.nb = cfg.nk, cfg.nb
@@ -176,6 +183,15 @@ class System:
                      pol=(ctypes.c_double * 2)(pu.pol[0], pu.pol[1]), kind=pu.kind)
         ctx = _vp()
         nbytes = lambda t: t.numel() * t.element_size()  # noqa: E731
+        if self.noalloc:
+            rc = _lib.kbe_create_noalloc(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.byref(p), _vp(self.history.data_ptr()), nbytes(self.history),
+                                         _vp(self.obs.data_ptr()), nbytes(self.obs), _vp(self.stream.cuda_stream),
+                                         ctypes.byref(ctx))
+            if rc != KBE_OK:
+                raise KbeError(f"kbe_create_noalloc: {ERRORS.get(rc, rc)}")
+            self._ctx = ctx
+            return
         rc = _lib.kbe_create(ctypes.byref(c), hop.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(p),
                              _vp(self.history.data_ptr()), nbytes(self.history),
                              _vp(self.workspace.data_ptr()), nbytes(self.workspace),
@@ -206,7 +222,7 @@ class System:
             rc = _lib.kbe_adjoint_query(ctypes.byref(self._cconf), ctypes.byref(nbytes))
             if rc != KBE_OK:
                 raise KbeError(f"kbe_adjoint_query: {ERRORS.get(rc, rc)}")
-            self.adj_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.workspace.device)
+            self.adj_workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.history.device)
             self._attach()
         grad = np.zeros(3)
         left = _i32(self.current_step)
@@ -293,6 +309,8 @@ class System:
     # ------------------------------------------------------------------ buffers
     def buffer(self, which: int) -> torch.Tensor:
         """complex128 view of a workspace sub-buffer (current role)."""
+        if self.workspace is None:
+            raise KbeError("buffer(): the workspace of an allocation-free context is not a torch tensor")
         ptr, nbytes = _vp(), ctypes.c_size_t()
         self._check(_lib.kbe_buffer(self._ctx, which, ctypes.byref(ptr), ctypes.byref(nbytes)), "kbe_buffer")
         off = ptr.value - self.workspace.data_ptr()

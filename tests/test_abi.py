@@ -219,6 +219,8 @@ def test_binding_constants_match_header():
     for n in ("SIGMA", "I_PREV", "I_CUR", "RHO_PREV", "RHO_CUR", "D_PREV", "D_CUR", "PROP", "COL0", "DIAG", "ROWS"):
         assert getattr(kbe, "BUF_" + n) == e["KBE_BUF_" + n], n
     assert (inputs.PRECISION_FP64, inputs.PRECISION_FP32) == (e["KBE_FP64"], e["KBE_FP32"])
+    mx = re.search(r"#define KBE_NOALLOC_WORKSPACE_MAX \(\(size_t\)(\d+) << (\d+)\)", open(HEADER).read())
+    assert kbe.NOALLOC_WORKSPACE_MAX == int(mx.group(1)) << int(mx.group(2))
     assert (inputs.INTERACTION_HUBBARD, inputs.INTERACTION_INTERBAND) == (e["KBE_INT_HUBBARD"], e["KBE_INT_INTERBAND"])
     assert (inputs.PULSE_PEIERLS, inputs.PULSE_DIPOLE_KICK) == (e["KBE_PULSE_PEIERLS"], e["KBE_PULSE_DIPOLE_KICK"])
 

@@ -337,11 +337,34 @@ def main():
                 "history_sums_GBs": ach32, "history_sums_frac": ach32 / HBM_PEAK_GBS if ach32 else None,
                 "trajectory": r32["traj"], "trajectory_speedup_vs_fp64": r64["whole_s"] / r32["whole_s"],
                 "history_GB": round(r32["hist_gb"], 2),
-                "max_rel_err_vs_fp64": err, "error_over_steps": f"0..{cfg.nt}",
-                "workload": f"{c32.name}: history stored and summed in FP32"}
+                "max_rel_err_vs_fp64": err, "error_over_steps": f"0..{cfg.nt}", "kernel": "k_hist_pair32"
+                if cfg.nb <= 2 else ("k_hist_bulk32_split" if cfg.nb == 4 else "k_hist_bulk32"),
+                "workload": f"{c32.name}: history stored and summed in FP32 on the vector ALU"}
         print(f"[bench] FP32 form: steps {first}..{cfg.nt} in {r32['elapsed']:.3f} s = {K / r32['elapsed']:.1f} "
               f"steps/s ({elapsed / r32['elapsed']:.2f}x); history sums {ach32 or 0:.0f} GB/s; whole trajectory "
               f"{r32['traj']['steps_per_s']:.1f} steps/s ({r64['whole_s'] / r32['whole_s']:.2f}x); max rel err vs "
+              f"FP64 over {cfg.nt} steps {max(err.values()):.1e}", file=sys.stderr, flush=True)
+        fresh(S)
+        S = kbe.System(cfg)
+
+    mfma = None
+    if not args.no_fp32:
+        fresh(S)
+        cm = cfg.replace(precision=inputs.PRECISION_FP32_MFMA)
+        S, rm = run(cm)
+        names = {"n_band1": 14, "n_band0": 13, "n_orb0": 9, "n_orb1": 10, "Jx": 6, "Etot": 5, "N": 1}
+        err = _rel_devs(rm["obs"], obs, names)
+        achm = rm["kbytes"] / (rm["kms"] * 1e-3) / 1e9 if rm["kms"] > 0 else None
+        mfma = {"value": K / rm["elapsed"], "unit": "steps/s", "speedup_vs_fp64": elapsed / rm["elapsed"],
+                "history_sums_GBs": achm, "history_sums_frac": achm / HBM_PEAK_GBS if achm else None,
+                "kernel": "k_hist_mfma",
+                "trajectory": rm["traj"], "trajectory_speedup_vs_fp64": r64["whole_s"] / rm["whole_s"],
+                "history_GB": round(rm["hist_gb"], 2),
+                "max_rel_err_vs_fp64": err, "error_over_steps": f"0..{cfg.nt}",
+                "workload": f"{cm.name}: FP32 history, column sums on FP32 MFMA with hi/lo split Sigma"}
+        print(f"[bench] FP32-MFMA form: steps {first}..{cfg.nt} in {rm['elapsed']:.3f} s = {K / rm['elapsed']:.1f} "
+              f"steps/s ({elapsed / rm['elapsed']:.2f}x); history sums {achm or 0:.0f} GB/s; whole trajectory "
+              f"{rm['traj']['steps_per_s']:.1f} steps/s ({r64['whole_s'] / rm['whole_s']:.2f}x); max rel err vs "
               f"FP64 over {cfg.nt} steps {max(err.values()):.1e}", file=sys.stderr, flush=True)
         fresh(S)
         S = kbe.System(cfg)
@@ -458,6 +481,7 @@ def main():
                      "algorithmic_bytes_per_launch": kbytes / launches if launches else None},
         "cpu_baseline": cpu,
         "fp32_form": fp32,
+        "fp32_mfma_form": mfma,
         "adaptive_corrector": adaptive,
         "gregory": gregory,
         "paper_workload": paper,

@@ -57,7 +57,12 @@ enum {
                             real-space lines of the current row, (nt_max + 1) * 8 * N_k complex. */
 };
 
-enum { KBE_FP64 = 0, KBE_FP32 = 1 };
+/* Precision of the stored history and of the history sums (the rest of the step is FP64 in
+ * every form): KBE_FP64; KBE_FP32, FP32 storage summed on the vector ALU; KBE_FP32_MFMA, FP32
+ * storage in the quad layout below, the column sums of eq. (CI) on the FP32 matrix cores with
+ * the self-energy row split into FP32 hi + lo parts (compensated products, FP32 accumulation
+ * over 32-row tiles, FP64 across tiles) and the row sums on the vector ALU in FP32. */
+enum { KBE_FP64 = 0, KBE_FP32 = 1, KBE_FP32_MFMA = 2 };
 
 /* Observable columns of the per-step time series (see kbe_observables). */
 enum {
@@ -87,7 +92,7 @@ typedef struct {
   int32_t n_corr;       /* corrector passes K per step (>= 0); a step costs K+1 history passes.
                            With corr_tol > 0 the most passes a step may take. */
   int32_t nt_max;       /* largest step index the buffers hold */
-  int32_t precision;    /* KBE_FP64, or KBE_FP32: history stored and summed in FP32 (see below) */
+  int32_t precision;    /* KBE_FP64, KBE_FP32 or KBE_FP32_MFMA: history stored and summed in FP32 */
   int32_t quad_points;  /* quadrature of eq. (CI): 0 or 1 = the trapezoid rule (the second-order
                            quadrature of Sec. "Computational Kernels"); q = 2..6 = Gregory end corrections on q
                            nodes per end of each interval [0, N]: node j weighs
@@ -138,6 +143,12 @@ typedef struct kbe_ctx kbe_ctx;
  *             c = s * nb^2 + a * nb + b (s = 0: G^<, s = 1: G^>). In the FP32 form the
  *             components of a row segment are stored in pairs interleaved per column:
  *               elem = k C P + C (base(s) + 64 (j - 64 s)) + 128 (c / 2) + 2 (t' - 64 s) + c % 2.
+ *             In the FP32-MFMA form (KBE_FP32_MFMA) strip s holds its rows in quads of 4
+ *             (Q(s) = ceil((N - 64 s) / 4) quads, the last one padded); inside a quad the 64
+ *             columns form 4 groups g of 16, lane L = 16 (j % 4) + (t' % 16), and components
+ *             come in pairs ci = c / 2:
+ *               elem = k C P + 256 C (qbase(s) + (j - 64 s) / 4) + 2 (64 (g C / 2 + ci) + L) + c % 2,
+ *               qbase(s) = s ceil(N / 4) - 8 s (s - 1),  P = 256 qbase(ceil(N / 64)).
  *             Entries above the
  *             diagonal in a strip's first 64 rows are unused. Elements are complex128 (KBE_FP64)
  *             or complex64 (KBE_FP32). In the FP32 form the history sums read the FP32 history

@@ -47,7 +47,10 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
     return KBE_ERR_INVALID_ARG;
   }
   if (c->interaction == KBE_INT_INTERBAND && c->nb != 2) { *why = "the interband preset needs nb = 2"; return KBE_ERR_SHAPE; }
-  if (c->precision != KBE_FP64 && c->precision != KBE_FP32) { *why = "precision must be KBE_FP64 or KBE_FP32"; return KBE_ERR_INVALID_ARG; }
+  if (c->precision != KBE_FP64 && c->precision != KBE_FP32 && c->precision != KBE_FP32_MFMA) {
+    *why = "precision must be KBE_FP64, KBE_FP32 or KBE_FP32_MFMA";
+    return KBE_ERR_INVALID_ARG;
+  }
   if (c->n_corr < 0 || c->n_corr > 16) { *why = "n_corr must be 0..16"; return KBE_ERR_INVALID_ARG; }
   if (!(c->corr_tol >= 0.0) || !std::isfinite(c->corr_tol)) { *why = "corr_tol must be finite and >= 0"; return KBE_ERR_INVALID_ARG; }
   if (c->corr_tol > 0.0 && c->n_corr < 1) { *why = "corr_tol > 0 needs n_corr >= 1 (the most passes)"; return KBE_ERR_INVALID_ARG; }
@@ -65,12 +68,13 @@ int make_layout(const kbe_config* c, Layout* L, std::string* why) {
   d.C = 2 * d.nbb;
   d.Tp = ((c->nt_max + 1 + 7) / 8) * 8;
   d.Smax = (c->nt_max + 63) / 64;
-  d.fp32 = c->precision == KBE_FP32 ? 1 : 0;
-  d.spb = c->nb <= 2 ? 2 : 1;
+  d.fp32 = c->precision == KBE_FP64 ? 0 : 1;
+  d.mfma = c->precision == KBE_FP32_MFMA ? 1 : 0;
+  d.spb = (c->nb <= 2 && !d.mfma) ? 2 : 1;
   d.qp = c->quad_points > 1 ? c->quad_points : 1;
   d.rring = d.qp > 2 ? d.qp : 2;
   d.N = c->nt_max + 1;
-  d.P = kbe::strip_base((d.N + 63) / 64, d.N);
+  d.P = d.mfma ? 256 * kbe::quad_base((d.N + 63) / 64, d.N) : kbe::strip_base((d.N + 63) / 64, d.N);
   const size_t cz = sizeof(cplx);
   size_t nk = d.nk;
   size_t sz[B_COUNT];

@@ -84,6 +84,7 @@ struct Dims {
   int Tp;          // padded length of per-row buffers (>= nt_max + 1, multiple of 8)
   int Smax;        // number of 64-column strips of the largest history pass
   int fp32;        // 1: the packed history is stored in FP32 (complex64)
+  int mfma;        // 1: FP32 storage in the quad layout of the matrix-core history sums
   int spb;         // 64-column strips per row-partial slot group: 2 when one history-sum block
                    // covers a pair of strips (nb <= 2), else 1
   int qp;          // quadrature nodes per end carrying end corrections (1: trapezoid)
@@ -96,8 +97,26 @@ __host__ __device__ __forceinline__ int64_t seg_off(const Dims& d, int j, int tp
   int s = tp >> 6;
   return strip_base(s, d.N) + 64 * (int64_t)(j - 64 * s);
 }
+// Quad layout of the FP32-MFMA form. Strip s of a k holds its rows j = 64 s .. in quads of 4
+// rows (the last quad padded), Q(s) = ceil((N - 64 s) / 4) quads of 4 x 64 x C complex64
+// elements each. Inside a quad the 64 columns form 4 groups g of 16; lane L = 16 (j % 4) +
+// (t' % 16) of a wavefront holds the (row, column) pair that feeds the matrix cores as their
+// K x N operand tile, and the components come in pairs c = 2 ci, 2 ci + 1 (one 16-byte load):
+//   elem(k, c, j, t') = k C P + 256 C (qbase(s) + q) + 2 (64 (g C / 2 + ci) + L) + c % 2,
+//   q = (j - 64 s) / 4,  qbase(s) = sum_{s' < s} Q(s') = s Qn - 8 s (s - 1),  Qn = ceil(N / 4),
+//   P = 256 qbase(ceil(N / 64)).
+__host__ __device__ __forceinline__ int64_t quad_base(int64_t s, int64_t N) {
+  return s * ((N + 3) / 4) - 8 * s * (s - 1);
+}
 // Element index (complex units of the storage type).
 __host__ __device__ __forceinline__ int64_t hist_idx(const Dims& d, int k, int c, int j, int tp) {
+  if (d.mfma) {
+    int s = tp >> 6, rel = j - 64 * s;
+    int L = 16 * (rel & 3) + (tp & 15), g = (tp >> 4) & 3;
+    int64_t seg = quad_base(s, d.N) + (rel >> 2);
+    return (int64_t)k * d.C * d.P + 256 * (int64_t)d.C * seg + 2 * (64 * (int64_t)(g * (d.C >> 1) + (c >> 1)) + L) +
+           (c & 1);
+  }
   int64_t in_seg = d.fp32 ? 128 * (c >> 1) + 2 * (tp & 63) + (c & 1) : 64 * c + (tp & 63);
   return (int64_t)k * d.C * d.P + (int64_t)d.C * seg_off(d, j, tp) + in_seg;
 }

@@ -1503,6 +1503,257 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
+// ------------------------------------------------------------------ history sums, FP32-MFMA form
+// The same sums as above on the quad layout of the FP32-MFMA form. A block takes strip s of one
+// k; its wavefronts split the 64 columns into 4 groups g of 16 (and, at nb = 4, the components
+// into their G^< and G^> halves: 8 wavefronts; at nb <= 3 each wavefront takes both halves: 4).
+// Per quad of 4 rows a lane L holds the pair (j = j0 + L / 16, t' = 16 g + L % 16):
+// * column term, on the matrix cores: for component (half, b) the 16 x 16 tile
+//     D[m][t'] += sum_{r < 4} A_l^ri[m][r] G_{l b}^ri(j0 + r, t'),   m = (hi/lo, a, re/im),
+//   one v_mfma_f32_16x16x4f32 per (l, re/im) with K = the quad's 4 rows: A holds the real
+//   embedding of Sigma^R(t_j)_{a l} (re rows: [Re, -Im]; im rows: [Im, Re]) split into its FP32
+//   high part and the FP32 rounding of the remainder (rows m < 2 nb: high, 2 nb <= m < 4 nb: low),
+//   so the two compensated products fill the 16-row tile at nb = 4 and are added in FP64 at the
+//   end. The tiles accumulate in FP32 over 8 quads (32 rows), then into FP64 registers.
+// * row term, on the vector ALU in FP32: each lane forms sgn Sigma^{>,<}_{t'} (G_{j t'})^dag of its
+//   pair; a DPP reduce-scatter over the 16 lanes of each row (four rows at once) leaves one
+//   component per lane; the wavefronts' partials of a 32-row chunk are staged in LDS (two
+//   buffers) and, after one block barrier per chunk, added in a fixed order in FP64 and stored
+//   to the strip's row-partial slot with streaming stores.
+// Quads past the strip's triangle (its first 16) and below m run without bounds selects. The
+// next quad's loads are issued before the current quad is processed.
+__device__ __forceinline__ float split_part(double x, bool low) {
+  float hi = (float)x;
+  return low ? (float)(x - (double)hi) : hi;
+}
+template <int CTRL, int CNT>
+__device__ __forceinline__ void rs16_step(float* x, bool upper) {
+  if constexpr (CNT >= 2) {
+    constexpr int H = CNT / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      float keep = upper ? x[i + H] : x[i];
+      float send = upper ? x[i] : x[i + H];
+      x[i] = keep + dpp_f<CTRL>(send);
+    }
+  } else {
+    x[0] += dpp_f<CTRL>(x[0]);
+  }
+}
+// Reduce-scatter of VP values (a power of two) over the 16 lanes of each row: partners differ in
+// bit 3 (row mirror), bit 2 (half-row mirror), bit 1 and bit 0 (quad permutations) of the lane.
+// Afterwards lane l of a row holds the row sums of values (VP / 16) l .. (VP / 16) l + VP / 16 - 1
+// in x[0 ..] if VP >= 16, else of value l / (16 / VP) in x[0].
+template <int VP>
+__device__ __forceinline__ void reduce_scatter16(float (&x)[VP], int lane) {
+  rs16_step<0x140, VP>(x, lane & 8);
+  rs16_step<0x141, (VP / 2 > 1 ? VP / 2 : 1)>(x, lane & 4);
+  rs16_step<0x4E, (VP / 4 > 1 ? VP / 4 : 1)>(x, lane & 2);
+  rs16_step<0xB1, (VP / 8 > 1 ? VP / 8 : 1)>(x, lane & 1);
+}
+
+template <int NB>
+struct MfmaShape {
+  static constexpr int NBB = NB * NB, C = 2 * NBB;
+  static constexpr int HS = NB == 4 ? 1 : 2;          // component halves per wavefront
+  static constexpr int WAVES = 4 * (2 / HS);
+  static constexpr int NCH = HS == 2 ? NBB : NBB / 2;  // 16-byte loads per lane and quad
+  static constexpr int VP = 2 * NBB <= 2 ? 2 : (2 * NBB <= 8 ? 8 : 32);           // row-term values, padded
+  static constexpr int CQ = 8;                        // quads per staged chunk (32 rows)
+  static constexpr int STAGE = 2 * WAVES * CQ * 4 * VP * 4;  // bytes
+  static constexpr int FIN = WAVES * HS * NB * 256 * 8;     // bytes
+  static constexpr int LDS = STAGE > FIN ? STAGE : FIN;
+};
+
+template <int NB>
+__global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_mfma(
+    Dims d, const float2* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
+    cplx* __restrict__ rowpart, int m) {
+  using Sh = MfmaShape<NB>;
+  constexpr int NBB = Sh::NBB, C = Sh::C, HS = Sh::HS, NCH = Sh::NCH, VP = Sh::VP, CQ = Sh::CQ, WAVES = Sh::WAVES;
+  static_assert(NB != 4 || NBB % 2 == 0, "halves must not share a 16-byte load");
+  __shared__ __align__(16) unsigned char smem[Sh::LDS];
+  float* stg = reinterpret_cast<float*>(smem);  // [2][WAVES][CQ][4][VP]
+  const int s = blockIdx.x / d.nk;
+  const int k = blockIdx.x - s * d.nk;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = HS == 1 ? (wv >> 1) : wv;
+  const int h0 = HS == 1 ? (wv & 1) : 0;   // first component half of this wavefront
+  const int r = lane >> 4, n = lane & 15;
+  const int tp = 64 * s + 16 * g + n;
+  const bool colv = tp < m;
+  const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
+  // row-term Sigma of this lane's column: half 0 (G^<) takes -Sigma^>, half 1 (G^>) +Sigma^<
+  cplx32 Srow[HS * NBB];
+#pragma unroll
+  for (int hh = 0; hh < HS; ++hh) {
+    const int H = h0 + hh;
+    const float sg = H ? 1.f : -1.f;
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) {
+      cplx v = colv ? sk[((1 - H) * NBB + e) * d.Tp + tp] : czero();
+      Srow[hh * NBB + e] = make_float2(sg * (float)v.x, sg * (float)v.y);
+    }
+  }
+  // this lane's row of the A operand: m = n = (hi/lo, a, re/im)
+  const int mi = n;
+  const bool arow = mi < 4 * NB;
+  const bool low = mi >= 2 * NB;
+  const int aa = (mi % (2 * NB)) >> 1;
+  const bool im_row = mi & 1;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4 D[HS][NB];
+  double col[HS][NB][4];
+#pragma unroll
+  for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      D[hh][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) col[hh][b][v] = 0.0;
+    }
+  // lane's 16-byte loads of quad q: float4 index (q C 128) + (g C/2 + ci) 64 + lane
+  const kbe_f4v* hq = reinterpret_cast<const kbe_f4v*>(hist) +
+                      ((int64_t)k * C * d.P + 256 * (int64_t)C * quad_base(s, d.N)) / 2 +
+                      (int64_t)(g * (C / 2) + h0 * (NBB / 2)) * 64 + lane;
+  const int nq = (m - 64 * s + 3) >> 2;   // quads holding rows below m
+  kbe_f4v cur[NCH], nxt[NCH];
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) cur[i] = __builtin_nontemporal_load(hq + i * 64);
+  cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
+  int buf = 0;
+  for (int q0 = 0; q0 < nq; q0 += CQ) {
+    float* sb = stg + buf * (WAVES * CQ * 4 * VP);
+    for (int qc = 0; qc < CQ; ++qc) {
+      const int q = q0 + qc;
+      if (q >= nq) break;
+      if (q + 1 < nq) {
+        const kbe_f4v* nx = hq + (int64_t)(q + 1) * 128 * C;
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) nxt[i] = __builtin_nontemporal_load(nx + i * 64);
+      }
+      const int j0 = 64 * s + 4 * q;
+      const int j = j0 + r;
+      auto quad = [&](auto tag) {
+        constexpr bool MASKED = decltype(tag)::value;
+        cplx32 G[HS * NBB];
+        const bool valid = MASKED ? (colv && tp <= j && j < m) : true;
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+          G[2 * i] = valid ? make_float2(cur[i].x, cur[i].y) : make_float2(0.f, 0.f);
+          if (2 * i + 1 < HS * NBB) G[2 * i + 1] = valid ? make_float2(cur[i].z, cur[i].w) : make_float2(0.f, 0.f);
+        }
+        // A operand of this lane: Sigma^R(t_j)_{a l}, real-embedded and split
+        float Af[NB][2];
+        const bool aval = arow && (MASKED ? j < m : true);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+          cplx x = aval ? sk[(2 * NBB + aa * NB + l) * d.Tp + j] : czero();
+          float pr = split_part(x.x, low), pi = split_part(x.y, low);
+          Af[l][0] = im_row ? pi : pr;
+          Af[l][1] = im_row ? pr : -pi;
+        }
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+            for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const cplx32 gv = G[hh * NBB + l * NB + b];
+                D[hh][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[l][ri], ri ? gv.y : gv.x, D[hh][b], 0, 0, 0);
+              }
+        // row term of this lane's pair
+        float x[VP];
+#pragma unroll
+        for (int i = 0; i < VP; ++i) x[i] = 0.f;
+#pragma unroll
+        for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              cplx32 t = make_float2(0.f, 0.f);
+#pragma unroll
+              for (int l = 0; l < NB; ++l) cmacc32(t, Srow[hh * NBB + a * NB + l], G[hh * NBB + b * NB + l]);
+              x[2 * (a * NB + b)] += t.x;
+              x[2 * (a * NB + b) + 1] += t.y;
+            }
+        if constexpr (MASKED) {
+          const bool rv = tp < j;   // the diagonal belongs to the end-point terms
+#pragma unroll
+          for (int i = 0; i < VP; ++i) x[i] = rv ? x[i] : 0.f;
+        }
+        reduce_scatter16<VP>(x, lane);
+        float* row = sb + ((wv * CQ + qc) * 4 + r) * VP;
+        if constexpr (VP >= 16) {
+#pragma unroll
+          for (int i = 0; i < VP / 16; ++i) row[(VP / 16) * n + i] = x[i];
+        } else {
+          if (n % (16 / VP) == 0) row[n / (16 / VP)] = x[0];
+        }
+      };
+      if (q >= 16 && j0 + 4 <= m)
+        quad(BoolTag<false>{});
+      else
+        quad(BoolTag<true>{});
+#pragma unroll
+      for (int i = 0; i < NCH; ++i) cur[i] = nxt[i];
+    }
+    // FP32 tiles of this chunk into the FP64 column sums
+#pragma unroll
+    for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) col[hh][b][v] += (double)D[hh][b][v];
+        D[hh][b] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    __syncthreads();  // the chunk is staged by every wavefront; the other buffer is free again
+    // row partials of the chunk: the wavefronts' parts added in a fixed order
+    for (int o = threadIdx.x; o < 4 * CQ * NBB; o += WAVES * 64) {
+      const int e = o / (4 * CQ), rho = o - e * (4 * CQ);
+      const int jj = 64 * s + 4 * q0 + rho;
+      if (jj < m) {
+        double re = 0.0, im = 0.0;
+        for (int w = 0; w < WAVES; ++w) {
+          const float* src = sb + (w * CQ * 4 + rho) * VP + 2 * e;
+          re += (double)src[0];
+          im += (double)src[1];
+        }
+        store_stream(rp + (int64_t)e * d.Tp + jj, cmk(re, im));
+      }
+    }
+    buf ^= 1;
+  }
+  // column sums: high and low parts of each tile added in FP64 through LDS
+  __syncthreads();  // every wavefront is done with the staging buffers
+  double* fin = reinterpret_cast<double*>(smem) + (int64_t)wv * HS * NB * 256;
+#pragma unroll
+  for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fin[((hh * NB + b) * 16 + 4 * r + v) * 16 + n] = col[hh][b][v];
+  __syncthreads();
+  const int a = lane >> 4;
+  if (a < NB && colv) {
+#pragma unroll
+    for (int hh = 0; hh < HS; ++hh)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double* t = fin + (hh * NB + b) * 256;
+        const int mre = 2 * a, mim = 2 * a + 1, lo = 2 * NB;
+        double re = t[mre * 16 + n] + t[(lo + mre) * 16 + n];
+        double im = t[mim * 16 + n] + t[(lo + mim) * 16 + n];
+        const int c = (h0 + hh) * NBB + a * NB + b;
+        colsum[rowbuf_idx(d, k, c, tp)] = cmk(re, im);
+      }
+  }
+}
+
 // ------------------------------------------------------------------ row assembly and update
 // Thread per (k, t'), t' <= m.
 //  EVAL/CORRECT, t' < m: I^{<,>}(t_m, t') = dt [bulk + end-point terms], where the
@@ -2056,6 +2307,11 @@ struct Launch {
   static hipError_t bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
     if (m < 1) return hipSuccess;
     int ns = (m + 63) / 64;
+    if (d.mfma) {
+      hipLaunchKernelGGL(k_hist_mfma<NB>, dim3(ns * d.nk), dim3(MfmaShape<NB>::WAVES * 64), 0, st, d,
+                         (const float2*)a.hist, (const cplx*)a.sig, a.colsum, a.rowpart, m);
+      return hipGetLastError();
+    }
     if constexpr (NB <= 2) {
       int np = (ns + 1) / 2;  // pairs of strips
       if (d.fp32)

@@ -30,7 +30,8 @@ PULSE_PEIERLS = 0      # vector potential A(t) in the Bloch Hamiltonian
 PULSE_DIPOLE_KICK = 1  # eq. (dipole): E(t) = amp * delta(t - t0), d_k = 1 (nb = 2)
 
 PRECISION_FP64 = 0
-PRECISION_FP32 = 1
+PRECISION_FP32 = 1        # history stored and summed in FP32 on the vector ALU
+PRECISION_FP32_MFMA = 2   # history stored in FP32, column sums on the matrix cores (hi/lo split Sigma)
 
 
 @dataclass
@@ -128,8 +129,8 @@ def c2() -> Config:
 
 
 def c3() -> Config:
-    """C2 with the history sums in the FP32 split-precision form."""
-    return c2().replace(name="c3_sq24_nb2_fp32", precision=PRECISION_FP32)
+    """C2 with the history sums in the FP32 split-precision matrix-core form."""
+    return c2().replace(name="c3_sq24_nb2_fp32mfma", precision=PRECISION_FP32_MFMA)
 
 
 def c4() -> Config:

@@ -127,21 +127,34 @@ def strip_base(s: int, N: int) -> int:
     return 64 * s * N - 2048 * s * (s - 1)
 
 
-def plane_length(nt_max: int) -> int:
+def quad_base(s, N):
+    """Quads of 4 rows before strip s in the FP32-MFMA layout (include/kbe.h)."""
+    return s * ((N + 3) // 4) - 8 * s * (s - 1)
+
+
+def plane_length(nt_max: int, mfma: bool = False) -> int:
     """P of the history layout (include/kbe.h): one k occupies C * P elements."""
     N = nt_max + 1
+    if mfma:
+        return 256 * quad_base((N + 63) // 64, N)
     return strip_base((N + 63) // 64, N)
 
 
-def hist_offset(c, j, tp, nt_max: int, C: int, fp32: bool = False):
+def hist_offset(c, j, tp, nt_max: int, C: int, fp32: bool = False, mfma: bool = False):
     """Element offset of component c of (t_j, t'_tp), tp <= j, inside the C * P elements of one
     k (strip-major, component-interleaved layout; component pairs interleaved per column in
-    the FP32 form); elementwise on numpy integer arrays."""
+    the FP32 form; quads of 4 rows in the FP32-MFMA form); elementwise on numpy integer arrays."""
     N = nt_max + 1
     c = np.asarray(c, dtype=np.int64)
     j = np.asarray(j, dtype=np.int64)
     tp = np.asarray(tp, dtype=np.int64)
     s = tp >> 6
+    if mfma:
+        rel = j - 64 * s
+        lane = 16 * (rel & 3) + (tp & 15)
+        g = (tp >> 4) & 3
+        seg = quad_base(s, N) + (rel >> 2)
+        return 256 * C * seg + 2 * (64 * (g * (C // 2) + (c >> 1)) + lane) + (c & 1)
     in_seg = 128 * (c >> 1) + 2 * (tp & 63) + (c & 1) if fp32 else 64 * c + (tp & 63)
     return C * (64 * s * N - 2048 * s * (s - 1) + 64 * (j - 64 * s)) + in_seg
 
@@ -161,7 +174,8 @@ class System:
         self._cconf = _c_config(cfg, self.nt_max)
         hb, wb, ob = _query(self._cconf)
         dev = torch.device(device)
-        self.fp32 = cfg.precision == _inputs.PRECISION_FP32
+        self.fp32 = cfg.precision != _inputs.PRECISION_FP64
+        self.mfma = cfg.precision == _inputs.PRECISION_FP32_MFMA
         hdt = torch.complex64 if self.fp32 else torch.complex128
         self.history = torch.empty(hb // (8 if self.fp32 else 16), dtype=hdt, device=dev)
         self.workspace = None if noalloc else torch.empty(wb, dtype=torch.uint8, device=dev)
@@ -169,7 +183,7 @@ class System:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.nk, self.nb = cfg.nk, cfg.nb
         self.C = 2 * cfg.nb * cfg.nb
-        self.P = plane_length(self.nt_max)
+        self.P = plane_length(self.nt_max, self.mfma)
         self.Tp = ((self.nt_max + 1 + 7) // 8) * 8
         self._ctx = None
         self._create()
@@ -323,7 +337,7 @@ class System:
 
     def _row_index(self, j: int) -> torch.Tensor:
         c, tp = np.meshgrid(np.arange(self.C), np.arange(j + 1), indexing="ij")
-        idx = hist_offset(c.ravel(), j, tp.ravel(), self.nt_max, self.C, self.fp32)   # [c][t'] flattened
+        idx = hist_offset(c.ravel(), j, tp.ravel(), self.nt_max, self.C, self.fp32, self.mfma)   # [c][t'] flattened
         return torch.from_numpy(idx).to(self.history.device)
 
     def history_row(self, j: int) -> torch.Tensor:

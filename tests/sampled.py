@@ -15,6 +15,6 @@ def collision_reference(K, S, cfg, m, k, sig_all):
     rows = []
     for j in range(m + 1):
         c, tp = np.meshgrid(np.arange(C), np.arange(j + 1), indexing="ij")
-        blk = hk[K.hist_offset(c, j, tp, S.nt_max, C, S.fp32)]  # [C][t']
+        blk = hk[K.hist_offset(c, j, tp, S.nt_max, C, S.fp32, S.mfma)]  # [C][t']
         rows.append(blk.T.reshape(j + 1, 1, 2, nb, nb))
     return O.collision_row(cfg.replace(nkx=1, nky=1), m, rows, sig_all[:, k:k + 1])

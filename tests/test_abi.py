@@ -92,6 +92,42 @@ def test_history_layout_is_a_bijection():
                 assert pair[1] - pair[0] == 1
 
 
+def test_mfma_history_layout_is_a_bijection():
+    """FP32-MFMA quad layout: every stored (c, t_j, t') of one k maps to a distinct offset inside
+    its C * P elements; a quad of 4 rows of a strip is one contiguous run of 256 C elements and
+    the quads of a strip follow each other; for one (quad, column group, component pair) the 64
+    lanes L = 16 (j % 4) + (t' % 16) read 64 consecutive 16-byte pairs (one 1 KB load)."""
+    import numpy as np
+    from paper_2505_19467_amd import kbe
+    for nt, C in ((1, 2), (63, 8), (64, 8), (65, 2), (200, 8), (1000, 8), (130, 32), (70, 18), (66, 32)):
+        N = nt + 1
+        P = kbe.plane_length(nt, mfma=True)
+        j, tp = np.tril_indices(N)
+        c = np.repeat(np.arange(C), len(j))
+        off = kbe.hist_offset(c, np.tile(j, C), np.tile(tp, C), nt, C, True, True)
+        assert off.min() >= 0 and off.max() < C * P
+        assert len(np.unique(off)) == len(off)
+        # unused: one 64x64 triangle per strip and component, plus at most 3 padding rows per strip
+        assert C * P - len(off) <= C * ((nt + 64) // 64) * (64 * 63 // 2 + 3 * 64)
+        for s in range(0, (N + 63) // 64):
+            nq = (N - 64 * s + 3) // 4
+            assert kbe.quad_base(s + 1, N) - kbe.quad_base(s, N) == nq
+            rows = np.arange(64 * s, N)
+            starts = kbe.hist_offset(0, rows[::4], np.full(len(rows[::4]), 64 * s), nt, C, True, True)
+            assert np.all(np.diff(starts) == 256 * C)
+        # one 16-byte load of lane L: components 2 ci, 2 ci + 1 of its pair are adjacent, and
+        # lane L + 1 continues where lane L ends
+        s, q, g, ci = 0, 8, 1, C // 2 - 1   # rows 32..35, columns 16..31: all stored
+        lanes = np.arange(64)
+        jj, tt = 64 * s + 4 * q + lanes // 16, 64 * s + 16 * g + lanes % 16
+        keep = tt <= jj
+        assert keep.all()
+        e0 = kbe.hist_offset(2 * ci, jj, tt, max(nt, 80), C, True, True)
+        e1 = kbe.hist_offset(2 * ci + 1, jj, tt, max(nt, 80), C, True, True)
+        assert np.all(e1 - e0 == 1)
+        assert np.all(e0[keep] == e0[0] + 2 * lanes[keep])
+
+
 def test_create_rejects_undersized_buffers():
     """kbe_create checks every buffer size against the layout of its own config before it
     launches anything (so this runs without a GPU): one element short in any buffer, or a
@@ -218,7 +254,8 @@ def test_binding_constants_match_header():
         assert kbe.OBS[col] == e[name], col
     for n in ("SIGMA", "I_PREV", "I_CUR", "RHO_PREV", "RHO_CUR", "D_PREV", "D_CUR", "PROP", "COL0", "DIAG", "ROWS"):
         assert getattr(kbe, "BUF_" + n) == e["KBE_BUF_" + n], n
-    assert (inputs.PRECISION_FP64, inputs.PRECISION_FP32) == (e["KBE_FP64"], e["KBE_FP32"])
+    assert (inputs.PRECISION_FP64, inputs.PRECISION_FP32, inputs.PRECISION_FP32_MFMA) == \
+        (e["KBE_FP64"], e["KBE_FP32"], e["KBE_FP32_MFMA"])
     mx = re.search(r"#define KBE_NOALLOC_WORKSPACE_MAX \(\(size_t\)(\d+) << (\d+)\)", open(HEADER).read())
     assert kbe.NOALLOC_WORKSPACE_MAX == int(mx.group(1)) << int(mx.group(2))
     assert (inputs.INTERACTION_HUBBARD, inputs.INTERACTION_INTERBAND) == (e["KBE_INT_HUBBARD"], e["KBE_INT_INTERBAND"])

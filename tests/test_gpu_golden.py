@@ -105,6 +105,11 @@ def test_c2_full_run_fp32_form_matches_oracle(K):
     _compare_c2(K, inputs.c2().replace(precision=inputs.PRECISION_FP32), FP32_TOL)
 
 
+def test_c2_full_run_fp32_mfma_form_matches_oracle(K):
+    _say("golden: 24x24 nb=2 FP32-MFMA form, 1000 steps")
+    _compare_c2(K, inputs.c3(), FP32_TOL)
+
+
 def test_c4_full_gradient_matches_tangent_linear_oracle(K):
     """The gradient workload at its full length: d n_band1(t_400) / d(amp, omega, U)."""
     _say("golden: 12x12 nb=2 reverse sweep over 400 steps vs the tangent-linear oracle")

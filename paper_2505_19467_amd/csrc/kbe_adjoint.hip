@@ -45,6 +45,13 @@ __device__ __forceinline__ void mm_acc_adag(cplx* acc, const cplx* A, const cplx
 //   lam^s_{jt'} += dt SR_j^dag Ibar^s(t');   t' < j:  lam^< -= dt Irow(j)^dag S^>_{t'}, lam^> += dt Irow(j)^dag S^<_{t'}
 //   SRbar_j     += dt sum_{t'} sum_s Ibar^s(t') G^s_{jt'}^dag           (across lanes, per strip)
 //   Sbar^>_{t'} -= dt sum_{j > t'} Irow(j) G^<_{jt'},  Sbar^<_{t'} += dt sum_{j > t'} Irow(j) G^>_{jt'}   (in lane)
+// Layout of the work as in the forward history sums: block = (strip s, k); lane l owns column
+// 64 s + l (its Sigma, Ibar and Sigma-adjoint column sums in registers); each wavefront takes 16
+// consecutive rows of every 64-row chunk, one row per iteration (the history block and the
+// adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight, then C 1 KB stores).
+// The SRbar row partial of a row (nb^2 components) goes through one 64-lane reduce-scatter with
+// the components as groups; a wavefront's 16 row partials are staged in LDS and stored as 256-byte
+// runs. Rows past the strip's first 64 (and below m) run without bounds selects.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ lam,
                                                   const cplx* __restrict__ sig, const cplx* __restrict__ Ibar,
@@ -52,13 +59,14 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
                                                   int m, double dt) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int CH = (C < 8) ? C : 8;
-  constexpr int R = NB == 1 ? 2 : 1;
   __shared__ cplx red[3][CH][64];
-  int s = blockIdx.x / d.nk;
-  int k = blockIdx.x - s * d.nk;
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int tp = 64 * s + lane;
-  bool colv = tp < m;
+  __shared__ cplx stg[4][NBB * 16];
+  const int s = blockIdx.x / d.nk;
+  const int k = blockIdx.x - s * d.nk;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // rows wavefront-uniform
+  const int tp = 64 * s + lane;
+  const bool colv = tp < m;
   const cplx* sk = sig + (int64_t)k * 3 * NBB * d.Tp;
   cplx Sl[NBB], Sg[NBB], Ib[C];
 #pragma unroll
@@ -71,105 +79,102 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   cplx acc[C];  // [0, NBB): Sbar^<_{t'}, [NBB, C): Sbar^>_{t'}
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
-  int64_t base = strip_lane_base(d, k, s, lane);
+  const int64_t base = strip_lane_base(d, k, s, lane);
   const cplx* hk = hist + base;
   cplx* lk = lam + base;
   cplx* rp = sbar_rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
-  for (int jb = 64 * s + R * wv; jb < m; jb += 4 * R) {
-    cplx G[R][C], L[R][C];
+  cplx* st = stg[wv];
+  for (int cb = 64 * s; cb < m; cb += 64) {
+    const int rb = cb + 16 * wv;
+    for (int i = 0; i < 16; ++i) {
+      const int j = rb + i;
+      if (j >= m) break;
+      auto row = [&](auto tag) {
+        constexpr bool MASKED = decltype(tag)::value;
+        const bool v = MASKED ? (colv && tp <= j) : true;
+        const int64_t off = 64 * (int64_t)C * j;
+        cplx G[C], L[C];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int j = jb + r;
-      bool v = colv && tp <= j && j < m;
-      int64_t off = 64 * (int64_t)C * j;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        G[r][c] = v ? hk[off + 64 * c] : czero();
-        L[r][c] = v ? lk[off + 64 * c] : czero();
-      }
-    }
-    double rt[R][2 * NBB];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int j = jb + r;
-      bool v = colv && tp <= j && j < m;
-      int jc = j < m ? j : m - 1;
-      cplx SR[NBB], Irow[NBB];
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        SR[e] = sk[(2 * NBB + e) * d.Tp + jc];
-        Irow[e] = cadd(Ibar[rowbuf_idx(d, k, e, jc)], Ibar[rowbuf_idx(d, k, NBB + e, jc)]);
-      }
-      bool rv = tp < j;
-      // adjoint history
-      cplx dl[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) dl[c] = czero();
-      mm_acc_adag<NB>(dl, SR, Ib);
-      mm_acc_adag<NB>(dl + NBB, SR, Ib + NBB);
-      if (rv) {
-        cplx u[NBB], w[NBB];
-        mat_zero<NB>(u);
-        mat_zero<NB>(w);
-        mm_acc_adag<NB>(u, Irow, Sg);
-        mm_acc_adag<NB>(w, Irow, Sl);
+        for (int c = 0; c < C; ++c) {
+          G[c] = v ? load_stream(hk + off + 64 * c) : czero();
+          L[c] = v ? load_stream(lk + off + 64 * c) : czero();
+        }
+        cplx SR[NBB], Irow[NBB];
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
-          dl[e] = csub(dl[e], u[e]);
-          dl[NBB + e] = cadd(dl[NBB + e], w[e]);
+          SR[e] = sk[(2 * NBB + e) * d.Tp + j];
+          Irow[e] = cadd(Ibar[rowbuf_idx(d, k, e, j)], Ibar[rowbuf_idx(d, k, NBB + e, j)]);
         }
-        // Sigma adjoints of the row term (in lane)
-        cplx x[NBB], y[NBB];
-        mat_zero<NB>(x);
-        mat_zero<NB>(y);
-        mm_acc<NB>(x, Irow, G[r] + NBB);  // Irow G^>  -> Sbar^<
-        mm_acc<NB>(y, Irow, G[r]);        // Irow G^<  -> -Sbar^>
+        const bool rv = MASKED ? tp < j : true;
+        // adjoint history
+        cplx dl[C];
 #pragma unroll
-        for (int e = 0; e < NBB; ++e) {
-          acc[e] = cadd(acc[e], cscal(x[e], dt));
-          acc[NBB + e] = csub(acc[NBB + e], cscal(y[e], dt));
+        for (int c = 0; c < C; ++c) dl[c] = czero();
+        mm_acc_adag<NB>(dl, SR, Ib);
+        mm_acc_adag<NB>(dl + NBB, SR, Ib + NBB);
+        if (rv) {
+          cplx u[NBB], w[NBB];
+          mat_zero<NB>(u);
+          mat_zero<NB>(w);
+          mm_acc_adag<NB>(u, Irow, Sg);
+          mm_acc_adag<NB>(w, Irow, Sl);
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) {
+            dl[e] = csub(dl[e], u[e]);
+            dl[NBB + e] = cadd(dl[NBB + e], w[e]);
+          }
+          // Sigma adjoints of the row term (in lane)
+          cplx x[NBB], y[NBB];
+          mat_zero<NB>(x);
+          mat_zero<NB>(y);
+          mm_acc<NB>(x, Irow, G + NBB);  // Irow G^>  -> Sbar^<
+          mm_acc<NB>(y, Irow, G);        // Irow G^<  -> -Sbar^>
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) {
+            acc[e] = cadd(acc[e], cscal(x[e], dt));
+            acc[NBB + e] = csub(acc[NBB + e], cscal(y[e], dt));
+          }
         }
-      }
-      if (v) {
-        int64_t off = 64 * (int64_t)C * j;
+        if (v) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) lk[off + 64 * c] = cadd(L[r][c], cscal(dl[c], dt));
-      }
-      // SRbar_j partial: sum_s Ibar^s G^s^dag (lanes with a stored block)
-      cplx q[NBB];
-      mat_zero<NB>(q);
-      if (v) {
-        mm_acc_bdag<NB>(q, Ib, G[r]);
-        mm_acc_bdag<NB>(q, Ib + NBB, G[r] + NBB);
-      }
+          for (int c = 0; c < C; ++c) store_stream(lk + off + 64 * c, cadd(L[c], cscal(dl[c], dt)));
+        }
+        // SRbar_j partial: sum_s Ibar^s G^s^dag (zero where no block is stored)
+        cplx q[NBB];
+        mat_zero<NB>(q);
+        mm_acc_bdag<NB>(q, Ib, G);
+        mm_acc_bdag<NB>(q, Ib + NBB, G + NBB);
+        if constexpr (NBB == 4) {
+          // the four components are the four groups of one reduce-scatter
+          double xg[4][2];
 #pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        rt[r][2 * e] = q[e].x * dt;
-        rt[r][2 * e + 1] = q[e].y * dt;
-      }
-    }
+          for (int e = 0; e < 4; ++e) {
+            xg[e][0] = q[e].x * dt;
+            xg[e][1] = q[e].y * dt;
+          }
+          reduce_rows<4>(xg);
+          const int e = reduced_row<4>(lane);
+          if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
+        } else {
+          double rt[1][2 * NBB];
 #pragma unroll
-    for (int q = 0; q < 2 * NBB; ++q) {
-      double y;
-      if constexpr (R == 2) {
-        double x = rs_half(rt[0][q], rt[1][q]);
-        y = rs_row(x, x);
-      } else {
-        double x = rs_half(rt[0][q], rt[0][q]);
-        y = rs_row(x, x);
-      }
-      rt[0][q] = row16_sum(y);
-    }
-    int rsel = -1;
-    if constexpr (R == 2) {
-      if ((lane & 31) == 0) rsel = lane >> 5;
-    } else {
-      if (lane == 0) rsel = 0;
-    }
-    if (rsel >= 0 && jb + rsel < m) {
+          for (int e = 0; e < NBB; ++e) {
+            rt[0][2 * e] = q[e].x * dt;
+            rt[0][2 * e + 1] = q[e].y * dt;
+          }
+          reduce_rows<1>(rt);
+          if (reduced_row<1>(lane) >= 0) {
 #pragma unroll
-      for (int e = 0; e < NBB; ++e) rp[(int64_t)e * d.Tp + jb + rsel] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * 16 + i] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+          }
+        }
+      };
+      if (j >= 64 * s + 64)
+        row(BoolTag<false>{});
+      else
+        row(BoolTag<true>{});
     }
+    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
   }
 #pragma unroll
   for (int c0 = 0; c0 < C; c0 += CH) {

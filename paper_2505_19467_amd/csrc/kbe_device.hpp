@@ -368,7 +368,13 @@ __device__ __forceinline__ double row16_sum(double x) {
 }
 
 
-// ------------------------------------------------------------------ factorised line transforms
+// ------------------------------------------------------------------ history streams and row partials
+// Compile-time flag for the masked and unmasked copies of a loop body.
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
 // Keep the compiler from moving LDS accesses of one wavefront across this point (the lanes of
 // a wavefront exchange values through LDS; the hardware executes them in order).
 __device__ __forceinline__ void wave_sync() {
@@ -376,6 +382,67 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// History blocks are read once per pass: stream them past the caches.
+typedef double kbe_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx load_stream(const cplx* p) {
+  kbe_d2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_d2v*>(p));
+  return make_double2(v.x, v.y);
+}
+// Streaming store of one complex value (row partials are not read again in this pass).
+__device__ __forceinline__ void store_stream(cplx* p, cplx v) {
+  kbe_d2v w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<kbe_d2v*>(p));
+}
+
+// Reduce-scatter of the row terms of R rows (R = 1, 2, 4) over the 64 lanes: half-wave and
+// 16-lane-row permlane swaps, then DPP within rows. Afterwards rt[0][q] holds whole-row sums
+// in the lanes for which reduced_row<R>(lane) >= 0 names the row:
+//   R = 4: lanes 0-15 row 0, 32-47 row 1, 16-31 row 2, 48-63 row 3
+//   R = 2: lanes 0-31 row 0, 32-63 row 1;   R = 1: every lane row 0
+template <int R, int Q>
+__device__ __forceinline__ void reduce_rows(double (&rt)[R][Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double y;
+    if constexpr (R == 4) {
+      y = rs_row(rs_half(rt[0][q], rt[1][q]), rs_half(rt[2][q], rt[3][q]));
+    } else if constexpr (R == 2) {
+      double x = rs_half(rt[0][q], rt[1][q]);
+      y = rs_row(x, x);
+    } else {
+      double x = rs_half(rt[0][q], rt[0][q]);
+      y = rs_row(x, x);
+    }
+    rt[0][q] = row16_sum(y);
+  }
+}
+// the one lane per row that stores it (-1: none)
+template <int R>
+__device__ __forceinline__ int reduced_row(int lane) {
+  if constexpr (R == 4) {
+    return (lane & 15) == 0 ? (((lane >> 5) & 1) | (((lane >> 4) & 1) << 1)) : -1;
+  } else if constexpr (R == 2) {
+    return (lane & 31) == 0 ? (lane >> 5) : -1;
+  } else {
+    return lane == 0 ? 0 : -1;
+  }
+}
+// A wavefront's 16 staged rows (st[e * 16 + r], nb^2 components) to rows rb .. rb + 15 of a
+// row-partial slot: 16 consecutive rows per component, 256 contiguous bytes, streaming stores.
+template <int NBB>
+__device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int rb, int m, int lane) {
+  wave_sync();
+#pragma unroll
+  for (int q = lane; q < NBB * 16; q += 64) {
+    int row = rb + (q & 15);
+    if (row < m) store_stream(rp + (int64_t)(q >> 4) * Tp + row, st[q]);
+  }
+  wave_sync();
+}
+
+
+// ------------------------------------------------------------------ factorised line transforms
 
 // Roots of unity tw[u] = e^{+2 pi i u / n}, u < n, into an LDS table (the block's threads in turn).
 __device__ __forceinline__ void fill_roots(cplx* tw, int n) {

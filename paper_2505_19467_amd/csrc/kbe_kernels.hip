@@ -24,11 +24,6 @@
 
 namespace kbe {
 
-template <bool B>
-struct BoolTag {
-  static constexpr bool value = B;
-};
-
 // ------------------------------------------------------------------ utility
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -609,24 +604,12 @@ __global__ __launch_bounds__(256) void k_diag_I(Dims d, const cplx* __restrict__
 }
 
 // ------------------------------------------------------------------ history sums (hot loop)
-// History blocks are read once per pass: stream them past the caches.
-typedef double kbe_d2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ cplx load_stream(const cplx* p) {
-  kbe_d2v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_d2v*>(p));
-  return make_double2(v.x, v.y);
-}
 typedef float kbe_f4v __attribute__((ext_vector_type(4)));
 // two complex64 values (a component pair of one column) in one 16-byte load
 __device__ __forceinline__ void load_stream32x2(const float2* p, float2& a, float2& b) {
   kbe_f4v v = __builtin_nontemporal_load(reinterpret_cast<const kbe_f4v*>(p));
   a = make_float2(v.x, v.y);
   b = make_float2(v.z, v.w);
-}
-
-// Streaming store of one complex value (row partials are not read again in this pass).
-__device__ __forceinline__ void store_stream(cplx* p, cplx v) {
-  kbe_d2v w = {v.x, v.y};
-  __builtin_nontemporal_store(w, reinterpret_cast<kbe_d2v*>(p));
 }
 
 typedef float2 cplx32;
@@ -665,28 +648,6 @@ __device__ __forceinline__ float row16_sum32(float x) {
   return x;
 }
 
-// Reduce-scatter of the row terms of R rows (R = 1, 2, 4) over the 64 lanes: half-wave and
-// 16-lane-row permlane swaps, then DPP within rows. Afterwards rt[0][q] holds whole-row sums
-// in the lanes for which reduced_row<R>(lane) >= 0 names the row:
-//   R = 4: lanes 0-15 row 0, 32-47 row 1, 16-31 row 2, 48-63 row 3
-//   R = 2: lanes 0-31 row 0, 32-63 row 1;   R = 1: every lane row 0
-template <int R, int Q>
-__device__ __forceinline__ void reduce_rows(double (&rt)[R][Q]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double y;
-    if constexpr (R == 4) {
-      y = rs_row(rs_half(rt[0][q], rt[1][q]), rs_half(rt[2][q], rt[3][q]));
-    } else if constexpr (R == 2) {
-      double x = rs_half(rt[0][q], rt[1][q]);
-      y = rs_row(x, x);
-    } else {
-      double x = rs_half(rt[0][q], rt[0][q]);
-      y = rs_row(x, x);
-    }
-    rt[0][q] = row16_sum(y);
-  }
-}
 template <int R, int Q>
 __device__ __forceinline__ void reduce_rows32(float (&rt)[R][Q]) {
 #pragma unroll
@@ -704,30 +665,6 @@ __device__ __forceinline__ void reduce_rows32(float (&rt)[R][Q]) {
     rt[0][q] = row16_sum32(y);
   }
 }
-// the one lane per row that stores it (-1: none)
-template <int R>
-__device__ __forceinline__ int reduced_row(int lane) {
-  if constexpr (R == 4) {
-    return (lane & 15) == 0 ? (((lane >> 5) & 1) | (((lane >> 4) & 1) << 1)) : -1;
-  } else if constexpr (R == 2) {
-    return (lane & 31) == 0 ? (lane >> 5) : -1;
-  } else {
-    return lane == 0 ? 0 : -1;
-  }
-}
-// A wavefront's 16 staged rows (st[e * 16 + r], nb^2 components) to rows rb .. rb + 15 of a
-// row-partial slot: 16 consecutive rows per component, 256 contiguous bytes, streaming stores.
-template <int NBB>
-__device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int rb, int m, int lane) {
-  wave_sync();
-#pragma unroll
-  for (int q = lane; q < NBB * 16; q += 64) {
-    int row = rb + (q & 15);
-    if (row < m) store_stream(rp + (int64_t)(q >> 4) * Tp + row, st[q]);
-  }
-  wave_sync();
-}
-
 // The nb = 4 kernels' two component halves stage the row partials of the same 16 rows; after a
 // block barrier each of the two wavefronts stores half of the nb^2 components of their sum
 // (st0 + st1, a fixed order) to rows rb .. rb + 15 of the strip's slot, 256-byte runs.
@@ -1514,14 +1451,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 //   embedding of Sigma^R(t_j)_{a l} (re rows: [Re, -Im]; im rows: [Im, Re]) split into its FP32
 //   high part and the FP32 rounding of the remainder (rows m < 2 nb: high, 2 nb <= m < 4 nb: low),
 //   so the two compensated products fill the 16-row tile at nb = 4 and are added in FP64 at the
-//   end. The tiles accumulate in FP32 over 8 quads (32 rows), then into FP64 registers.
+//   end. The tiles accumulate in FP32 over one chunk of quads (8 quads = 32 rows at nb = 4, 16
+//   quads = 64 rows otherwise), then into FP64 registers. The A operands of a chunk are split and
+//   staged in LDS once per block, one chunk ahead, by all its threads (every wavefront of the block
+//   needs the same rows).
 // * row term, on the vector ALU in FP32: each lane forms sgn Sigma^{>,<}_{t'} (G_{j t'})^dag of its
 //   pair; a DPP reduce-scatter over the 16 lanes of each row (four rows at once) leaves one
-//   component per lane; the wavefronts' partials of a 32-row chunk are staged in LDS (two
-//   buffers) and, after one block barrier per chunk, added in a fixed order in FP64 and stored
-//   to the strip's row-partial slot with streaming stores.
+//   component per lane; the wavefronts' partials of a chunk are staged in LDS (two buffers) and,
+//   after one block barrier per chunk, added in a fixed order in FP64 and stored to the strip's
+//   row-partial slot with streaming stores.
 // Quads past the strip's triangle (its first 16) and below m run without bounds selects. The
-// next quad's loads are issued before the current quad is processed.
+// next quad's loads are issued before the current quad is processed, and no load sits behind a
+// branch, so the waits for one quad's data are exact.
 __device__ __forceinline__ float split_part(double x, bool low) {
   float hi = (float)x;
   return low ? (float)(x - (double)hi) : hi;
@@ -1559,21 +1500,68 @@ struct MfmaShape {
   static constexpr int WAVES = 4 * (2 / HS);
   static constexpr int NCH = HS == 2 ? NBB : NBB / 2;  // 16-byte loads per lane and quad
   static constexpr int VP = 2 * NBB <= 2 ? 2 : (2 * NBB <= 8 ? 8 : 32);           // row-term values, padded
-  static constexpr int CQ = 8;                        // quads per staged chunk (32 rows)
+  static constexpr int CQ = NB == 4 ? 8 : 16;         // quads per staged chunk (32 or 64 rows)
+  static constexpr int PF = 1;                        // quads whose loads are in flight ahead
   static constexpr int STAGE = 2 * WAVES * CQ * 4 * VP * 4;  // bytes
+  static constexpr int AFR = 2 * CQ * 64 * 2 * NB * 4;       // bytes: A operands of two chunks
   static constexpr int FIN = WAVES * HS * NB * 256 * 8;     // bytes
-  static constexpr int LDS = STAGE > FIN ? STAGE : FIN;
+  static constexpr int LDS = (STAGE + AFR) > FIN ? (STAGE + AFR) : FIN;
+};
+
+// A operands of the quads of one chunk, [quad][lane][l][re/im] (2 nb floats per lane): lane
+// L = 16 r + n of quad q gives row n = (hi/lo, a, re/im) of the real embedding of
+// Sigma^R(t_j)_{a l}, j = 64 s + 4 q + r, split into the FP32 high part and the FP32 rounding of
+// the remainder; zero outside the 4 nb rows of the tile and for j >= m. Each thread takes
+// entries e = tid, tid + block, ...: load() issues the FP64 reads, store() splits and writes.
+template <int NB, int NE>
+struct AfrFill {
+  static_assert(NE * MfmaShape<NB>::WAVES * 64 == MfmaShape<NB>::CQ * 64, "every thread fills NE whole entries");
+  cplx x[NE][NB];
+  double z[NE];
+  // every lane loads a valid entry (row clamped below m); entries outside the tile or past m are
+  // zeroed only in store(), so no branch or early use sits behind the loads and the waits for
+  // the quads' history loads stay exact
+  __device__ __forceinline__ void load(const Dims& d, const cplx* sk, int s, int qfirst, int m, int tid, int nthr) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * nthr;
+      const int L = e & 63, n = L & 15;
+      const int j = 64 * s + 4 * (qfirst + (e >> 6)) + (L >> 4);
+      z[i] = (n < 4 * NB && j < m) ? 1.0 : 0.0;
+      const int aa = (n % (2 * NB)) >> 1;
+      const int jl = j < m ? j : m - 1;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) x[i][l] = sk[(2 * NB * NB + aa * NB + l) * d.Tp + jl];
+    }
+  }
+  __device__ __forceinline__ void store(float* afr, int tid, int nthr) const {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + i * nthr;
+      const int n = e & 15;
+      const bool low = n >= 2 * NB, im_row = n & 1;
+      float* dst = afr + e * 2 * NB;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) {
+        const float pr = split_part(x[i][l].x * z[i], low), pi = split_part(x[i][l].y * z[i], low);
+        dst[2 * l] = im_row ? pi : pr;
+        dst[2 * l + 1] = im_row ? pr : -pi;
+      }
+    }
+  }
 };
 
 template <int NB>
-__global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_mfma(
+__global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_hist_mfma(
     Dims d, const float2* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
     cplx* __restrict__ rowpart, int m) {
   using Sh = MfmaShape<NB>;
   constexpr int NBB = Sh::NBB, C = Sh::C, HS = Sh::HS, NCH = Sh::NCH, VP = Sh::VP, CQ = Sh::CQ, WAVES = Sh::WAVES;
-  static_assert(NB != 4 || NBB % 2 == 0, "halves must not share a 16-byte load");
+  static_assert(HS == 2 || NBB % 2 == 0, "halves must not share a 16-byte load");
   __shared__ __align__(16) unsigned char smem[Sh::LDS];
   float* stg = reinterpret_cast<float*>(smem);  // [2][WAVES][CQ][4][VP]
+  float* afr = reinterpret_cast<float*>(smem + Sh::STAGE);  // [2][CQ][64][2 nb]
+  constexpr int NTHR = WAVES * 64, NE = (CQ * 64 + NTHR - 1) / NTHR;
   const int s = blockIdx.x / d.nk;
   const int k = blockIdx.x - s * d.nk;
   const int lane = threadIdx.x & 63;
@@ -1596,12 +1584,6 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
       Srow[hh * NBB + e] = make_float2(sg * (float)v.x, sg * (float)v.y);
     }
   }
-  // this lane's row of the A operand: m = n = (hi/lo, a, re/im)
-  const int mi = n;
-  const bool arow = mi < 4 * NB;
-  const bool low = mi >= 2 * NB;
-  const int aa = (mi % (2 * NB)) >> 1;
-  const bool im_row = mi & 1;
   typedef float f4 __attribute__((ext_vector_type(4)));
   f4 D[HS][NB];
   double col[HS][NB][4];
@@ -1618,21 +1600,46 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
                       ((int64_t)k * C * d.P + 256 * (int64_t)C * quad_base(s, d.N)) / 2 +
                       (int64_t)(g * (C / 2) + h0 * (NBB / 2)) * 64 + lane;
   const int nq = (m - 64 * s + 3) >> 2;   // quads holding rows below m
-  kbe_f4v cur[NCH], nxt[NCH];
+  constexpr int PF = Sh::PF, RING = PF + 1;
+  static_assert(CQ % RING == 0, "a chunk holds whole turns of the load ring");
+  // quad x lives in ring[x % RING]; its loads are issued while quad x - PF is processed
+  kbe_f4v ring[RING][NCH];
+  // loads are never behind a branch (a quad index past the last is clamped to it), so the
+  // waits for one quad's data leave the later quads' loads in flight. Quads q < 4 g lie wholly
+  // above the diagonal for this wavefront's columns (16 g .. 16 g + 15 of the strip): their loads
+  // are pointed at quad 4 g, which the wavefront reads anyway (cache hits instead of HBM traffic
+  // for the unused part of the strip's triangle); the masks zero them.
+  const int qlo = 4 * g < nq - 1 ? 4 * g : nq - 1;
 #pragma unroll
-  for (int i = 0; i < NCH; ++i) cur[i] = __builtin_nontemporal_load(hq + i * 64);
+  for (int u = 0; u < PF; ++u) {
+    const int qu = u < qlo ? qlo : (u < nq ? u : nq - 1);
+#pragma unroll
+    for (int i = 0; i < NCH; ++i) ring[u][i] = __builtin_nontemporal_load(hq + (int64_t)qu * 128 * C + i * 64);
+  }
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, s));
+  AfrFill<NB, NE> fill;
+  fill.load(d, sk, s, 0, m, threadIdx.x, NTHR);
+  fill.store(afr, threadIdx.x, NTHR);
+  __syncthreads();
   int buf = 0;
   for (int q0 = 0; q0 < nq; q0 += CQ) {
     float* sb = stg + buf * (WAVES * CQ * 4 * VP);
-    for (int qc = 0; qc < CQ; ++qc) {
-      const int q = q0 + qc;
-      if (q >= nq) break;
-      if (q + 1 < nq) {
-        const kbe_f4v* nx = hq + (int64_t)(q + 1) * 128 * C;
+    const float* ab = afr + buf * (CQ * 64 * 2 * NB);
+    const bool more = q0 + CQ < nq;
+    if (more) fill.load(d, sk, s, q0 + CQ, m, threadIdx.x, NTHR);  // the next chunk's A operands
+    for (int qt = 0; qt < CQ; qt += RING) {
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) nxt[i] = __builtin_nontemporal_load(nx + i * 64);
+    for (int u = 0; u < RING; ++u) {
+      const int qc = qt + u;
+      const int q = q0 + qc;   // quads past the last run masked (all zero), so that every chunk
+                               // issues the same loads and the waits at its end stay exact
+      {
+        const int qn = q + PF < qlo ? qlo : (q + PF < nq ? q + PF : nq - 1);
+        const kbe_f4v* nx = hq + (int64_t)qn * 128 * C;
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) ring[(u + PF) % RING][i] = __builtin_nontemporal_load(nx + i * 64);
       }
+      const kbe_f4v* cur = ring[u];
       const int j0 = 64 * s + 4 * q;
       const int j = j0 + r;
       auto quad = [&](auto tag) {
@@ -1644,15 +1651,13 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
           G[2 * i] = valid ? make_float2(cur[i].x, cur[i].y) : make_float2(0.f, 0.f);
           if (2 * i + 1 < HS * NBB) G[2 * i + 1] = valid ? make_float2(cur[i].z, cur[i].w) : make_float2(0.f, 0.f);
         }
-        // A operand of this lane: Sigma^R(t_j)_{a l}, real-embedded and split
+        // A operand of this lane: Sigma^R(t_j)_{a l}, real-embedded and split (staged)
         float Af[NB][2];
-        const bool aval = arow && (MASKED ? j < m : true);
+        const float* af = ab + (qc * 64 + lane) * 2 * NB;
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
-          cplx x = aval ? sk[(2 * NBB + aa * NB + l) * d.Tp + j] : czero();
-          float pr = split_part(x.x, low), pi = split_part(x.y, low);
-          Af[l][0] = im_row ? pi : pr;
-          Af[l][1] = im_row ? pr : -pi;
+          Af[l][0] = af[2 * l];
+          Af[l][1] = af[2 * l + 1];
         }
 #pragma unroll
         for (int l = 0; l < NB; ++l)
@@ -1695,13 +1700,13 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
           if (n % (16 / VP) == 0) row[n / (16 / VP)] = x[0];
         }
       };
-      if (q >= 16 && j0 + 4 <= m)
+      if (q >= 16 && j0 + 4 <= m)   // (q >= nq implies j0 >= m: masked)
         quad(BoolTag<false>{});
       else
         quad(BoolTag<true>{});
-#pragma unroll
-      for (int i = 0; i < NCH; ++i) cur[i] = nxt[i];
     }
+    }
+    if (more) fill.store(afr + (buf ^ 1) * (CQ * 64 * 2 * NB), threadIdx.x, NTHR);
     // FP32 tiles of this chunk into the FP64 column sums
 #pragma unroll
     for (int hh = 0; hh < HS; ++hh)
@@ -1768,6 +1773,35 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
 // band copy; stored blocks j > t' from the ring of recent rows (row m: the current iterate) or
 // the column copies (j < qp); blocks above the diagonal as -G_{t' j}^dag from the column copies
 // (j < qp) or the band (t' - j < qp). Every node the corrections visit is one of these.
+// Component sc (nb^2 entries) of the block G(t_j, t') an end-point correction needs, from the
+// copies that hold it (as end_block, for one component).
+template <int NB>
+__device__ __forceinline__ void end_block1(const Dims& d, const cplx* __restrict__ row64, const cplx* __restrict__ colq,
+                                           const cplx* __restrict__ band, int k, int m, int j, int tp, int sc,
+                                           cplx* G) {
+  constexpr int NBB = NB * NB;
+  if (j == tp) {
+#pragma unroll
+    for (int e = 0; e < NBB; ++e) G[e] = band[band_idx(d, k, sc * NBB + e, tp, 0)];
+  } else if (j > tp) {
+    if (j > m - d.rring) {
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) G[e] = row64[row64_idx(d, j, k, sc * NBB + e, tp)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < NBB; ++e) G[e] = colq[colq_idx(d, k, sc * NBB + e, j, tp)];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        int cs = sc * NBB + b * NB + a;
+        cplx v = j < d.qp ? colq[colq_idx(d, k, cs, tp, j)] : band[band_idx(d, k, cs, tp, tp - j)];
+        G[a * NB + b] = cneg(cconj(v));
+      }
+  }
+}
 template <int NB>
 __device__ __forceinline__ void end_block(const Dims& d, const cplx* __restrict__ row64, const cplx* __restrict__ colq,
                                           const cplx* __restrict__ band, int k, int m, int j, int tp, cplx* G) {
@@ -1797,6 +1831,16 @@ __device__ __forceinline__ void end_block(const Dims& d, const cplx* __restrict_
   }
 }
 
+// Threads per (k, t') of the row kernel: one carrying both components G^<, G^> (nb <= 3), or at
+// nb = 4 two, lanes 2i and 2i + 1 carrying G^< and G^> (the state of both, 32 complex numbers in
+// each of several rows, would not fit one thread's registers).
+template <int NB>
+struct RowSplit {
+  static constexpr int SCN = NB == 4 ? 1 : 2;   // components per thread
+  static constexpr int TPT = 2 / SCN;           // threads per (k, t')
+  static constexpr int TPB = 256 / TPT;         // t' per block of 256 threads
+};
+
 template <int NB, int MODE, bool GREG>
 __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cplx* __restrict__ row64,
                                              const cplx* __restrict__ sig, const cplx* __restrict__ colsum,
@@ -1806,170 +1850,150 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              const cplx* __restrict__ rho_prev, cplx* __restrict__ rho_cur,
                                              const cplx* __restrict__ Dprev, const cplx* __restrict__ Dcur, int m,
                                              double dt, int commit, double* __restrict__ chg, QuadW Q) {
-  constexpr int NBB = NB * NB, C = 2 * NBB;
-  int k = blockIdx.y;
-  int tp = blockIdx.x * 256 + threadIdx.x;
-  if (tp > m) return;
+  constexpr int NBB = NB * NB;
+  constexpr int SCN = RowSplit<NB>::SCN, TPT = RowSplit<NB>::TPT;
+  const int k = blockIdx.y;
+  const int tp = blockIdx.x * RowSplit<NB>::TPB + threadIdx.x / TPT;
+  const int sc0 = SCN == 1 ? (threadIdx.x & 1) : 0;   // first component of this thread
+  if (tp > m) return;   // (both lanes of a pair leave together)
   if (MODE == KBE_ROW_EVAL && tp == m) return;
   const cplx* P = props + (int64_t)k * 3 * NBB;
+  double dmax = 0.0;
   if (tp < m) {
-    cplx In[C];
-    if (MODE != KBE_ROW_PREDICT) {
+    cplx rs[NBB];   // row partials of the history sums, shared by both components (gathered after
+                    // the first component's end-point terms, which need the registers more)
 #pragma unroll
-      for (int c = 0; c < C; ++c) In[c] = colsum[rowbuf_idx(d, k, c, tp)];
-      cplx rs[NBB];
-      mat_zero<NB>(rs);
-      int nslot = (tp >> 6) / d.spb + 1;
-      for (int q = 0; q < nslot; ++q) {
-        const cplx* rp = rowpart_slot(d, rowpart, k, q);
+    for (int ls = 0; ls < SCN; ++ls) {
+      const int sc = sc0 + ls;
+      cplx In[NBB];
+      if (MODE != KBE_ROW_PREDICT) {
+        // end-point terms of component sc, accumulated term by term
+        cplx E[NBB];
+        mat_zero<NB>(E);
+        if constexpr (!GREG) {
+          // trapezoid: half weights at j = 0 and j = m (first integral), j = 0 and j = t' (second)
+          {
+            cplx SRmm[NBB], Gm[NBB];
 #pragma unroll
-        for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], rp[(int64_t)e * d.Tp + tp]);
-      }
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        In[e] = cadd(In[e], rs[e]);
-        In[NBB + e] = cadd(In[NBB + e], rs[e]);
-      }
-      // end-point terms
-      cplx E[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) E[c] = czero();
-      if constexpr (!GREG) {
-        // trapezoid: half weights at j = 0 and j = m (first integral), j = 0 and j = t' (second)
-        cplx SRmm[NBB], SRm0[NBB], Gm[C], G0[C];
-#pragma unroll
-        for (int e = 0; e < NBB; ++e) {
-          SRmm[e] = sig[sig_idx(d, k, 2, e, m)];
-          SRm0[e] = sig[sig_idx(d, k, 2, e, 0)];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) Gm[c] = row64[row64_idx(d, m, k, c, tp)];
-        if (tp == 0) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) G0[c] = col0[colq_idx(d, k, c, 0, 0)];
-        } else {
-#pragma unroll
-          for (int sc = 0; sc < 2; ++sc)
+            for (int e = 0; e < NBB; ++e) {
+              SRmm[e] = cscal(sig[sig_idx(d, k, 2, e, m)], 0.5);
+              Gm[e] = row64[row64_idx(d, m, k, sc * NBB + e, tp)];
+            }
+            mm_acc<NB>(E, SRmm, Gm);
+          }
+          // G(t_0, t') of both components: G_00, or -G(t', t_0)^dag
+          auto g0 = [&](int c, int a, int b) {
+            return tp == 0 ? col0[colq_idx(d, k, c * NBB + a * NB + b, 0, 0)]
+                           : cneg(cconj(col0[colq_idx(d, k, c * NBB + b * NB + a, tp, 0)]));
+          };
+          {
+            cplx SRm0[NBB], G0[NBB];
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-              for (int b = 0; b < NB; ++b)
-                G0[sc * NBB + a * NB + b] = cneg(cconj(col0[colq_idx(d, k, sc * NBB + b * NB + a, tp, 0)]));
-        }
-#pragma unroll
-        for (int sc = 0; sc < 2; ++sc) {
-          cplx x1[NBB], x0[NBB];
-          mat_zero<NB>(x1);
-          mat_zero<NB>(x0);
-          mm_acc<NB>(x1, SRmm, Gm + sc * NBB);
-          mm_acc<NB>(x0, SRm0, G0 + sc * NBB);
-#pragma unroll
-          for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cscal(csub(x1[e], x0[e]), 0.5);
-        }
-        if (tp > 0) {
-          cplx GRtt[NBB], GR0t[NBB];
-#pragma unroll
-          for (int e = 0; e < NBB; ++e) {
-            GRtt[e] = csub(diag[band_idx(d, k, NBB + e, tp, 0)], diag[band_idx(d, k, e, tp, 0)]);
-            GR0t[e] = csub(G0[NBB + e], G0[e]);
+              for (int b = 0; b < NB; ++b) {
+                SRm0[a * NB + b] = cscal(sig[sig_idx(d, k, 2, a * NB + b, 0)], -0.5);
+                G0[a * NB + b] = g0(sc, a, b);
+              }
+            mm_acc<NB>(E, SRm0, G0);
           }
-#pragma unroll
-          for (int sc = 0; sc < 2; ++sc) {
-            cplx St[NBB], S0[NBB], y1[NBB], y0[NBB];
+          if (tp > 0) {
+            cplx St[NBB], GRtt[NBB];
 #pragma unroll
             for (int e = 0; e < NBB; ++e) {
-              St[e] = sig[sig_idx(d, k, sc, e, tp)];
-              S0[e] = sig[sig_idx(d, k, sc, e, 0)];
+              St[e] = cscal(sig[sig_idx(d, k, sc, e, tp)], -0.5);
+              GRtt[e] = csub(diag[band_idx(d, k, NBB + e, tp, 0)], diag[band_idx(d, k, e, tp, 0)]);
             }
-            mat_zero<NB>(y1);
-            mat_zero<NB>(y0);
-            mm_acc<NB>(y1, St, GRtt);
-            mm_acc<NB>(y0, S0, GR0t);
+            mm_acc<NB>(E, St, GRtt);
+            cplx S0[NBB], GR0t[NBB];
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(csub(y0[e], y1[e]), 0.5));
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                S0[a * NB + b] = cscal(sig[sig_idx(d, k, sc, a * NB + b, 0)], 0.5);
+                GR0t[a * NB + b] = csub(g0(1, a, b), g0(0, a, b));
+              }
+            mm_acc<NB>(E, S0, GR0t);
           }
-        }
-      } else {
-        // Gregory end corrections (d.qp nodes per end): against the bulk's unit weights,
-        //   E = sum_j (w^(m)_j - [j < m]) SR_mj G_jt'  +  sum_{j <= t'} (w^(t')_j - [j < t']) Sigma_mj GA_jt',
-        // nonzero on the nodes j < q' and j > N - q' of each interval (q' = min(qp, N + 1)).
-        const int qm = d.qp < m + 1 ? d.qp : m + 1;
-        for (int r = 0; r < 2; ++r) {
-          int j0 = r == 0 ? 0 : (qm > m - qm + 1 ? qm : m - qm + 1);
-          int j1 = r == 0 ? qm : m + 1;
-          for (int j = j0; j < j1; ++j) {
-            double w = quad_w(Q, j, m) - (j < m ? 1.0 : 0.0);
-            if (w == 0.0) continue;
-            cplx G[C], SR[NBB];
-            end_block<NB>(d, row64, col0, diag, k, m, j, tp, G);
-#pragma unroll
-            for (int e = 0; e < NBB; ++e) SR[e] = sig[sig_idx(d, k, 2, e, j)];
-#pragma unroll
-            for (int sc = 0; sc < 2; ++sc) {
-              cplx x[NBB];
-              mat_zero<NB>(x);
-              mm_acc<NB>(x, SR, G + sc * NBB);
-#pragma unroll
-              for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(x[e], w));
-            }
-          }
-        }
-        if (tp > 0) {
-          const int qt = d.qp < tp + 1 ? d.qp : tp + 1;
+        } else {
+          // Gregory end corrections (d.qp nodes per end): against the bulk's unit weights,
+          //   E = sum_j (w^(m)_j - [j < m]) SR_mj G_jt'  +  sum_{j <= t'} (w^(t')_j - [j < t']) Sigma_mj GA_jt',
+          // nonzero on the nodes j < q' and j > N - q' of each interval (q' = min(qp, N + 1)).
+          const int qm = d.qp < m + 1 ? d.qp : m + 1;
           for (int r = 0; r < 2; ++r) {
-            int j0 = r == 0 ? 0 : (qt > tp - qt + 1 ? qt : tp - qt + 1);
-            int j1 = r == 0 ? qt : tp + 1;
+            int j0 = r == 0 ? 0 : (qm > m - qm + 1 ? qm : m - qm + 1);
+            int j1 = r == 0 ? qm : m + 1;
             for (int j = j0; j < j1; ++j) {
-              double w = quad_w(Q, j, tp) - (j < tp ? 1.0 : 0.0);
+              double w = quad_w(Q, j, m) - (j < m ? 1.0 : 0.0);
               if (w == 0.0) continue;
-              cplx G[C], GA[NBB];
-              end_block<NB>(d, row64, col0, diag, k, m, j, tp, G);
+              cplx G[NBB], SR[NBB];
+              end_block1<NB>(d, row64, col0, diag, k, m, j, tp, sc, G);
 #pragma unroll
-              for (int e = 0; e < NBB; ++e) GA[e] = csub(G[e], G[NBB + e]);  // -(G^> - G^<)
+              for (int e = 0; e < NBB; ++e) SR[e] = cscal(sig[sig_idx(d, k, 2, e, j)], w);
+              mm_acc<NB>(E, SR, G);
+            }
+          }
+          if (tp > 0) {
+            const int qt = d.qp < tp + 1 ? d.qp : tp + 1;
+            for (int r = 0; r < 2; ++r) {
+              int j0 = r == 0 ? 0 : (qt > tp - qt + 1 ? qt : tp - qt + 1);
+              int j1 = r == 0 ? qt : tp + 1;
+              for (int j = j0; j < j1; ++j) {
+                double w = quad_w(Q, j, tp) - (j < tp ? 1.0 : 0.0);
+                if (w == 0.0) continue;
+                cplx GA[NBB], Gg[NBB], S[NBB];
+                end_block1<NB>(d, row64, col0, diag, k, m, j, tp, 0, GA);
+                end_block1<NB>(d, row64, col0, diag, k, m, j, tp, 1, Gg);
 #pragma unroll
-              for (int sc = 0; sc < 2; ++sc) {
-                cplx S[NBB], x[NBB];
-#pragma unroll
-                for (int e = 0; e < NBB; ++e) S[e] = sig[sig_idx(d, k, sc, e, j)];
-                mat_zero<NB>(x);
-                mm_acc<NB>(x, S, GA);
-#pragma unroll
-                for (int e = 0; e < NBB; ++e) E[sc * NBB + e] = cadd(E[sc * NBB + e], cscal(x[e], w));
+                for (int e = 0; e < NBB; ++e) {
+                  GA[e] = csub(GA[e], Gg[e]);  // -(G^> - G^<)
+                  S[e] = cscal(sig[sig_idx(d, k, sc, e, j)], w);
+                }
+                mm_acc<NB>(E, S, GA);
               }
             }
           }
         }
-      }
+        if (ls == 0) {
+          mat_zero<NB>(rs);
+          int nslot = (tp >> 6) / d.spb + 1;
+          for (int q = 0; q < nslot; ++q) {
+            const cplx* rp = rowpart_slot(d, rowpart, k, q);
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        In[c] = cscal(cadd(In[c], E[c]), dt);
-        Icur[rowbuf_idx(d, k, c, tp)] = In[c];
-      }
-    }
-    if (MODE != KBE_ROW_EVAL) {
-      cplx Ib[C], Go[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        cplx ip = Iprev[rowbuf_idx(d, k, c, tp)];
-        Ib[c] = (MODE == KBE_ROW_PREDICT) ? ip : cscal(cadd(ip, In[c]), 0.5);
-        Go[c] = row64[row64_idx(d, m - 1, k, c, tp)];
-      }
-      cplx V[NBB], Phi[NBB];
-#pragma unroll
-      for (int e = 0; e < NBB; ++e) {
-        V[e] = P[e];
-        Phi[e] = P[2 * NBB + e];
-      }
-      double dmax = 0.0;
-#pragma unroll
-      for (int sc = 0; sc < 2; ++sc) {
-        cplx g[NBB];
-        mat_zero<NB>(g);
-        mm_acc<NB>(g, V, Go + sc * NBB);
-        mm_acc<NB>(g, Phi, Ib + sc * NBB);
+            for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], rp[(int64_t)e * d.Tp + tp]);
+          }
+        }
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
-          int c = sc * NBB + e;
+          In[e] = cscal(cadd(cadd(colsum[rowbuf_idx(d, k, sc * NBB + e, tp)], rs[e]), E[e]), dt);
+          Icur[rowbuf_idx(d, k, sc * NBB + e, tp)] = In[e];
+        }
+      }
+      if (MODE != KBE_ROW_EVAL) {
+        // G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t') for component sc
+        cplx Ib[NBB], Go[NBB], g[NBB];
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) {
+          cplx ip = Iprev[rowbuf_idx(d, k, sc * NBB + e, tp)];
+          Ib[e] = (MODE == KBE_ROW_PREDICT) ? ip : cscal(cadd(ip, In[e]), 0.5);
+          Go[e] = row64[row64_idx(d, m - 1, k, sc * NBB + e, tp)];
+        }
+        mat_zero<NB>(g);
+        {
+          cplx V[NBB];
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) V[e] = P[e];
+          mm_acc<NB>(g, V, Go);
+        }
+        {
+          cplx Phi[NBB];
+#pragma unroll
+          for (int e = 0; e < NBB; ++e) Phi[e] = P[2 * NBB + e];
+          mm_acc<NB>(g, Phi, Ib);
+        }
+#pragma unroll
+        for (int e = 0; e < NBB; ++e) {
+          const int c = sc * NBB + e;
           if (MODE == KBE_ROW_CORRECT && chg) {  // change against the iterate this pass started from
             cplx dg = csub(g[e], row64[row64_idx(d, m, k, c, tp)]);
             dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
@@ -1982,12 +2006,10 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
           }
         }
       }
-      if (MODE == KBE_ROW_CORRECT && chg) chg[(int64_t)k * d.Tp + tp] = dmax;
     }
-  } else {
-    // tp == m, PREDICT or CORRECT: density matrix and equal-time block
+  } else if (sc0 == 0) {
+    // tp == m, PREDICT or CORRECT: density matrix and equal-time block (one thread per k)
     cplx V[NBB], Vh[NBB], r0[NBB], Db[NBB], t1[NBB], rho[NBB], t2[NBB];
-    double dmax = 0.0;
 #pragma unroll
     for (int e = 0; e < NBB; ++e) {
       V[e] = P[e];
@@ -2011,25 +2033,28 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         int e = a * NB + b;
         cplx rv = csub(rho[e], cscal(t2[e], dt));
         rho_cur[(int64_t)k * NBB + e] = rv;
-        cplx g[2];
-        g[0] = cmuli(rv);
-        g[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
+        cplx gg[2];
+        gg[0] = cmuli(rv);
+        gg[1] = cneg(cmuli(csub(cmk(a == b ? 1.0 : 0.0, 0.0), rv)));
 #pragma unroll
         for (int sc = 0; sc < 2; ++sc) {
           int c = sc * NBB + e;
           if (MODE == KBE_ROW_CORRECT && chg) {
-            cplx dg = csub(g[sc], row64[row64_idx(d, m, k, c, m)]);
+            cplx dg = csub(gg[sc], row64[row64_idx(d, m, k, c, m)]);
             dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
           }
-          row64[row64_idx(d, m, k, c, m)] = g[sc];
+          row64[row64_idx(d, m, k, c, m)] = gg[sc];
           if (commit) {
-            commit_store(d, hist, k, c, m, m, g[sc]);
-            diag[band_idx(d, k, c, m, 0)] = g[sc];
-            if (m < d.qp) col0[colq_idx(d, k, c, m, m)] = g[sc];
+            commit_store(d, hist, k, c, m, m, gg[sc]);
+            diag[band_idx(d, k, c, m, 0)] = gg[sc];
+            if (m < d.qp) col0[colq_idx(d, k, c, m, m)] = gg[sc];
           }
         }
       }
-    if (MODE == KBE_ROW_CORRECT && chg) chg[(int64_t)k * d.Tp + m] = dmax;
+  }
+  if (MODE == KBE_ROW_CORRECT && chg) {
+    if constexpr (TPT == 2) dmax = fmax(dmax, __shfl_xor(dmax, 1));   // the pair's two components
+    if (sc0 == 0) chg[(int64_t)k * d.Tp + tp] = dmax;
   }
 }
 
@@ -2338,7 +2363,7 @@ struct Launch {
     return hipGetLastError();
   }
   static hipError_t row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
-    dim3 grid((m + 1 + 255) / 256, d.nk);
+    dim3 grid((m + 1 + RowSplit<NB>::TPB - 1) / RowSplit<NB>::TPB, d.nk);
 #define KBE_ROW_ARGS                                                                                      \
   d, a.hist, a.row64, (const cplx*)a.sig, (const cplx*)a.colsum, (const cplx*)a.rowpart, a.col0, a.diag, \
       (const cplx*)a.I_prev, a.I_cur, (const cplx*)a.props, (const cplx*)a.rho_prev, a.rho_cur,           \

@@ -164,12 +164,10 @@ def _compare_run(K, cfg, nsteps):
         i = O.OBS[name]
         x, r = obs[:, i], ref["obs"][:, i]
         if np.abs(r).max() < 1e-12:
-            # zero by symmetry (e.g. J_y for a pulse along x, unused orbitals): the cancelling
-            # terms are O(1) per k-point, so what remains is rounding of O(1) numbers summed over
-            # the grid and carried through the run; the bound is a hundredth of the FP64 target
-            # at the scale of those terms
+            # zero by symmetry (e.g. J_y for a pulse along x, unused orbitals): both sides must
+            # stay at the rounding level of the O(1) terms that cancel
             vanish[name] = float(np.abs(x).max())
-            assert vanish[name] < 1e-12, name
+            assert vanish[name] < 1e-14, name
             continue
         worst[name] = relerr(x, r)
     assert np.abs(obs[:, 0] - ref["obs"][:, 0]).max() < 1e-12

@@ -32,24 +32,29 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 # HBM traffic of the FP64 history-sum kernel per launch: rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
 # scaled by what the same counters read for a plain 1 GiB device copy (x2.000 and x1.000), averaged
-# over the launches of one timed window, keyed by (workload, nt, timed steps K); summary and
-# commands in profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for the kernel source it was measured
-# on (SHA-1 of the code of kbe_kernels.hip + kbe_device.hpp, comments removed); reported as null
-# once that code changes, or for a window that was not measured.
-MEASURED_TRAFFIC = {"bytes_per_launch": {("c2", 1000, 1000): 1.2684e10},
-                    "source_sha1": "217d5f8b3496bdd2b4b7f7bb7ba9f39116b03ba6"}
+# over the launches of the timed window (the last K steps of the trajectory), keyed by (workload,
+# nt, timed steps K); summary and commands in profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for
+# the code it was measured on (SHA-1 of the k_hist_pair template and kbe_device.hpp, comments
+# removed); reported as null once that code changes, or for a window that was not measured.
+MEASURED_TRAFFIC = {"bytes_per_launch": {("c2", 1000, 20): 3.70663e10, ("c2", 1000, 1000): 1.26848e10},
+                    "source_sha1": "c439e14bb0c4c89c204c2caecf22db87bb9bf55d"}
 
 
 def _kernel_source_sha1():
-    """SHA-1 of the kernel sources with comments and blank lines removed (code changes only)."""
+    """SHA-1 of the FP64 history-sum kernel's code (the k_hist_pair template) and of the shared
+    device header, comments and blank lines removed: code changes of that kernel only."""
     import hashlib
     import re
     d = os.path.join(ROOT, "paper_2505_19467_amd", "csrc")
-    code = []
-    for f in ("kbe_kernels.hip", "kbe_device.hpp"):
-        text = re.sub(r"/\*.*?\*/", "", open(os.path.join(d, f)).read(), flags=re.S)
-        code += [ln.split("//")[0].rstrip() for ln in text.splitlines()]
-    return hashlib.sha1("\n".join(ln for ln in code if ln).encode()).hexdigest()
+
+    def code(text):
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        return [ln.split("//")[0].rstrip() for ln in text.splitlines()]
+    k = open(os.path.join(d, "kbe_kernels.hip")).read()
+    a = k.index("__global__ __launch_bounds__(256) void k_hist_pair(")
+    b = k.index("// ------------------------------------------------------------------", a)
+    lines = code(k[a:b]) + code(open(os.path.join(d, "kbe_device.hpp")).read())
+    return hashlib.sha1("\n".join(ln for ln in lines if ln).encode()).hexdigest()
 
 
 def _rel_devs(obs, ref, names):

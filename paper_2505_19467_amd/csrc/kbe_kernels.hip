@@ -1956,8 +1956,23 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         }
         if (ls == 0) {
           mat_zero<NB>(rs);
-          int nslot = (tp >> 6) / d.spb + 1;
-          for (int q = 0; q < nslot; ++q) {
+          const int nslot = (tp >> 6) / d.spb + 1;
+          // slots in groups of 4: the loads of a group are issued together
+          int q = 0;
+          for (; q + 4 <= nslot; q += 4) {
+            cplx v[4][NBB];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const cplx* rp = rowpart_slot(d, rowpart, k, q + u);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) v[u][e] = rp[(int64_t)e * d.Tp + tp];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], v[u][e]);
+          }
+          for (; q < nslot; ++q) {
             const cplx* rp = rowpart_slot(d, rowpart, k, q);
 #pragma unroll
             for (int e = 0; e < NBB; ++e) rs[e] = cadd(rs[e], rp[(int64_t)e * d.Tp + tp]);

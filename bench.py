@@ -117,6 +117,75 @@ def cpu_baseline(cfg, sample_steps: int, same_steps: int):
     return dt, threads, dt_same, dt1
 
 
+def cpu_extended(what: str):
+    """Longer CPU-oracle baselines beside the GPU path on the same workload, one per call
+    (each is minutes of oracle work on the host's cores, so none runs by default):
+
+    * ``c1``: the 16-point chain, nb = 2, all 200 steps: oracle with all threads and with one;
+    * ``c4``: the 12x12 gradient workload, all 400 steps: oracle forward run; an FD gradient of
+      its three parameters by central differences costs six such runs; GPU forward run and
+      reverse sweep;
+    * ``c4_tlm``: the oracle's tangent-linear run of the same 400 steps (the CPU way to the
+      gradient that the reverse sweep computes);
+    * ``c5_400``: the 16x16, nb = 4 workload truncated to n_t = 400, oracle and GPU.
+
+    The oracle prints a progress line every 5 % of the steps."""
+    import torch
+    from oracle import oracle as O
+    from paper_2505_19467_amd import inputs, kbe
+    O.build()
+    threads = O.max_threads()
+    if what == "c1":
+        cfg = inputs.c1()
+    elif what in ("c4", "c4_tlm"):
+        cfg = inputs.c4()
+    elif what == "c5_400":
+        cfg = inputs.c5().replace(nt=400)
+    else:
+        raise SystemExit(f"bench.py: unknown --cpu-extended workload {what!r} (c1, c4, c4_tlm, c5_400)")
+    n = cfg.nt
+    O.set_progress(max(1, n // 20))
+
+    def oracle_time(fn, nthreads=None):
+        if nthreads:
+            O.set_threads(nthreads)
+        t0 = time.perf_counter()
+        fn()
+        el = time.perf_counter() - t0
+        O.set_threads(threads)
+        print(f"[bench] oracle {what}: {el:.1f} s with {nthreads or threads} threads", file=sys.stderr, flush=True)
+        return el
+
+    out = {"workload": cfg.name, "steps": n, "cpu_model": cpu_model(), "threads": threads, "kind": "oracle"}
+    if what == "c4_tlm":
+        out["tlm_s"] = oracle_time(lambda: O.tlm_run(cfg, n))
+        print(json.dumps(out), flush=True)
+        return
+    out["oracle_s"] = oracle_time(lambda: O.run(cfg, n))
+    if what == "c1":
+        out["oracle_one_thread_s"] = oracle_time(lambda: O.run(cfg, n), 1)
+    if what == "c4":
+        out["fd_gradient_s_derived"] = 6 * out["oracle_s"]
+    S = kbe.System(cfg)
+    S.step(min(5, n))
+    S.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(n)
+    torch.cuda.synchronize()
+    out["gpu_s"] = time.perf_counter() - t0
+    if what == "c4":
+        t0 = time.perf_counter()
+        S.adjoint_gradient("n_band1")
+        torch.cuda.synchronize()
+        out["gpu_reverse_s"] = time.perf_counter() - t0
+    S.close()
+    out["oracle_steps_per_s"] = n / out["oracle_s"]
+    out["gpu_steps_per_s"] = n / out["gpu_s"]
+    print(f"[bench] {what}: oracle {out['oracle_s']:.1f} s, GPU {out['gpu_s']:.3f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_leg(torch, inputs, kbe):
     """Gradient workload: the 12x12-k, nb = 2, 400-step system; forward propagation (its
     history is the reverse sweep's checkpoint store), then the reverse sweep for
@@ -242,7 +311,13 @@ def main():
                     help="do not record HIP events around the history-sum launches (for counter-collection runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run one device-to-device copy of GIB GiB (to scale HBM byte counters) and exit")
+    ap.add_argument("--cpu-extended", default=None, metavar="WORKLOAD",
+                    help="only time the CPU oracle on a longer workload beside the GPU (c1, c4, c4_tlm, "
+                         "c5_400) and exit")
     args = ap.parse_args()
+    if args.cpu_extended:
+        cpu_extended(args.cpu_extended)
+        return
     if args.copy_calibration > 0:
         import torch
         n = int(args.copy_calibration * 2 ** 30) // 8

@@ -65,6 +65,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -1166,6 +1167,15 @@ void from_doubles(const double* src, size_t n, C* dst) {
 
 }  // namespace
 
+static int g_progress = 0;
+
+static void report_step(int m, int nsteps) {
+  if (g_progress > 0 && (m % g_progress == 0 || m == nsteps)) {
+    std::fprintf(stderr, "[oracle] step %d of %d\n", m, nsteps);
+    std::fflush(stderr);
+  }
+}
+
 extern "C" {
 
 int oracle_nobs() { return NOBS; }
@@ -1177,6 +1187,9 @@ int oracle_max_threads() { return omp_get_max_threads(); }
 void oracle_set_threads(int32_t n) {
   if (n > 0) omp_set_num_threads(n);
 }
+// every > 0: the run entry points print "[oracle] step m of n" to stderr after every `every`
+// steps (long timing runs); 0 (the default) prints nothing
+void oracle_set_progress(int32_t every) { g_progress = every > 0 ? every : 0; }
 
 int oracle_quad_weights(int32_t quad_points, int32_t N, double* out) {
   if (quad_points < 1 || quad_points > QUAD_MAX || N < 0 || !out) return -1;
@@ -1205,6 +1218,7 @@ int oracle_run(const Params* p, const double* hop, int32_t nsteps, double* obs, 
     step(st, m);
     if (obs) observables(st, m, obs + (size_t)m * NOBS);
     dipole_kick(st, m);
+    report_step(m, nsteps);
   }
   if (final_row) to_doubles(st.rows[nsteps].data(), st.rows[nsteps].size(), final_row);
   if (hist) {
@@ -1282,6 +1296,7 @@ int oracle_tlm_run(const Params* p, const double* hop, int32_t nsteps, double* o
     step(st, m);
     emit(m);
     dipole_kick(st, m);
+    report_step(m, nsteps);
   }
   return 0;
 }

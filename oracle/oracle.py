@@ -73,6 +73,7 @@ def lib():
         _lib.oracle_full_square_check.argtypes = [P, dp, ctypes.c_int32, dp]
         _lib.oracle_max_threads.restype = ctypes.c_int
         _lib.oracle_set_threads.argtypes = [ctypes.c_int32]
+        _lib.oracle_set_progress.argtypes = [ctypes.c_int32]
     return _lib
 
 
@@ -242,3 +243,9 @@ def max_threads() -> int:
 def set_threads(n: int) -> None:
     """Set the oracle's OpenMP thread count (for a one-core timing)."""
     lib().oracle_set_threads(int(n))
+
+
+def set_progress(every: int) -> None:
+    """every > 0: the runs print "[oracle] step m of n" to stderr after every ``every`` steps
+    (long timing runs); 0 turns it off."""
+    lib().oracle_set_progress(int(every))

@@ -299,9 +299,11 @@ struct kbe_ctx {
       if (hipEventRecord(ev[ev_used + 1], st) != hipSuccess) return fail(KBE_ERR_HIP, "hipEventRecord failed");
       ev_used += 2;
       ev_m.push_back(m);
-      return KBE_OK;
+    } else {
+      int rc = check(kbe::launch_bulk(L.d, a, m, st), "history-sum launch");
+      if (rc) return rc;
     }
-    return check(kbe::launch_bulk(L.d, a, m, st), "history-sum launch");
+    return check(kbe::launch_rowpart_fold(L.d, a, m, st), "row-partial fold launch");
   }
   // Sigma row, equal-time collision integral, history sums of row m.
   int collision_parts(LaunchArgs& a, int m) {
@@ -489,6 +491,7 @@ struct kbe_ctx {
     if (!rc) rc = check(kbe::launch_sigma(d, e, m - 1, st), "self-energy launch");
     if (!rc) rc = check(kbe::launch_diag_I(d, e, m - 1, st), "equal-time collision launch");
     if (!rc) rc = check(kbe::launch_bulk(d, e, m - 1, st), "history-sum launch");
+    if (!rc) rc = check(kbe::launch_rowpart_fold(d, e, m - 1, st), "row-partial fold launch");
     if (!rc) rc = check(kbe::launch_row(d, e, m - 1, KBE_ROW_EVAL, st), "collision-row launch");
     // recompute the predictor (row m of the working copy only)
     LaunchArgs p = a;
@@ -511,6 +514,7 @@ struct kbe_ctx {
     if (!rc) rc = check(kbe::launch_sigma(d, c, m, st), "self-energy launch");
     if (!rc) rc = check(kbe::launch_diag_I(d, c, m, st), "equal-time collision launch");
     if (!rc) rc = check(kbe::launch_bulk(d, c, m, st), "history-sum launch");
+    if (!rc) rc = check(kbe::launch_rowpart_fold(d, c, m, st), "row-partial fold launch");
     if (!rc) rc = check(kbe::launch_row(d, c, m, KBE_ROW_EVAL, st), "collision-row launch");
     if (!rc) rc = check(kbe::launch_hf(d, c, 0.5, st), "mean-field launch");
     if (!rc) rc = check(kbe::launch_props(d, c, st), "propagator launch");

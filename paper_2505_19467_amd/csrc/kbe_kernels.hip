@@ -1839,7 +1839,41 @@ struct RowSplit {
   static constexpr int SCN = NB == 4 ? 1 : 2;   // components per thread
   static constexpr int TPT = 2 / SCN;           // threads per (k, t')
   static constexpr int TPB = 256 / TPT;         // t' per block of 256 threads
+  // nb = 4: the strips' row partials are summed into slot 0 by k_rowpart_fold before the row
+  // kernel runs (at one wave per SIMD, the row kernel's serial gather of up to n_t / 64 slots
+  // would be latency-bound)
+  static constexpr bool FOLD = NB == 4;
 };
+
+// Row term of the history sums at nb = 4: the per-strip partials of row t' (slots 0 .. t' / 64)
+// summed in slot order into slot 0, one thread per (k, entry, t'). Each slot-0 element is read
+// and written by its own thread only, so the fold is in place; it runs once after each history
+// pass, and the row kernels then read slot 0 alone. The sum has the order of the row kernels'
+// own gather, so the result is the same.
+template <int NB>
+__global__ __launch_bounds__(256) void k_rowpart_fold(Dims d, cplx* __restrict__ rowpart, int m) {
+  const int nblk = (m + 255) / 256;           // blocks per (k, entry)
+  const int ke = blockIdx.x / nblk;           // k * nb^2 + entry
+  const int tp = (blockIdx.x - ke * nblk) * 256 + threadIdx.x;
+  const int k = ke / (NB * NB), e = ke - k * (NB * NB);
+  if (tp >= m) return;
+  const int nslot = (tp >> 6) / d.spb + 1;
+  if (nslot == 1) return;
+  const int64_t off = (int64_t)e * d.Tp + tp;
+  cplx* p0 = rowpart + (int64_t)k * d.Smax * d.nbb * d.Tp + off;   // slot 0 of (k, e, t')
+  const int64_t step = (int64_t)d.nbb * d.Tp;                         // one slot further
+  cplx s = p0[0];
+  int q = 1;
+  for (; q + 4 <= nslot; q += 4) {
+    cplx v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = p0[(q + u) * step];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s = cadd(s, v[u]);
+  }
+  for (; q < nslot; ++q) s = cadd(s, p0[q * step]);
+  p0[0] = s;
+}
 
 template <int NB, int MODE, bool GREG>
 __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cplx* __restrict__ row64,
@@ -1956,7 +1990,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         }
         if (ls == 0) {
           mat_zero<NB>(rs);
-          const int nslot = (tp >> 6) / d.spb + 1;
+          const int nslot = RowSplit<NB>::FOLD ? 1 : (tp >> 6) / d.spb + 1;
           // slots in groups of 4: the loads of a group are issued together
           int q = 0;
           for (; q + 4 <= nslot; q += 4) {
@@ -2377,6 +2411,15 @@ struct Launch {
     }
     return hipGetLastError();
   }
+  static hipError_t fold(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+    if constexpr (RowSplit<NB>::FOLD) {
+      if (m < 65) return hipSuccess;   // one strip: nothing to fold
+      hipLaunchKernelGGL(k_rowpart_fold<NB>, dim3((m + 255) / 256 * NB * NB * d.nk), dim3(256), 0, st, d,
+                         a.rowpart, m);
+      return hipGetLastError();
+    }
+    return hipSuccess;
+  }
   static hipError_t row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
     dim3 grid((m + 1 + RowSplit<NB>::TPB - 1) / RowSplit<NB>::TPB, d.nk);
 #define KBE_ROW_ARGS                                                                                      \
@@ -2459,6 +2502,9 @@ hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t 
 }
 hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
   KBE_DISPATCH(d.nb, bulk(d, a, m, st));
+}
+hipError_t launch_rowpart_fold(const Dims& d, const LaunchArgs& a, int m, hipStream_t st) {
+  KBE_DISPATCH(d.nb, fold(d, a, m, st));
 }
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st) {
   KBE_DISPATCH(d.nb, row(d, a, m, mode, st));

@@ -62,6 +62,9 @@ hipError_t launch_kick(const Dims& d, const LaunchArgs& a, int m, double kc, dou
                        hipStream_t st);
 hipError_t launch_diag_I(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_bulk(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
+// after each history pass at nb = 4 (a no-op otherwise): sums the strips' row partials into slot 0,
+// which the row kernels then read alone; not idempotent, so exactly once per history pass
+hipError_t launch_rowpart_fold(const Dims& d, const LaunchArgs& a, int m, hipStream_t st);
 hipError_t launch_row(const Dims& d, const LaunchArgs& a, int m, int mode, hipStream_t st);
 // out[0] = max over k and t' <= m of chg[k][t'] (one block, deterministic)
 hipError_t launch_change_max(const Dims& d, const double* chg, int m, double* out, hipStream_t st);

@@ -692,9 +692,10 @@ __device__ __forceinline__ void flush_rows_fold(const cplx* st0, const cplx* st1
 // block is read from HBM once. The row terms of the two strips are added before the 64-lane
 // reduce-scatter (at nb = 2 the four components of the row term share one reduce-scatter as
 // four groups), so one row partial covers 128 columns: the writes that interleave with the
-// read stream are half of what one strip per block would produce, and they leave as whole
-// 256-byte runs (a wavefront's 16 rows staged in LDS, streaming stores). Both measures keep
-// the read stream from stalling on scattered write-backs. Row partials go to slot sp; the 4
+// read stream are half of what one strip per block would produce, and they leave in long runs
+// (the block's rows of four 64-row chunks staged in LDS, then stored by all its threads as
+// contiguous 4 KB runs per component, streaming stores). Both measures keep the read stream
+// from stalling on scattered write-backs. Row partials go to slot sp; the 4
 // wavefronts' column sums are combined in LDS. Deterministic: no atomics.
 template <int NB>
 __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restrict__ hist,
@@ -703,7 +704,9 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int R = NB == 1 ? 4 : 1;
   __shared__ cplx red[3][C][64];
-  __shared__ cplx stg[4][NBB * 16];
+  // row partials of the last ROWS_ST rows (4 chunks of 64), stored by the whole block at once
+  constexpr int ROWS_ST = 256;
+  __shared__ cplx stg[NBB][ROWS_ST];
   __shared__ cplx sS[2][2][NBB][64];  // [strip of the pair][Sigma^<, Sigma^>][e][lane]
   const int sp = blockIdx.x / d.nk;
   const int k = blockIdx.x - sp * d.nk;
@@ -733,9 +736,10 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[h][c] = czero();
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
-  cplx* st = stg[wv];
   for (int cb = 128 * sp; cb < m; cb += 64) {
     const int rb = cb + 16 * wv;
+    const int cslot = ((cb - 128 * sp) >> 6) % (ROWS_ST / 64);   // chunk's place in the staging
+    cplx* st = &stg[0][64 * cslot + 16 * wv];                      // st[e * ROWS_ST + row]
     for (int i = 0; i < 16 / R; ++i) {
       const int jb = rb + R * i;
       if (jb >= m) break;
@@ -796,13 +800,13 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
           reduce_rows<4>(xg);
           int e = reduced_row<4>(lane);
-          if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
+          if (e >= 0) st[e * ROWS_ST + i] = cmk(xg[0][0], xg[0][1]);
         } else {
           reduce_rows<R>(rt);
           int rr = reduced_row<R>(lane);
           if (rr >= 0) {
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) st[e * 16 + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
           }
         }
       };
@@ -811,7 +815,18 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
       else
         iteration(BoolTag<true>{});
     }
-    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+    // every fourth chunk (and the last): the staged rows of all four wavefronts leave as one
+    // contiguous run of up to 256 rows per component (4 KB), streaming stores
+    if (cslot == ROWS_ST / 64 - 1 || cb + 64 >= m) {
+      __syncthreads();
+      const int base = cb - 64 * cslot;
+      const int nrows = (cb + 64 < m ? cb + 64 : m) - base;
+      for (int q = threadIdx.x; q < NBB * nrows; q += 256) {
+        const int e = q / nrows, row = q - e * nrows;
+        store_stream(rp + (int64_t)e * d.Tp + base + row, stg[e][row]);
+      }
+      __syncthreads();
+    }
   }
   // combine the 4 wavefronts' column sums, strip by strip
 #pragma unroll
@@ -850,7 +865,8 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int R = NB == 1 ? 4 : 2;
   __shared__ cplx red[3][C][64];
-  __shared__ cplx stg[4][NBB * 16];
+  constexpr int ROWS_ST = 256;   // row partials staged over four 64-row chunks, as in k_hist_pair
+  __shared__ cplx stg[NBB][ROWS_ST];
   __shared__ cplx32 sS[2][2][NBB][64];
   const int sp = blockIdx.x / d.nk;
   const int k = blockIdx.x - sp * d.nk;
@@ -883,9 +899,10 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
       acc32[h][c] = make_float2(0.f, 0.f);
     }
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
-  cplx* st = stg[wv];
   for (int cb = 128 * sp; cb < m; cb += 64) {
     const int rb = cb + 16 * wv;
+    const int cslot = ((cb - 128 * sp) >> 6) % (ROWS_ST / 64);
+    cplx* st = &stg[0][64 * cslot + 16 * wv];   // st[e * ROWS_ST + row]
     for (int i = 0; i < 16 / R; ++i) {
       const int jb = rb + R * i;
       if (jb >= m) break;
@@ -965,7 +982,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
             int r = g >> 1, p2 = g & 1;
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-              st[(2 * p2 + c) * 16 + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
+              st[(2 * p2 + c) * ROWS_ST + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
           }
         } else {
           reduce_rows32<R>(rt);
@@ -973,7 +990,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
           if (rr >= 0) {
 #pragma unroll
             for (int e = 0; e < NBB; ++e)
-              st[e * 16 + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+              st[e * ROWS_ST + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
           }
         }
       };
@@ -991,7 +1008,16 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
         acc[h][c].y += (double)acc32[h][c].y;
         acc32[h][c] = make_float2(0.f, 0.f);
       }
-    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+    if (cslot == ROWS_ST / 64 - 1 || cb + 64 >= m) {
+      __syncthreads();
+      const int base = cb - 64 * cslot;
+      const int nrows = (cb + 64 < m ? cb + 64 : m) - base;
+      for (int q = threadIdx.x; q < NBB * nrows; q += 256) {
+        const int e = q / nrows, row = q - e * nrows;
+        store_stream(rp + (int64_t)e * d.Tp + base + row, stg[e][row]);
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1459,7 +1485,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 //   pair; a DPP reduce-scatter over the 16 lanes of each row (four rows at once) leaves one
 //   component per lane; the wavefronts' partials of a chunk are staged in LDS (two buffers) and,
 //   after one block barrier per chunk, added in a fixed order in FP64 and stored to the strip's
-//   row-partial slot with streaming stores.
+//   row-partial slot with streaming stores (at nb <= 2 staged over four chunks and stored as
+//   4 KB runs).
 // Quads past the strip's triangle (its first 16) and below m run without bounds selects. The
 // next quad's loads are issued before the current quad is processed, and no load sits behind a
 // branch, so the waits for one quad's data are exact.
@@ -1505,6 +1532,11 @@ struct MfmaShape {
   static constexpr int STAGE = 2 * WAVES * CQ * 4 * VP * 4;  // bytes
   static constexpr int AFR = 2 * CQ * 64 * 2 * NB * 4;       // bytes: A operands of two chunks
   static constexpr int FIN = WAVES * HS * NB * 256 * 8;     // bytes
+  // row partials leave in runs of ROWS rows per component: at nb <= 2 the FP64 sums of four
+  // 64-row chunks are staged (runs of 4 KB; fewer, longer write bursts in the read stream), at
+  // nb >= 3 each chunk's rows are stored directly (a 64-row staging costs more than it saves there)
+  static constexpr int ROWS = NB <= 2 ? 256 : 4 * CQ;
+  static constexpr int RSTG = NB <= 2 ? NBB * ROWS * 16 : 0;   // bytes
   static constexpr int LDS = (STAGE + AFR) > FIN ? (STAGE + AFR) : FIN;
 };
 
@@ -1559,6 +1591,8 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
   constexpr int NBB = Sh::NBB, C = Sh::C, HS = Sh::HS, NCH = Sh::NCH, VP = Sh::VP, CQ = Sh::CQ, WAVES = Sh::WAVES;
   static_assert(HS == 2 || NBB % 2 == 0, "halves must not share a 16-byte load");
   __shared__ __align__(16) unsigned char smem[Sh::LDS];
+  constexpr int CPF = Sh::ROWS / (4 * CQ);   // chunks per row-partial store
+  __shared__ cplx rstg[Sh::RSTG > 0 ? Sh::RSTG / 16 : 1];
   float* stg = reinterpret_cast<float*>(smem);  // [2][WAVES][CQ][4][VP]
   float* afr = reinterpret_cast<float*>(smem + Sh::STAGE);  // [2][CQ][64][2 nb]
   constexpr int NTHR = WAVES * 64, NE = (CQ * 64 + NTHR - 1) / NTHR;
@@ -1622,7 +1656,7 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
   fill.store(afr, threadIdx.x, NTHR);
   __syncthreads();
   int buf = 0;
-  for (int q0 = 0; q0 < nq; q0 += CQ) {
+  for (int q0 = 0, ci = 0; q0 < nq; q0 += CQ, ++ci) {
     float* sb = stg + buf * (WAVES * CQ * 4 * VP);
     const float* ab = afr + buf * (CQ * 64 * 2 * NB);
     const bool more = q0 + CQ < nq;
@@ -1728,7 +1762,23 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
           re += (double)src[0];
           im += (double)src[1];
         }
-        store_stream(rp + (int64_t)e * d.Tp + jj, cmk(re, im));
+        if constexpr (CPF > 1)
+          rstg[e * Sh::ROWS + (ci % CPF) * 4 * CQ + rho] = cmk(re, im);
+        else
+          store_stream(rp + (int64_t)e * d.Tp + jj, cmk(re, im));
+      }
+    }
+    if constexpr (CPF > 1) {
+      if (ci % CPF == CPF - 1 || !more) {
+        __syncthreads();
+        const int base = 64 * s + 4 * q0 - (ci % CPF) * 4 * CQ;
+        const int end = 64 * s + 4 * q0 + 4 * CQ;
+        const int nrows = (end < m ? end : m) - base;
+        for (int o = threadIdx.x; o < NBB * nrows; o += WAVES * 64) {
+          const int e = o / nrows, row = o - e * nrows;
+          store_stream(rp + (int64_t)e * d.Tp + base + row, rstg[e * Sh::ROWS + row]);
+        }
+        __syncthreads();
       }
     }
     buf ^= 1;

@@ -50,8 +50,9 @@ __device__ __forceinline__ void mm_acc_adag(cplx* acc, const cplx* A, const cplx
 // consecutive rows of every 64-row chunk, one row per iteration (the history block and the
 // adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight, then C 1 KB stores).
 // The SRbar row partial of a row (nb^2 components) goes through one 64-lane reduce-scatter with
-// the components as groups; a wavefront's 16 row partials are staged in LDS and stored as 256-byte
-// runs. Rows past the strip's first 64 (and below m) run without bounds selects.
+// the components as groups; the row partials of four 64-row chunks are staged in LDS and stored
+// by the whole block as 4 KB runs per component. Rows past the strip's first 64 (and below m) run
+// without bounds selects.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ lam,
                                                   const cplx* __restrict__ sig, const cplx* __restrict__ Ibar,
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   constexpr int NBB = NB * NB, C = 2 * NBB;
   constexpr int CH = (C < 8) ? C : 8;
   __shared__ cplx red[3][CH][64];
-  __shared__ cplx stg[4][NBB * 16];
+  constexpr int ROWS_ST = 256;   // row partials of four 64-row chunks, stored by the block at once
+  __shared__ cplx stg[NBB][ROWS_ST];
   const int s = blockIdx.x / d.nk;
   const int k = blockIdx.x - s * d.nk;
   const int lane = threadIdx.x & 63;
@@ -83,9 +85,10 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   const cplx* hk = hist + base;
   cplx* lk = lam + base;
   cplx* rp = sbar_rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
-  cplx* st = stg[wv];
   for (int cb = 64 * s; cb < m; cb += 64) {
     const int rb = cb + 16 * wv;
+    const int cslot = ((cb - 64 * s) >> 6) % (ROWS_ST / 64);
+    cplx* st = &stg[0][64 * cslot + 16 * wv];   // st[e * ROWS_ST + row]
     for (int i = 0; i < 16; ++i) {
       const int j = rb + i;
       if (j >= m) break;
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
           }
           reduce_rows<4>(xg);
           const int e = reduced_row<4>(lane);
-          if (e >= 0) st[e * 16 + i] = cmk(xg[0][0], xg[0][1]);
+          if (e >= 0) st[e * ROWS_ST + i] = cmk(xg[0][0], xg[0][1]);
         } else {
           double rt[1][2 * NBB];
 #pragma unroll
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
           reduce_rows<1>(rt);
           if (reduced_row<1>(lane) >= 0) {
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) st[e * 16 + i] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + i] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
           }
         }
       };
@@ -174,7 +177,16 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
       else
         row(BoolTag<true>{});
     }
-    flush_rows<NBB>(st, rp, d.Tp, rb, m, lane);
+    if (cslot == ROWS_ST / 64 - 1 || cb + 64 >= m) {
+      __syncthreads();
+      const int base = cb - 64 * cslot;
+      const int nrows = (cb + 64 < m ? cb + 64 : m) - base;
+      for (int q = threadIdx.x; q < NBB * nrows; q += 256) {
+        const int e = q / nrows, row = q - e * nrows;
+        store_stream(rp + (int64_t)e * d.Tp + base + row, stg[e][row]);
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int c0 = 0; c0 < C; c0 += CH) {

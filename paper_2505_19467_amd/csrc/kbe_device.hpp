@@ -428,18 +428,6 @@ __device__ __forceinline__ int reduced_row(int lane) {
     return lane == 0 ? 0 : -1;
   }
 }
-// A wavefront's 16 staged rows (st[e * 16 + r], nb^2 components) to rows rb .. rb + 15 of a
-// row-partial slot: 16 consecutive rows per component, 256 contiguous bytes, streaming stores.
-template <int NBB>
-__device__ __forceinline__ void flush_rows(const cplx* st, cplx* rp, int Tp, int rb, int m, int lane) {
-  wave_sync();
-#pragma unroll
-  for (int q = lane; q < NBB * 16; q += 64) {
-    int row = rb + (q & 15);
-    if (row < m) store_stream(rp + (int64_t)(q >> 4) * Tp + row, st[q]);
-  }
-  wave_sync();
-}
 
 
 // ------------------------------------------------------------------ factorised line transforms

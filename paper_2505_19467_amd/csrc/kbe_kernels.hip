@@ -1893,6 +1893,10 @@ struct RowSplit {
   // kernel runs (at one wave per SIMD, the row kernel's serial gather of up to n_t / 64 slots
   // would be latency-bound)
   static constexpr bool FOLD = NB == 4;
+  // nb = 4: a corrector pass runs as EVAL (the collision row, stored) + UPDATE (the update from
+  // the stored row), two waves per SIMD each without spills: the fused kernel holds 256 VGPRs +
+  // 100 AGPRs, one wave per SIMD
+  static constexpr bool CSPLIT = NB == 4;
 };
 
 // Row term of the history sums at nb = 4: the per-strip partials of row t' (slots 0 .. t' / 64)
@@ -1936,6 +1940,8 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
                                              double dt, int commit, double* __restrict__ chg, QuadW Q) {
   constexpr int NBB = NB * NB;
   constexpr int SCN = RowSplit<NB>::SCN, TPT = RowSplit<NB>::TPT;
+  constexpr bool UPD = MODE == KBE_ROW_UPDATE || MODE == KBE_ROW_UPDATE_CHG;   // I(t_m, .) stored
+  constexpr bool CHG = MODE == KBE_ROW_CORRECT || MODE == KBE_ROW_UPDATE_CHG;  // change output
   const int k = blockIdx.y;
   const int tp = blockIdx.x * RowSplit<NB>::TPB + threadIdx.x / TPT;
   const int sc0 = SCN == 1 ? (threadIdx.x & 1) : 0;   // first component of this thread
@@ -1950,7 +1956,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
     for (int ls = 0; ls < SCN; ++ls) {
       const int sc = sc0 + ls;
       cplx In[NBB];
-      if (MODE != KBE_ROW_PREDICT) {
+      if (MODE == KBE_ROW_CORRECT || MODE == KBE_ROW_EVAL) {
         // end-point terms of component sc, accumulated term by term
         cplx E[NBB];
         mat_zero<NB>(E);
@@ -2074,6 +2080,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
           cplx ip = Iprev[rowbuf_idx(d, k, sc * NBB + e, tp)];
+          if constexpr (UPD) In[e] = Icur[rowbuf_idx(d, k, sc * NBB + e, tp)];
           Ib[e] = (MODE == KBE_ROW_PREDICT) ? ip : cscal(cadd(ip, In[e]), 0.5);
           Go[e] = row64[row64_idx(d, m - 1, k, sc * NBB + e, tp)];
         }
@@ -2093,7 +2100,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
 #pragma unroll
         for (int e = 0; e < NBB; ++e) {
           const int c = sc * NBB + e;
-          if (MODE == KBE_ROW_CORRECT && chg) {  // change against the iterate this pass started from
+          if (CHG && chg) {  // change against the iterate this pass started from
             cplx dg = csub(g[e], row64[row64_idx(d, m, k, c, tp)]);
             dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
           }
@@ -2138,7 +2145,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
 #pragma unroll
         for (int sc = 0; sc < 2; ++sc) {
           int c = sc * NBB + e;
-          if (MODE == KBE_ROW_CORRECT && chg) {
+          if (CHG && chg) {
             cplx dg = csub(gg[sc], row64[row64_idx(d, m, k, c, m)]);
             dmax = fmax(dmax, sqrt(dg.x * dg.x + dg.y * dg.y));
           }
@@ -2151,7 +2158,7 @@ __global__ __launch_bounds__(256) void k_row(Dims d, void* __restrict__ hist, cp
         }
       }
   }
-  if (MODE == KBE_ROW_CORRECT && chg) {
+  if (CHG && chg) {
     if constexpr (TPT == 2) dmax = fmax(dmax, __shfl_xor(dmax, 1));   // the pair's two components
     if (sc0 == 0) chg[(int64_t)k * d.Tp + tp] = dmax;
   }
@@ -2480,17 +2487,23 @@ struct Launch {
     if (d.qp > 1) {
       if (mode == KBE_ROW_PREDICT)
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
-      else if (mode == KBE_ROW_CORRECT)
+      else if (mode == KBE_ROW_CORRECT && !RowSplit<NB>::CSPLIT)
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
       else
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL, true>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
     } else {
       if (mode == KBE_ROW_PREDICT)
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_PREDICT, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
-      else if (mode == KBE_ROW_CORRECT)
+      else if (mode == KBE_ROW_CORRECT && !RowSplit<NB>::CSPLIT)
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_CORRECT, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
       else
         hipLaunchKernelGGL((k_row<NB, KBE_ROW_EVAL, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+    }
+    if (mode == KBE_ROW_CORRECT && RowSplit<NB>::CSPLIT) {
+      if (a.chg)
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_UPDATE_CHG, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
+      else
+        hipLaunchKernelGGL((k_row<NB, KBE_ROW_UPDATE, false>), grid, dim3(256), 0, st, KBE_ROW_ARGS);
     }
 #undef KBE_ROW_ARGS
     return hipGetLastError();

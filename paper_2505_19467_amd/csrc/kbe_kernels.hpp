@@ -14,6 +14,11 @@
 #define KBE_ROW_PREDICT 0
 #define KBE_ROW_CORRECT 1
 #define KBE_ROW_EVAL 2
+// the corrector's update alone, from the I(t_m, .) an EVAL launch has just stored (launch_row
+// runs a corrector pass at nb = 4 as EVAL + UPDATE: kernels of two waves per SIMD, where the
+// fused one fits one); UPDATE_CHG also writes the row's largest change (tolerance mode)
+#define KBE_ROW_UPDATE 3
+#define KBE_ROW_UPDATE_CHG 4
 
 namespace kbe {
 

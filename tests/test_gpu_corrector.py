@@ -48,7 +48,8 @@ def _series_err(obs, ref):
 
 # tolerances in wide gaps of the changes the oracle logs for these runs (factors 8-18 away)
 @pytest.mark.parametrize("name,n_corr,tol,nsteps", [("c1", 5, 1.7e-9, 60), ("c1", 6, 2.2e-6, 80),
-                                                    ("c4", 4, 1.5e-8, 30), ("c2", 4, 6e-9, 20)])
+                                                    ("c4", 4, 1.5e-8, 30), ("c2", 4, 6e-9, 20),
+                                                    ("c5", 4, 6e-6, 20)])
 def test_tolerance_corrector_matches_oracle(K, name, n_corr, tol, nsteps):
     _say(f"tolerance corrector {name} n_corr={n_corr} tol={tol:g} steps={nsteps}")
     cfg = inputs.WORKLOADS[name]().replace(n_corr=n_corr, corr_tol=tol)

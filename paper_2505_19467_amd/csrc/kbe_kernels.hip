@@ -1816,8 +1816,9 @@ __global__ __launch_bounds__(MfmaShape<NB>::WAVES * 64) __attribute__((amdgpu_wa
 //     + 1/2 SR_mm G_{m t'} - 1/2 SR_m0 G_{0 t'}                                  (first, [0, t_m])
 //     + [t' > 0] (-1/2 Sigma_{m t'} GR_{t' t'} + 1/2 Sigma_{m0} GR_{0 t'})       (second, [0, t'])
 //   with GR = G^> - G^<, G_{0 t'} = -(G_{t' 0})^dag.
-//  PREDICT/CORRECT, t' < m: G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t').
-//  PREDICT/CORRECT, t' = m: rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag and the
+//  PREDICT/CORRECT/UPDATE, t' < m: G(t_m, t') = V G(t_{m-1}, t') + Phi Ibar(t') (UPDATE: the
+//   corrector's update with I(t_m, t') read back from an EVAL launch's output).
+//  PREDICT/CORRECT/UPDATE, t' = m: rho_m = V rho_{m-1} V^dag - dt Vh Dbar Vh^dag and the
 //   equal-time block G^< = i rho_m, G^> = -i (1 - rho_m).
 // G_{j t'} (both components) for the end corrections of output t' < m: the diagonal from the
 // band copy; stored blocks j > t' from the ring of recent rows (row m: the current iterate) or

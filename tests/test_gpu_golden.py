@@ -5,7 +5,9 @@ the oracle (the 24x24 run takes hours on the CPU, so it is stored, not recompute
 
 * the 24x24, nb = 2 workload propagated for all 1000 steps (Algorithm "prop", K = 1): every
   observable series and sampled entries of the final row G(t_1000, .), against the FP64 path
-  (1e-10 relative, the FP64 target) and the FP32-storage form (1e-6 relative);
+  (1e-10 relative, the FP64 target) and both FP32-storage forms (1e-6 relative);
+* the paper's own model on the chain of n_k = 1024 points (interband U, the dipole kick at
+  step 25) for its first 100 steps, against the FP64 path (1e-10);
 * the 12x12 gradient workload at its full 400 steps: the oracle's tangent-linear derivatives
   of the final upper-band occupation, against the reverse sweep (1e-9 relative).
 
@@ -56,17 +58,20 @@ def _load_table(name):
     return cols, np.loadtxt(path, comments="#")
 
 
-def _c2_golden():
-    cols, obs = _load_table("c2_nt1000_obs.txt")
-    _, fr = _load_table("c2_nt1000_final_row.txt")
+def _golden_run(prefix):
+    cols, obs = _load_table(f"{prefix}_obs.txt")
+    _, fr = _load_table(f"{prefix}_final_row.txt")
     return cols, obs, fr
 
 
 def _compare_c2(K, cfg, tol):
-    cols, gobs, gfr = _c2_golden()
-    n = cfg.nt
+    _compare_run(K, cfg, cfg.nt, "c2_nt1000", tol)
+
+
+def _compare_run(K, cfg, n, prefix, tol):
+    cols, gobs, gfr = _golden_run(prefix)
     assert gobs.shape[0] == n + 1
-    S = K.System(cfg)
+    S = K.System(cfg, nt_max=n)
     S.step(n)
     obs = S.observables()
     final = S.history_row(n).cpu().numpy()       # [t'][k][comp][a][b]
@@ -107,6 +112,13 @@ def test_c2_full_run_fp32_form_matches_oracle(K):
 def test_c2_full_run_fp32_mfma_form_matches_oracle(K):
     _say("golden: 24x24 nb=2 FP32-MFMA form, 1000 steps")
     _compare_c2(K, inputs.c3(), FP32_TOL)
+
+
+def test_paper_model_100_steps_matches_oracle(K):
+    """The paper's workload at its n_k = 1024 through the dipole kick (step 25) and 75 steps
+    beyond it."""
+    _say("golden: chain n_k = 1024, interband U, dipole kick, FP64, 100 steps")
+    _compare_run(K, inputs.paper_chain(), 100, "p1_nt100", FP64_TOL)
 
 
 def test_c4_full_gradient_matches_tangent_linear_oracle(K):

@@ -374,6 +374,11 @@ template <bool B>
 struct BoolTag {
   static constexpr bool value = B;
 };
+// Compile-time count (e.g. the strips of a pair that have work in a loop body's rows).
+template <int N>
+struct IntTag {
+  static constexpr int value = N;
+};
 
 // Keep the compiler from moving LDS accesses of one wavefront across this point (the lanes of
 // a wavefront exchange values through LDS; the hardware executes them in order).

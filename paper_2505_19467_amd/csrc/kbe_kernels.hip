@@ -744,13 +744,14 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
       const int jb = rb + R * i;
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks (as in k_hist_pair32)
-      auto iteration = [&](auto tag) {
+      auto iteration = [&](auto tag, auto nh) {
         constexpr bool MASKED = decltype(tag)::value;
+        constexpr int NH = decltype(nh)::value;   // strips of the pair with work in these rows
         cplx G[R][2][C];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < NH; ++h) {
             int j = jb + r;
             bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx* row = hk[h] + 64 * (int64_t)C * j;
@@ -768,7 +769,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
 #pragma unroll
           for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.0;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < NH; ++h) {
             mm_acc<NB>(acc[h], SR, G[r][h]);
             mm_acc<NB>(acc[h] + NBB, SR, G[r][h] + NBB);
             cplx Sl[NBB], Sg[NBB], a[NBB], u[NBB];
@@ -810,10 +811,13 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
         }
       };
+      // rows of the pair's first 64 lie above every column of its second strip: one strip's work
       if (jb >= 128 * sp + 128 && jb + R <= m)
-        iteration(BoolTag<false>{});
+        iteration(BoolTag<false>{}, IntTag<2>{});
+      else if (jb + R <= 128 * sp + 64)
+        iteration(BoolTag<true>{}, IntTag<1>{});
       else
-        iteration(BoolTag<true>{});
+        iteration(BoolTag<true>{}, IntTag<2>{});
     }
     // every fourth chunk (and the last): the staged rows of all four wavefronts leave as one
     // contiguous run of up to 256 rows per component (4 KB), streaming stores
@@ -908,13 +912,14 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks: every lane's columns lie
       // below the row, so that common case runs without the bounds selects
-      auto iteration = [&](auto tag) {
+      auto iteration = [&](auto tag, auto nh) {
         constexpr bool MASKED = decltype(tag)::value;
+        constexpr int NH = decltype(nh)::value;   // strips of the pair with work in these rows
         cplx32 G[R][2][C];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < NH; ++h) {
             int j = jb + r;
             bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx32* row = hk[h] + 64 * (int64_t)C * j;
@@ -939,7 +944,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
 #pragma unroll
           for (int e = 0; e < 2 * NBB; ++e) rt[r][e] = 0.f;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+          for (int h = 0; h < NH; ++h) {
 #pragma unroll
             for (int sc = 0; sc < 2; ++sc)
 #pragma unroll
@@ -994,10 +999,13 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
           }
         }
       };
+      // rows of the pair's first 64 lie above every column of its second strip: one strip's work
       if (jb >= 128 * sp + 128 && jb + R <= m)
-        iteration(BoolTag<false>{});
+        iteration(BoolTag<false>{}, IntTag<2>{});
+      else if (jb + R <= 128 * sp + 64)
+        iteration(BoolTag<true>{}, IntTag<1>{});
       else
-        iteration(BoolTag<true>{});
+        iteration(BoolTag<true>{}, IntTag<2>{});
     }
     // the group's FP32 column sums into the FP64 accumulators
 #pragma unroll

@@ -745,7 +745,8 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks (as in k_hist_pair32)
       auto iteration = [&](auto tag, auto nh) {
-        constexpr bool MASKED = decltype(tag)::value;
+        constexpr int MM = decltype(tag)::value;   // masks: 0 none, 1 the second strip's only, 2 all
+        constexpr bool MASKED = MM == 2;
         constexpr int NH = decltype(nh)::value;   // strips of the pair with work in these rows
         cplx G[R][2][C];
 #pragma unroll
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
 #pragma unroll
           for (int h = 0; h < NH; ++h) {
             int j = jb + r;
-            bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
+            bool v = (MM == 2 || (MM == 1 && h == 1)) ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx* row = hk[h] + 64 * (int64_t)C * j;
 #pragma unroll
             for (int c = 0; c < C; ++c) G[r][h][c] = v ? load_stream(row + 64 * c) : czero();
@@ -782,7 +783,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
             mat_zero<NB>(u);
             mm_acc_bdag<NB>(a, Sl, G[r][h] + NBB);
             mm_acc_bdag<NB>(u, Sg, G[r][h]);
-            bool rv = MASKED ? tp[h] < j : true;
+            bool rv = (MM == 2 || (MM == 1 && h == 1)) ? tp[h] < j : true;
 #pragma unroll
             for (int e = 0; e < NBB; ++e) {
               rt[r][2 * e] += rv ? a[e].x - u[e].x : 0.0;
@@ -811,13 +812,17 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
         }
       };
-      // rows of the pair's first 64 lie above every column of its second strip: one strip's work
+      // rows of the pair's first 64 lie above every column of its second strip: one strip's
+      // work; in its next 64 rows every column of the first strip lies below the row: masks for
+      // the second strip only
       if (jb >= 128 * sp + 128 && jb + R <= m)
-        iteration(BoolTag<false>{}, IntTag<2>{});
+        iteration(IntTag<0>{}, IntTag<2>{});
       else if (jb + R <= 128 * sp + 64)
-        iteration(BoolTag<true>{}, IntTag<1>{});
+        iteration(IntTag<2>{}, IntTag<1>{});
+      else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128)
+        iteration(IntTag<1>{}, IntTag<2>{});
       else
-        iteration(BoolTag<true>{}, IntTag<2>{});
+        iteration(IntTag<2>{}, IntTag<2>{});
     }
     // every fourth chunk (and the last): the staged rows of all four wavefronts leave as one
     // contiguous run of up to 256 rows per component (4 KB), streaming stores
@@ -913,7 +918,8 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
       // rows past the pair's first 128 (and below m) need no masks: every lane's columns lie
       // below the row, so that common case runs without the bounds selects
       auto iteration = [&](auto tag, auto nh) {
-        constexpr bool MASKED = decltype(tag)::value;
+        constexpr int MM = decltype(tag)::value;   // masks: 0 none, 1 the second strip's only, 2 all
+        constexpr bool MASKED = MM == 2;
         constexpr int NH = decltype(nh)::value;   // strips of the pair with work in these rows
         cplx32 G[R][2][C];
 #pragma unroll
@@ -921,7 +927,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
 #pragma unroll
           for (int h = 0; h < NH; ++h) {
             int j = jb + r;
-            bool v = MASKED ? (colv[h] && tp[h] <= j && j < m) : true;
+            bool v = (MM == 2 || (MM == 1 && h == 1)) ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx32* row = hk[h] + 64 * (int64_t)C * j;
 #pragma unroll
             for (int c2 = 0; c2 < C / 2; ++c2) {
@@ -954,7 +960,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
 #pragma unroll
                   for (int l = 0; l < NB; ++l)
                     cmac32(acc32[h][sc * NBB + a * NB + b], SR[a * NB + l], G[r][h][sc * NBB + l * NB + b]);
-            bool rv = MASKED ? tp[h] < j : true;
+            bool rv = (MM == 2 || (MM == 1 && h == 1)) ? tp[h] < j : true;
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -999,13 +1005,17 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
           }
         }
       };
-      // rows of the pair's first 64 lie above every column of its second strip: one strip's work
+      // rows of the pair's first 64 lie above every column of its second strip: one strip's
+      // work; in its next 64 rows every column of the first strip lies below the row: masks for
+      // the second strip only
       if (jb >= 128 * sp + 128 && jb + R <= m)
-        iteration(BoolTag<false>{}, IntTag<2>{});
+        iteration(IntTag<0>{}, IntTag<2>{});
       else if (jb + R <= 128 * sp + 64)
-        iteration(BoolTag<true>{}, IntTag<1>{});
+        iteration(IntTag<2>{}, IntTag<1>{});
+      else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128)
+        iteration(IntTag<1>{}, IntTag<2>{});
       else
-        iteration(BoolTag<true>{}, IntTag<2>{});
+        iteration(IntTag<2>{}, IntTag<2>{});
     }
     // the group's FP32 column sums into the FP64 accumulators
 #pragma unroll

@@ -740,17 +740,18 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
     const int rb = cb + 16 * wv;
     const int cslot = ((cb - 128 * sp) >> 6) % (ROWS_ST / 64);   // chunk's place in the staging
     cplx* st = &stg[0][64 * cslot + 16 * wv];                      // st[e * ROWS_ST + row]
-    for (int i = 0; i < 16 / R; ++i) {
+    for (int i = 0; i < 16 / R;) {
       const int jb = rb + R * i;
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks (as in k_hist_pair32)
-      auto iteration = [&](auto tag, auto nh) {
+      auto iteration = [&](auto tag, auto nh, auto nr) {
+        constexpr int RR = decltype(nr)::value;   // rows in this iteration
         constexpr int MM = decltype(tag)::value;   // masks: 0 none, 1 the second strip's only, 2 all
         constexpr bool MASKED = MM == 2;
         constexpr int NH = decltype(nh)::value;   // strips of the pair with work in these rows
-        cplx G[R][2][C];
+        cplx G[RR][2][C];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < RR; ++r)
 #pragma unroll
           for (int h = 0; h < NH; ++h) {
             int j = jb + r;
@@ -759,9 +760,9 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
 #pragma unroll
             for (int c = 0; c < C; ++c) G[r][h][c] = v ? load_stream(row + 64 * c) : czero();
           }
-        double rt[R][2 * NBB];
+        double rt[RR][2 * NBB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < RR; ++r) {
           int j = jb + r;
           int jc = MASKED ? (j < m ? j : m - 1) : j;
           cplx SR[NBB];
@@ -791,7 +792,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
             }
           }
         }
-        if constexpr (R == 1 && NBB == 4) {
+        if constexpr (RR == 1 && NBB == 4) {
           // one row, four components: each component's (re, im) is one group of a 4-group
           // reduce-scatter (2 lane reductions instead of 8)
           double xg[4][2];
@@ -802,27 +803,37 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
           reduce_rows<4>(xg);
           int e = reduced_row<4>(lane);
-          if (e >= 0) st[e * ROWS_ST + i] = cmk(xg[0][0], xg[0][1]);
+          if (e >= 0) st[e * ROWS_ST + (jb - rb)] = cmk(xg[0][0], xg[0][1]);
         } else {
-          reduce_rows<R>(rt);
-          int rr = reduced_row<R>(lane);
+          reduce_rows<RR>(rt);
+          int rr = reduced_row<RR>(lane);
           if (rr >= 0) {
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + R * i + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + (jb - rb) + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
           }
         }
       };
       // rows of the pair's first 64 lie above every column of its second strip: one strip's
       // work; in its next 64 rows every column of the first strip lies below the row: masks for
       // the second strip only
-      if (jb >= 128 * sp + 128 && jb + R <= m)
-        iteration(IntTag<0>{}, IntTag<2>{});
-      else if (jb + R <= 128 * sp + 64)
-        iteration(IntTag<2>{}, IntTag<1>{});
-      else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128)
-        iteration(IntTag<1>{}, IntTag<2>{});
-      else
-        iteration(IntTag<2>{}, IntTag<2>{});
+      if (jb >= 128 * sp + 128 && jb + R <= m) {
+        iteration(IntTag<0>{}, IntTag<2>{}, IntTag<R>{});
+        i += 1;
+      } else if (R == 1 && jb + 2 <= 128 * sp + 64 && jb + 2 <= m) {
+        // two rows at a time where only the first strip has work: its loads of both rows in
+        // flight together (one row would keep half the loads of a full iteration in flight)
+        iteration(IntTag<2>{}, IntTag<1>{}, IntTag<2>{});
+        i += 2;
+      } else if (jb + R <= 128 * sp + 64) {
+        iteration(IntTag<2>{}, IntTag<1>{}, IntTag<R>{});
+        i += 1;
+      } else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128) {
+        iteration(IntTag<1>{}, IntTag<2>{}, IntTag<R>{});
+        i += 1;
+      } else {
+        iteration(IntTag<2>{}, IntTag<2>{}, IntTag<R>{});
+        i += 1;
+      }
     }
     // every fourth chunk (and the last): the staged rows of all four wavefronts leave as one
     // contiguous run of up to 256 rows per component (4 KB), streaming stores

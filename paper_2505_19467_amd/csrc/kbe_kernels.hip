@@ -686,10 +686,11 @@ __device__ __forceinline__ void flush_rows_fold(const cplx* st0, const cplx* st1
 //                               t' < j, shared by I^< and I^>    (G_{t' j} = -G_{j t'}^dag)
 // nb <= 2, FP64. Block = (pair of 64-column strips 2 sp, 2 sp + 1; k), the pairs with the
 // most rows launched first. Lane l owns columns 128 sp + l and 128 sp + 64 + l and keeps both
-// column sums in registers; the Sigma of its two columns (row term) sits in LDS. Each
-// wavefront takes 16 consecutive rows of every 64-row chunk, R rows per iteration (R = 1 at
-// nb = 2: 2 x 8 loads of 1 KB-contiguous data in flight; R = 4 at nb = 1), so every stored
-// block is read from HBM once. The row terms of the two strips are added before the 64-lane
+// column sums in registers; the Sigma of its two columns (row term) sits in LDS. Wavefront w
+// takes rows w, w + 4, ..., w + 60 of every 64-row chunk (so a chunk cut short by m leaves no
+// wavefront idle while the others finish), R rows per iteration (R = 1 at nb = 2: 2 x 8 loads
+// of 1 KB-contiguous data in flight; R = 4 at nb = 1), so every stored block is read from HBM
+// once. The row terms of the two strips are added before the 64-lane
 // reduce-scatter (at nb = 2 the four components of the row term share one reduce-scatter as
 // four groups), so one row partial covers 128 columns: the writes that interleave with the
 // read stream are half of what one strip per block would produce, and they leave in long runs
@@ -737,11 +738,11 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
     for (int c = 0; c < C; ++c) acc[h][c] = czero();
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
   for (int cb = 128 * sp; cb < m; cb += 64) {
-    const int rb = cb + 16 * wv;
+    const int rb = cb + wv;   // the wavefront's rows of the chunk: rb, rb + 4, ..., rb + 60
     const int cslot = ((cb - 128 * sp) >> 6) % (ROWS_ST / 64);   // chunk's place in the staging
-    cplx* st = &stg[0][64 * cslot + 16 * wv];                      // st[e * ROWS_ST + row]
-    for (int i = 0; i < 16 / R;) {
-      const int jb = rb + R * i;
+    cplx* st = &stg[0][64 * cslot];                                // st[e * ROWS_ST + (row - cb)]
+    for (int i = 0; i < 16;) {
+      const int jb = rb + 4 * i;
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks (as in k_hist_pair32)
       auto iteration = [&](auto tag, auto nh, auto nr) {
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
         for (int r = 0; r < RR; ++r)
 #pragma unroll
           for (int h = 0; h < NH; ++h) {
-            int j = jb + r;
+            int j = jb + 4 * r;
             bool v = (MM == 2 || (MM == 1 && h == 1)) ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx* row = hk[h] + 64 * (int64_t)C * j;
 #pragma unroll
@@ -763,7 +764,7 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
         double rt[RR][2 * NBB];
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-          int j = jb + r;
+          int j = jb + 4 * r;
           int jc = MASKED ? (j < m ? j : m - 1) : j;
           cplx SR[NBB];
 #pragma unroll
@@ -803,36 +804,37 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
           }
           reduce_rows<4>(xg);
           int e = reduced_row<4>(lane);
-          if (e >= 0) st[e * ROWS_ST + (jb - rb)] = cmk(xg[0][0], xg[0][1]);
+          if (e >= 0) st[e * ROWS_ST + (jb - cb)] = cmk(xg[0][0], xg[0][1]);
         } else {
           reduce_rows<RR>(rt);
           int rr = reduced_row<RR>(lane);
           if (rr >= 0) {
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + (jb - rb) + rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + (jb - cb) + 4 * rr] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
           }
         }
       };
       // rows of the pair's first 64 lie above every column of its second strip: one strip's
       // work; in its next 64 rows every column of the first strip lies below the row: masks for
       // the second strip only
-      if (jb >= 128 * sp + 128 && jb + R <= m) {
+      // (an iteration's rows jb, jb + 4, ..., jb + 4 (RR - 1) lie in one 64-row chunk)
+      if (jb >= 128 * sp + 128 && jb + 4 * (R - 1) < m) {
         iteration(IntTag<0>{}, IntTag<2>{}, IntTag<R>{});
-        i += 1;
-      } else if (R == 1 && jb + 2 <= 128 * sp + 64 && jb + 2 <= m) {
+        i += R;
+      } else if (R == 1 && jb + 4 < 128 * sp + 64 && jb + 4 < m) {
         // two rows at a time where only the first strip has work: its loads of both rows in
         // flight together (one row would keep half the loads of a full iteration in flight)
         iteration(IntTag<2>{}, IntTag<1>{}, IntTag<2>{});
         i += 2;
-      } else if (jb + R <= 128 * sp + 64) {
+      } else if (jb + 4 * (R - 1) < 128 * sp + 64) {
         iteration(IntTag<2>{}, IntTag<1>{}, IntTag<R>{});
-        i += 1;
-      } else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128) {
+        i += R;
+      } else if (jb >= 128 * sp + 64 && jb + 4 * (R - 1) < m && jb + 4 * (R - 1) < 128 * sp + 128) {
         iteration(IntTag<1>{}, IntTag<2>{}, IntTag<R>{});
-        i += 1;
+        i += R;
       } else {
         iteration(IntTag<2>{}, IntTag<2>{}, IntTag<R>{});
-        i += 1;
+        i += R;
       }
     }
     // every fourth chunk (and the last): the staged rows of all four wavefronts leave as one
@@ -874,10 +876,10 @@ __global__ __launch_bounds__(256) void k_hist_pair(Dims d, const cplx* __restric
 // Same structure as k_hist_pair over an FP32-stored history (complex64, half the bytes, a
 // column's component pairs in one 16-byte load): R = 2 rows per iteration at nb = 2 (2 rows x
 // 2 strips x 4 loads in flight per wavefront), R = 4 at nb = 1. Products and the 64-lane row
-// reductions in FP32; the column sums accumulate in FP32 over each wavefront's 16-row groups
-// and are then added into FP64 registers; row partials and column sums leave the kernel in
-// FP64 (the cross-strip reduction, the end points, the update and the density matrix stay
-// FP64).
+// reductions in FP32; the column sums accumulate in FP32 over each wavefront's 16 rows of a
+// 64-row chunk and are then added into FP64 registers; row partials and column sums leave the
+// kernel in FP64 (the cross-strip reduction, the end points, the update and the density matrix
+// stay FP64).
 template <int NB>
 __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __restrict__ hist,
                                                      const cplx* __restrict__ sig, cplx* __restrict__ colsum,
@@ -920,11 +922,11 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
     }
   cplx* rp = const_cast<cplx*>(rowpart_slot(d, rowpart, k, sp));
   for (int cb = 128 * sp; cb < m; cb += 64) {
-    const int rb = cb + 16 * wv;
+    const int rb = cb + wv;   // the wavefront's rows of the chunk: rb, rb + 4, ..., rb + 60
     const int cslot = ((cb - 128 * sp) >> 6) % (ROWS_ST / 64);
-    cplx* st = &stg[0][64 * cslot + 16 * wv];   // st[e * ROWS_ST + row]
+    cplx* st = &stg[0][64 * cslot];   // st[e * ROWS_ST + (row - cb)]
     for (int i = 0; i < 16 / R; ++i) {
-      const int jb = rb + R * i;
+      const int jb = rb + 4 * R * i;
       if (jb >= m) break;
       // rows past the pair's first 128 (and below m) need no masks: every lane's columns lie
       // below the row, so that common case runs without the bounds selects
@@ -937,7 +939,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
         for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int h = 0; h < NH; ++h) {
-            int j = jb + r;
+            int j = jb + 4 * r;
             bool v = (MM == 2 || (MM == 1 && h == 1)) ? (colv[h] && tp[h] <= j && j < m) : true;
             const cplx32* row = hk[h] + 64 * (int64_t)C * j;
 #pragma unroll
@@ -953,7 +955,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
         float rt[R][2 * NBB];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          int j = jb + r;
+          int j = jb + 4 * r;
           int jc = MASKED ? (j < m ? j : m - 1) : j;
           cplx32 SR[NBB];
 #pragma unroll
@@ -1004,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
             int r = g >> 1, p2 = g & 1;
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-              st[(2 * p2 + c) * ROWS_ST + R * i + r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
+              st[(2 * p2 + c) * ROWS_ST + (jb - cb) + 4 * r] = cmk((double)xg[0][2 * c], (double)xg[0][2 * c + 1]);
           }
         } else {
           reduce_rows32<R>(rt);
@@ -1012,18 +1014,19 @@ __global__ __launch_bounds__(256) void k_hist_pair32(Dims d, const cplx32* __res
           if (rr >= 0) {
 #pragma unroll
             for (int e = 0; e < NBB; ++e)
-              st[e * ROWS_ST + R * i + rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
+              st[e * ROWS_ST + (jb - cb) + 4 * rr] = cmk((double)rt[0][2 * e], (double)rt[0][2 * e + 1]);
           }
         }
       };
       // rows of the pair's first 64 lie above every column of its second strip: one strip's
       // work; in its next 64 rows every column of the first strip lies below the row: masks for
       // the second strip only
-      if (jb >= 128 * sp + 128 && jb + R <= m)
+      // (an iteration's rows jb, jb + 4, ..., jb + 4 (R - 1) lie in one 64-row chunk)
+      if (jb >= 128 * sp + 128 && jb + 4 * (R - 1) < m)
         iteration(IntTag<0>{}, IntTag<2>{});
-      else if (jb + R <= 128 * sp + 64)
+      else if (jb + 4 * (R - 1) < 128 * sp + 64)
         iteration(IntTag<2>{}, IntTag<1>{});
-      else if (jb >= 128 * sp + 64 && jb + R <= m && jb + R <= 128 * sp + 128)
+      else if (jb >= 128 * sp + 64 && jb + 4 * (R - 1) < m && jb + 4 * (R - 1) < 128 * sp + 128)
         iteration(IntTag<1>{}, IntTag<2>{});
       else
         iteration(IntTag<2>{}, IntTag<2>{});

@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # nt, timed steps K); summary and commands in profiles/k_hist_pair_c2_sq24_nb2.md. Valid only for
 # the code it was measured on (SHA-1 of the k_hist_pair template and kbe_device.hpp, comments
 # removed); reported as null once that code changes, or for a window that was not measured.
-MEASURED_TRAFFIC = {"bytes_per_launch": {("c2", 1000, 20): 3.70697e10, ("c2", 1000, 1000): 1.26860e10},
-                    "source_sha1": "b4fc3a2886b3876fff2a45644007c2740d99a44a"}
+MEASURED_TRAFFIC = {"bytes_per_launch": {("c2", 1000, 20): 3.70684e10, ("c2", 1000, 1000): 1.26860e10},
+                    "source_sha1": "7def1ccecd3e767c4a0d16a42dea89f26572e628"}
 
 
 def _kernel_source_sha1():

@@ -7,9 +7,10 @@
 //   y = conj(x)    -> xbar += conj(ybar)
 // and for a real parameter p:  dL/dp += Re sum conj(ybar) dy/dp.
 //
-//   k_adj_bulk    adjoint of the history sums: reads the stored block and the adjoint
-//                 history (read-modify-write, same strip-major layout), accumulates the
-//                 self-energy adjoints (column sums in registers, row sums across lanes)
+//   k_adj_bulk    adjoint of the history sums: reads the stored block, accumulates the
+//                 self-energy adjoints (column sums in registers, row sums across lanes); in
+//                 its fused form it also updates the adjoint history (read-modify-write, same
+//                 strip-major layout) for both collision passes of a reverse step
 //   k_adj_row     adjoint of the end-point and equal-time terms of eq. (CI): completes the
 //                 self-energy adjoint row and the adjoint of the current row
 //   k_adj_sigma   adjoint of eq. (2BSE) through the k <-> R transforms (Wirtinger products)
@@ -45,17 +46,23 @@ __device__ __forceinline__ void mm_acc_adag(cplx* acc, const cplx* A, const cplx
 //   lam^s_{jt'} += dt SR_j^dag Ibar^s(t');   t' < j:  lam^< -= dt Irow(j)^dag S^>_{t'}, lam^> += dt Irow(j)^dag S^<_{t'}
 //   SRbar_j     += dt sum_{t'} sum_s Ibar^s(t') G^s_{jt'}^dag           (across lanes, per strip)
 //   Sbar^>_{t'} -= dt sum_{j > t'} Irow(j) G^<_{jt'},  Sbar^<_{t'} += dt sum_{j > t'} Irow(j) G^>_{jt'}   (in lane)
-// Layout of the work as in the forward history sums: block = (strip s, k); lane l owns column
-// 64 s + l (its Sigma, Ibar and Sigma-adjoint column sums in registers); each wavefront takes 16
-// consecutive rows of every 64-row chunk, one row per iteration (the history block and the
-// adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight, then C 1 KB stores).
+// The lam terms are linear in (SR, Ibar, Irow, S): a reverse step's first pass (ADJ_SUMS) only
+// reads the history for its Sigma adjoints, and its second pass (ADJ_FUSED) applies the lam
+// terms of both passes in one read-modify-write of the adjoint history (the first pass's Sigma
+// row and Ibar come in as sig1, Ibar1; their columns sit in LDS): 4 streams per reverse step
+// instead of 6. Layout of the work as in the forward history sums: block = (strip s, k); lane l
+// owns column 64 s + l (its Sigma, Ibar and Sigma-adjoint column sums in registers); each
+// wavefront takes 16 consecutive rows of every 64-row chunk, one row per iteration (the history
+// block and, fused, the adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight,
+// then C 1 KB stores).
 // The SRbar row partial of a row (nb^2 components) goes through one 64-lane reduce-scatter with
 // the components as groups; the row partials of four 64-row chunks are staged in LDS and stored
 // by the whole block as 4 KB runs per component. Rows past the strip's first 64 (and below m) run
 // without bounds selects.
-template <int NB>
+template <int NB, int MODE>
 __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict__ hist, cplx* __restrict__ lam,
                                                   const cplx* __restrict__ sig, const cplx* __restrict__ Ibar,
+                                                  const cplx* __restrict__ sig1, const cplx* __restrict__ Ibar1,
                                                   cplx* __restrict__ sbar_col, cplx* __restrict__ sbar_rowpart,
                                                   int m, double dt) {
   constexpr int NBB = NB * NB, C = 2 * NBB;
@@ -78,6 +85,21 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   }
 #pragma unroll
   for (int c = 0; c < C; ++c) Ib[c] = colv ? Ibar[rowbuf_idx(d, k, c, tp)] : czero();
+  // ADJ_FUSED: the earlier pass's Sigma^<, Sigma^> and Ibar columns of the strip, in LDS
+  __shared__ cplx xS[MODE == ADJ_FUSED ? 2 * NBB * 64 : 1];
+  __shared__ cplx xI[MODE == ADJ_FUSED ? C * 64 : 1];
+  const cplx* sk1 = sig1 + (int64_t)k * 3 * NBB * d.Tp;
+  if constexpr (MODE == ADJ_FUSED) {
+    for (int q = threadIdx.x; q < 2 * NBB * 64; q += 256) {
+      const int l = q & 63, t = 64 * s + l;
+      xS[q] = t < m ? sk1[(q >> 6) * d.Tp + t] : czero();
+    }
+    for (int q = threadIdx.x; q < C * 64; q += 256) {
+      const int l = q & 63, t = 64 * s + l;
+      xI[q] = t < m ? Ibar1[rowbuf_idx(d, k, q >> 6, t)] : czero();
+    }
+    __syncthreads();
+  }
   cplx acc[C];  // [0, NBB): Sbar^<_{t'}, [NBB, C): Sbar^>_{t'}
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = czero();
@@ -100,7 +122,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           G[c] = v ? load_stream(hk + off + 64 * c) : czero();
-          L[c] = v ? load_stream(lk + off + 64 * c) : czero();
+          if constexpr (MODE != ADJ_SUMS) L[c] = v ? load_stream(lk + off + 64 * c) : czero();
         }
         cplx SR[NBB], Irow[NBB];
 #pragma unroll
@@ -109,23 +131,51 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
           Irow[e] = cadd(Ibar[rowbuf_idx(d, k, e, j)], Ibar[rowbuf_idx(d, k, NBB + e, j)]);
         }
         const bool rv = MASKED ? tp < j : true;
-        // adjoint history
-        cplx dl[C];
+        if constexpr (MODE == ADJ_FUSED) {
+          // adjoint history, accumulated into the loaded block with dt-scaled row factors:
+          //   lam^s += (dt SR)^dag Ibar^s;  t' < j:  lam^< += (-dt Irow)^dag S^>,  lam^> += (dt Irow)^dag S^<
+          // for this pass (column factors in registers), then for the earlier pass (from LDS,
+          // read here in every row: the barrier keeps the compiler from holding them in
+          // registers across the loop, which would leave room for one wavefront per SIMD only)
+          auto update = [&](const cplx* SRr, const cplx* Irr, auto col_ib, auto col_sg, auto col_sl) {
+            cplx A[NBB], X[NBB];
 #pragma unroll
-        for (int c = 0; c < C; ++c) dl[c] = czero();
-        mm_acc_adag<NB>(dl, SR, Ib);
-        mm_acc_adag<NB>(dl + NBB, SR, Ib + NBB);
-        if (rv) {
-          cplx u[NBB], w[NBB];
-          mat_zero<NB>(u);
-          mat_zero<NB>(w);
-          mm_acc_adag<NB>(u, Irow, Sg);
-          mm_acc_adag<NB>(w, Irow, Sl);
+            for (int e = 0; e < NBB; ++e) A[e] = cscal(SRr[e], dt);
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) X[e] = col_ib(sc * NBB + e);
+              mm_acc_adag<NB>(L + sc * NBB, A, X);
+            }
+            if (rv) {
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) A[e] = cscal(Irr[e], -dt);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) X[e] = col_sg(e);
+              mm_acc_adag<NB>(L, A, X);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) A[e] = cscal(Irr[e], dt);
+#pragma unroll
+              for (int e = 0; e < NBB; ++e) X[e] = col_sl(e);
+              mm_acc_adag<NB>(L + NBB, A, X);
+            }
+          };
+          update(SR, Irow, [&](int c) { return Ib[c]; }, [&](int e) { return Sg[e]; }, [&](int e) { return Sl[e]; });
+          asm volatile("" ::: "memory");
+          cplx SR1[NBB], Irow1[NBB];
 #pragma unroll
           for (int e = 0; e < NBB; ++e) {
-            dl[e] = csub(dl[e], u[e]);
-            dl[NBB + e] = cadd(dl[NBB + e], w[e]);
+            SR1[e] = sk1[(2 * NBB + e) * d.Tp + j];
+            Irow1[e] = cadd(Ibar1[rowbuf_idx(d, k, e, j)], Ibar1[rowbuf_idx(d, k, NBB + e, j)]);
           }
+          update(SR1, Irow1, [&](int c) { return xI[c * 64 + lane]; }, [&](int e) { return xS[(NBB + e) * 64 + lane]; },
+                 [&](int e) { return xS[e * 64 + lane]; });
+          if (v) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) store_stream(lk + off + 64 * c, L[c]);
+          }
+        }
+        if (rv) {
           // Sigma adjoints of the row term (in lane)
           cplx x[NBB], y[NBB];
           mat_zero<NB>(x);
@@ -137,10 +187,6 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
             acc[e] = cadd(acc[e], cscal(x[e], dt));
             acc[NBB + e] = csub(acc[NBB + e], cscal(y[e], dt));
           }
-        }
-        if (v) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) store_stream(lk + off + 64 * c, cadd(L[c], cscal(dl[c], dt)));
         }
         // SRbar_j partial: sum_s Ibar^s G^s^dag (zero where no block is stored)
         cplx q[NBB];
@@ -1019,12 +1065,16 @@ __global__ void k_adj_rho(Dims d, const void* __restrict__ hist, int m, cplx* __
 // ------------------------------------------------------------------ launchers
 template <int NB>
 struct AdjLaunch {
-  static hipError_t bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m,
-                         hipStream_t st) {
+  static hipError_t bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m, int mode,
+                         const cplx* sig1, const cplx* Ibar1, hipStream_t st) {
     if (m < 1) return hipSuccess;
     int ns = (m + 63) / 64;
-    hipLaunchKernelGGL(k_adj_bulk<NB>, dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist, b.lam,
-                       (const cplx*)a.sig, Ibar, b.sbar_col, b.sbar_rowpart, m, a.dt);
+    if (mode == ADJ_SUMS)
+      hipLaunchKernelGGL((k_adj_bulk<NB, ADJ_SUMS>), dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                         b.lam, (const cplx*)a.sig, Ibar, (const cplx*)a.sig, Ibar, b.sbar_col, b.sbar_rowpart, m, a.dt);
+    else
+      hipLaunchKernelGGL((k_adj_bulk<NB, ADJ_FUSED>), dim3(ns * d.nk), dim3(256), 0, st, d, (const cplx*)a.hist,
+                         b.lam, (const cplx*)a.sig, Ibar, sig1, Ibar1, b.sbar_col, b.sbar_rowpart, m, a.dt);
     return hipGetLastError();
   }
   static hipError_t row(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, const cplx* Dbar,
@@ -1084,9 +1134,10 @@ struct AdjLaunch {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_adj_bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m,
-                           hipStream_t st) {
-  KBE_ADJ_DISPATCH(d.nb, bulk(d, a, b, Ibar, m, st));
+hipError_t launch_adj_bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m, int mode,
+                           const cplx* sig1, const cplx* Ibar1, hipStream_t st) {
+  if (mode != ADJ_SUMS && (mode != ADJ_FUSED || !sig1 || !Ibar1)) return hipErrorInvalidValue;
+  KBE_ADJ_DISPATCH(d.nb, bulk(d, a, b, Ibar, m, mode, sig1, Ibar1, st));
 }
 hipError_t launch_adj_row(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, const cplx* Dbar,
                           int m, hipStream_t st) {

@@ -38,8 +38,16 @@ struct AdjArgs {
   double* theta_bar;  // [3] dL/d(amp, omega, U)
 };
 
-hipError_t launch_adj_bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m,
-                           hipStream_t st);
+// Modes of the adjoint history sums. A reverse step reverses two collision passes whose history
+// sums read the same stored blocks; the adjoint-history update of each is linear in its own
+// (Sigma row, Ibar), so the first of them (in reverse order) leaves it to the second:
+//   ADJ_SUMS   Sigma adjoints only (reads the history, not the adjoint history)
+//   ADJ_FUSED  Sigma adjoints of this pass; adjoint-history update of this pass plus that of the
+//              earlier ADJ_SUMS pass, whose Sigma row and Ibar are sig1, Ibar1
+// Any other mode, or ADJ_FUSED without sig1 and Ibar1, returns hipErrorInvalidValue.
+enum { ADJ_SUMS = 1, ADJ_FUSED = 2 };
+hipError_t launch_adj_bulk(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar, int m, int mode,
+                           const cplx* sig1, const cplx* Ibar1, hipStream_t st);
 hipError_t launch_adj_row(const Dims& d, const LaunchArgs& a, const AdjArgs& b, const cplx* Ibar,
                           const cplx* Dbar, int m, hipStream_t st);
 hipError_t launch_adj_sigma(const Dims& d, const LaunchArgs& a, const AdjArgs& b, int m, int* nblocks,

@@ -175,7 +175,7 @@ void pulse_dA(const kbe_pulse& p, double t, double* damp, double* domega) {
 enum {
   A_LAM = 0, A_IBAR0, A_IBAR1, A_IBARC, A_RBAR, A_SBAR, A_SBARCOL, A_IREPREV, A_IREC, A_SBARRP,
   A_DBAR0, A_DBAR1, A_DBARC, A_RHOBAR0, A_RHOBAR1, A_RHOBARP, A_RHOP, A_DC, A_DSCR, A_RHO0,
-  A_PROPSP, A_PROPSC, A_PBAR, A_HFP, A_HFC, A_KPART, A_UBAR, A_THETA, A_COUNT
+  A_PROPSP, A_PROPSC, A_PBAR, A_HFP, A_HFC, A_KPART, A_UBAR, A_THETA, A_SIGEV, A_COUNT
 };
 
 size_t adj_layout(const Layout& L, size_t* off) {
@@ -193,6 +193,7 @@ size_t adj_layout(const Layout& L, size_t* off) {
   sz[A_KPART] = nk * (d.nb + 1) * sizeof(double);
   sz[A_UBAR] = ((size_t)((d.N * d.nbb + 7) / 8) * 8) * sizeof(double);
   sz[A_THETA] = 3 * sizeof(double);
+  sz[A_SIGEV] = nk * 3 * d.nbb * d.Tp * cz;   // Sigma row of the evaluation pass, kept for the fused pass
   size_t o = 0;
   for (int i = 0; i < A_COUNT; ++i) {
     if (off) off[i] = o;
@@ -456,10 +457,11 @@ struct kbe_ctx {
     if (!rc) rc = check(kbe::launch_adj_seed(d, a, b, b.rho0, obs_id, damp, dom, st), "adjoint seed launch");
     return rc;
   }
-  int adj_sigma_pass(const LaunchArgs& a, const kbe::AdjArgs& b, const cplx* Ibar, const cplx* Dbar, int m) {
+  int adj_sigma_pass(const LaunchArgs& a, const kbe::AdjArgs& b, const cplx* Ibar, const cplx* Dbar, int m,
+                     int mode, const cplx* sig1 = nullptr, const cplx* Ibar1 = nullptr) {
     const Dims& d = L.d;
     int nblk = 0;
-    int rc = check(kbe::launch_adj_bulk(d, a, b, Ibar, m, st), "adjoint history-sum launch");
+    int rc = check(kbe::launch_adj_bulk(d, a, b, Ibar, m, mode, sig1, Ibar1, st), "adjoint history-sum launch");
     if (!rc) rc = check(kbe::launch_adj_row(d, a, b, Ibar, Dbar, m, st), "adjoint end-point launch");
     if (!rc) rc = check(kbe::launch_adj_sigma(d, a, b, m, &nblk, st), "adjoint self-energy launch");
     if (!rc) rc = check(kbe::launch_adj_reduce_u(b, nblk, st), "adjoint reduction launch");
@@ -479,11 +481,16 @@ struct kbe_ctx {
     // and D_{m-1} comes out of the recomputed evaluation pass of t_{m-1} below.
     cplx* rho0 = b.rho0;
     int rc = check(kbe::launch_adj_rho(d, hist, m - 1, rho0, st), "density read-back launch");
-    // committed rows m-1, m, column 0 and diagonal; Sigma of the committed row m
+    // committed rows m-1, m, column 0 and diagonal
     if (!rc) rc = check(kbe::launch_aux(d, a, m, st), "aux launch");
-    if (!rc) rc = check(kbe::launch_sigma(d, a, m, st), "self-energy launch");
-    // evaluation pass of t_m
-    if (!rc) rc = adj_sigma_pass(a, b, b.Ibar, b.Dbar, m);
+    // Sigma of the committed row m, in a buffer of its own: the corrector pass below applies this
+    // pass's adjoint-history update too (both updates are linear in their Sigma row and Ibar and
+    // touch the same stored blocks), so the history and the adjoint history stream once for both
+    LaunchArgs ev = a;
+    ev.sig = abuf<cplx>(A_SIGEV);
+    if (!rc) rc = check(kbe::launch_sigma(d, ev, m, st), "self-energy launch");
+    // evaluation pass of t_m: Sigma adjoints only
+    if (!rc) rc = adj_sigma_pass(ev, b, b.Ibar, b.Dbar, m, kbe::ADJ_SUMS);
     // recompute I(t_{m-1}, .)
     LaunchArgs e = a;
     e.I_cur = b.Ire_prev;
@@ -525,7 +532,7 @@ struct kbe_ctx {
       rc = check(kbe::launch_adj_hf(d, a, b, rho0, b.rhoP, 0.5, b.rhobar_prev, b.rhobar_P, damp, dom, st),
                  "adjoint mean-field launch");
     // corrector collision pass (Sigma of the predictor row, still in place)
-    if (!rc) rc = adj_sigma_pass(a, b, b.Ibar_c, b.Dbar_c, m);
+    if (!rc) rc = adj_sigma_pass(a, b, b.Ibar_c, b.Dbar_c, m, kbe::ADJ_FUSED, ev.sig, b.Ibar);
     // predictor update, its propagators and mean field
     if (!rc) rc = check(kbe::launch_adj_update(d, p, b, m, 0, nullptr, b.Rbar, rho0, st), "adjoint update launch");
     if (!rc) rc = check(kbe::launch_adj_props(d, a, b, b.hf_p, st), "adjoint propagator launch");

@@ -665,8 +665,8 @@ __device__ __forceinline__ void reduce_rows32(float (&rt)[R][Q]) {
     rt[0][q] = row16_sum32(y);
   }
 }
-// The nb = 4 kernels' two component halves stage the row partials of the same 16 rows; after a
-// block barrier each of the two wavefronts stores half of the nb^2 components of their sum
+// The FP64 nb = 4 kernel's two component halves stage the row partials of the same 16 rows;
+// after a block barrier each of the two wavefronts stores half of the nb^2 components of their sum
 // (st0 + st1, a fixed order) to rows rb .. rb + 15 of the strip's slot, 256-byte runs.
 template <int NBB>
 __device__ __forceinline__ void flush_rows_fold(const cplx* st0, const cplx* st1, cplx* rp, int Tp, int rb, int m,
@@ -676,6 +676,16 @@ __device__ __forceinline__ void flush_rows_fold(const cplx* st0, const cplx* st1
     int e = h * (NBB / 2) + (q >> 4), r = q & 15;
     int row = rb + r;
     if (row < m) store_stream(rp + (int64_t)e * Tp + row, cadd(st0[e * 16 + r], st1[e * 16 + r]));
+  }
+}
+// The FP32 nb = 4 kernel's two component halves stage the row partials of a 32-row chunk (rows
+// cb .. cb + 31, both wave pairs); after a block barrier the whole block stores their sum
+// (st0 + st1, a fixed order) to the strip's slot, one 512-byte run per component.
+template <int NBB>
+__device__ __forceinline__ void flush_chunk_fold(const cplx* st0, const cplx* st1, cplx* rp, int Tp, int cb, int m) {
+  for (int q = threadIdx.x; q < NBB * 32; q += 256) {
+    const int e = q >> 5, r = q & 31, row = cb + r;
+    if (row < m) store_stream(rp + (int64_t)e * Tp + row, cadd(st0[e * 32 + r], st1[e * 32 + r]));
   }
 }
 
@@ -1384,7 +1394,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 // FP32 form of k_hist_bulk_split: each half's 16 components are 8 column-interleaved pairs,
 // one 16-byte load each; FP32 products and row reductions, column sums in FP32 over each
-// wavefront's 16-row groups, then FP64.
+// wavefront's 16 rows of a 32-row chunk, then FP64. The row pair (0, 1) takes the even rows of
+// every 32-row chunk and (2, 3) the odd ones, so a chunk cut short by m keeps both pairs busy, and
+// the whole block stores a chunk's row partials as 512-byte runs (this kernel is bound by the
+// vector ALU; the FP64 kernel's stream ran 1.7 % slower with interleaved rows and keeps 16
+// consecutive rows per pair).
 template <int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hist_bulk32_split(
     Dims d, const cplx32* __restrict__ hist, const cplx* __restrict__ sig, cplx* __restrict__ colsum,
@@ -1393,8 +1407,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(NB == 4, "the four block rows share one reduce-scatter");
   static_assert(NBB % 2 == 0, "component pairs must not straddle the halves");
   __shared__ cplx32 sS[2][NBB][64];
-  __shared__ cplx stg[2][2][2][NBB * 16];  // [buffer][row pair][half][e * 16 + row]; column-sum
-                                           // combine after the row loop
+  __shared__ cplx stg[2][2][NBB * 32];  // [buffer][half][e * 32 + row - cb]; column-sum combine
+                                        // after the row loop
   int s = blockIdx.x / d.nk;
   int k = blockIdx.x - s * d.nk;
   int lane = threadIdx.x & 63;
@@ -1421,15 +1435,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const float sgn = h ? 1.f : -1.f;
   int buf = 0;
   for (int cb = 64 * s; cb < m; cb += 32) {  // the same chunks in every wavefront
-    const int rb = cb + 16 * rg;
-    cplx* st = stg[buf][rg][h];
+    const int rb = cb + rg;   // the wave pair's rows of the chunk: rb, rb + 2, ..., rb + 30
+    cplx* st = stg[buf][h];
     // groups of 16 rows past the strip's first 64 rows and below m need no masks (this
     // kernel is bound by the vector ALU; the FP64 kernel keeps one path, a second one would
     // not fit its registers)
     auto rows16 = [&](auto tag) {
       constexpr bool MASKED = decltype(tag)::value;
       for (int i = 0; i < 16; ++i) {
-        const int j = rb + i;
+        const int j = rb + 2 * i;
         if (MASKED && j >= m) break;
         bool v = MASKED ? (colv && tp <= j) : true;
         const cplx32* row = hk + 64 * (int64_t)C * j;
@@ -1467,11 +1481,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         int ra = reduced_row<NB>(lane);
         if (ra >= 0) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 16 + i] = cmk((double)x[0][2 * b], (double)x[0][2 * b + 1]);
+          for (int b = 0; b < NB; ++b) st[(ra * NB + b) * 32 + (j - cb)] = cmk((double)x[0][2 * b], (double)x[0][2 * b + 1]);
         }
       }
     };
-    if (rb >= 64 * s + 64 && rb + 16 <= m)
+    if (rb >= 64 * s + 64 && rb + 30 < m)
       rows16(BoolTag<false>{});
     else
       rows16(BoolTag<true>{});
@@ -1482,11 +1496,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       acc32[e] = make_float2(0.f, 0.f);
     }
     __syncthreads();  // both halves of the chunk staged; the other buffer is free again
-    flush_rows_fold<NBB>(stg[buf][rg][0], stg[buf][rg][1], rp, d.Tp, rb, m, lane, h);
+    flush_chunk_fold<NBB>(stg[buf][0], stg[buf][1], rp, d.Tp, cb, m);
     buf ^= 1;
   }
   __syncthreads();  // every wavefront is done with stg
-  cplx (*red)[NBB][64] = reinterpret_cast<cplx (*)[NBB][64]>(&stg[0][0][0][0]);
+  cplx (*red)[NBB][64] = reinterpret_cast<cplx (*)[NBB][64]>(&stg[0][0][0]);
   if (rg == 1) {
 #pragma unroll
     for (int e = 0; e < NBB; ++e) red[h][e][lane] = acc[e];

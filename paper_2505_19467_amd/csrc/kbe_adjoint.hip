@@ -108,11 +108,15 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
   cplx* lk = lam + base;
   cplx* rp = sbar_rowpart + ((int64_t)k * d.Smax + s) * NBB * d.Tp;
   for (int cb = 64 * s; cb < m; cb += 64) {
-    const int rb = cb + 16 * wv;
+    // the read-only pass: wavefront w takes rows w, w + 4, ..., w + 60 (a chunk cut short by m
+    // keeps all four busy); the fused pass: 16 consecutive rows (its read-modify-write stream
+    // runs better in 128 KB runs per wavefront)
+    constexpr int RS = MODE == ADJ_SUMS ? 4 : 1;
+    const int rb = cb + (MODE == ADJ_SUMS ? wv : 16 * wv);
     const int cslot = ((cb - 64 * s) >> 6) % (ROWS_ST / 64);
-    cplx* st = &stg[0][64 * cslot + 16 * wv];   // st[e * ROWS_ST + row]
+    cplx* st = &stg[0][64 * cslot];   // st[e * ROWS_ST + (row - cb)]
     for (int i = 0; i < 16; ++i) {
-      const int j = rb + i;
+      const int j = rb + RS * i;
       if (j >= m) break;
       auto row = [&](auto tag) {
         constexpr bool MASKED = decltype(tag)::value;
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
           }
           reduce_rows<4>(xg);
           const int e = reduced_row<4>(lane);
-          if (e >= 0) st[e * ROWS_ST + i] = cmk(xg[0][0], xg[0][1]);
+          if (e >= 0) st[e * ROWS_ST + (j - cb)] = cmk(xg[0][0], xg[0][1]);
         } else {
           double rt[1][2 * NBB];
 #pragma unroll
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(256) void k_adj_bulk(Dims d, const cplx* __restrict
           reduce_rows<1>(rt);
           if (reduced_row<1>(lane) >= 0) {
 #pragma unroll
-            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + i] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
+            for (int e = 0; e < NBB; ++e) st[e * ROWS_ST + (j - cb)] = cmk(rt[0][2 * e], rt[0][2 * e + 1]);
           }
         }
       };

@@ -51,10 +51,11 @@ __device__ __forceinline__ void mm_acc_adag(cplx* acc, const cplx* A, const cplx
 // terms of both passes in one read-modify-write of the adjoint history (the first pass's Sigma
 // row and Ibar come in as sig1, Ibar1; their columns sit in LDS): 4 streams per reverse step
 // instead of 6. Layout of the work as in the forward history sums: block = (strip s, k); lane l
-// owns column 64 s + l (its Sigma, Ibar and Sigma-adjoint column sums in registers); each
-// wavefront takes 16 consecutive rows of every 64-row chunk, one row per iteration (the history
-// block and, fused, the adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight,
-// then C 1 KB stores).
+// owns column 64 s + l (its Sigma, Ibar and Sigma-adjoint column sums in registers); in the
+// fused pass each wavefront takes 16 consecutive rows of every 64-row chunk, in the read-only
+// pass rows w, w + 4, ..., w + 60 (wavefront w), one row per iteration (the history block and,
+// fused, the adjoint-history block of the row: 2 C 1 KB-contiguous loads in flight, then C 1 KB
+// stores).
 // The SRbar row partial of a row (nb^2 components) goes through one 64-lane reduce-scatter with
 // the components as groups; the row partials of four 64-row chunks are staged in LDS and stored
 // by the whole block as 4 KB runs per component. Rows past the strip's first 64 (and below m) run
